@@ -1,0 +1,398 @@
+"""FP64 CPU oracle for the known-pose Fourier-slice refinement of Toader,
+Brubaker & Lederman (arXiv:2311.16100).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py, never by the product package.  It shares no
+code with the HIP library.  The operators live in plain C (oracle.c, built
+with gcc -O2 into liboracle.so); the algorithms on top of them (HVP,
+Hutchinson's estimator, the preconditioned SGD of Algorithm 1, the
+Armijo line search, conjugate gradients for the ground truth, the MLP of the
+learned preconditioner) are written here in numpy, step by step in the
+paper's order.
+
+Every function is double precision.  Inputs the GPU receives in float32
+(rotations, defocus, volumes, images) are accepted in float32 / complex64 and
+promoted.
+
+Parity status: every function here is pinned by a CPU test in tests/ against
+a closed form, an invariant or brute force; see the test module named in each
+docstring.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("r_max", ctypes.c_double), ("interp", ctypes.c_int32)]
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("kv", ctypes.c_double), ("cs_mm", ctypes.c_double), ("amp_contrast", ctypes.c_double),
+                ("pixel_A", ctypes.c_double), ("ctf_on", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        d, i64, u64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+        vp = ctypes.c_void_p
+        L.or_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
+        L.or_rademacher.argtypes = [u64, u64, i64, vp]
+        L.or_wavelength_A.argtypes = [d]
+        L.or_wavelength_A.restype = d
+        L.or_ctf.argtypes = [P(_Optics), i32, d, d]
+        L.or_ctf.restype = d
+        L.or_project.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp]
+        L.or_backproject.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, i32, d, vp]
+        L.or_sq_backproject.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, d, vp]
+        L.or_features.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# Problem description
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Grid:
+    """M: grid side (even); r_max: disk radius of the pixels used (default
+    M/2 - 1); interp: 0 nearest neighbour, 1 trilinear (Definition
+    "Projection operator", Sec. 2.1)."""
+    M: int
+    r_max: float | None = None
+    interp: int = 1
+
+    @property
+    def rmax(self) -> float:
+        return float(self.M // 2 - 1) if self.r_max is None else float(self.r_max)
+
+    def c(self):
+        return _Grid(self.M, self.rmax, self.interp)
+
+
+@dataclass(frozen=True)
+class Optics:
+    kv: float = 300.0
+    cs_mm: float = 2.7
+    amp_contrast: float = 0.1
+    pixel_A: float = 1.0
+    ctf_on: bool = True
+
+    def c(self):
+        return _Optics(self.kv, self.cs_mm, self.amp_contrast, self.pixel_A, int(self.ctf_on))
+
+
+NO_CTF = Optics(ctf_on=False)
+
+
+@dataclass
+class Poses:
+    rot: np.ndarray      # float32 [n,3,3]
+    defocus: np.ndarray  # float32 [n], Angstrom
+
+    def __post_init__(self):
+        self.rot = np.ascontiguousarray(self.rot, dtype=np.float32).reshape(-1, 3, 3)
+        self.defocus = np.ascontiguousarray(self.defocus, dtype=np.float32).reshape(-1)
+        assert self.rot.shape[0] == self.defocus.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.rot.shape[0]
+
+    def subset(self, idx) -> "Poses":
+        return Poses(self.rot[idx], self.defocus[idx])
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+# ---------------------------------------------------------------------------
+# Primitives (C)
+# ---------------------------------------------------------------------------
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block (Salmon et al., SC'11). Pinned by the published
+    known-answer vectors (tests/test_oracle_rng_ctf.py)."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def rademacher(seed: int, probe: int, nvox: int) -> np.ndarray:
+    """Rademacher(0.5) probe z in {+1,-1}^nvox of eq. (hutch), Sec. 3.2."""
+    z = np.empty(nvox, dtype=np.float64)
+    lib().or_rademacher(int(seed), int(probe), int(nvox), _ptr(z))
+    return z
+
+
+def wavelength_A(kv: float) -> float:
+    """Relativistic electron wavelength in Angstrom."""
+    return lib().or_wavelength_A(float(kv))
+
+
+def ctf(optics: Optics, M: int, defocus_A: float, k2: float) -> float:
+    """Weak-phase CTF at squared integer radius k2 (the paper's C_i, Sec. 2.1,
+    with the textbook formula; see oracle.c)."""
+    o = optics.c()
+    return lib().or_ctf(ctypes.byref(o), int(M), float(defocus_A), float(k2))
+
+
+def project(grid: Grid, optics: Optics, poses: Poses, vol) -> np.ndarray:
+    """C_i P_i v for every image, eq. (fwd model) without noise.  [n][M][M]."""
+    M = grid.M
+    v = _c128(vol).reshape(M, M, M)
+    out = np.zeros((poses.n, M, M), dtype=np.complex128)
+    g, o = grid.c(), optics.c()
+    lib().or_project(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
+                     _ptr(v), _ptr(out))
+    return out
+
+
+def backproject(grid: Grid, optics: Optics, poses: Poses, img, ctf_power: int = 1,
+                scale: float = 1.0, accum=None) -> np.ndarray:
+    """accum + scale * sum_i P_i^T C_i^p img_i (the adjoint, eq. (em v))."""
+    M = grid.M
+    im = _c128(img).reshape(poses.n, M, M)
+    out = np.zeros((M, M, M), dtype=np.complex128) if accum is None else _c128(accum).copy()
+    g, o = grid.c(), optics.c()
+    lib().or_backproject(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
+                         _ptr(im), int(ctf_power), float(scale), _ptr(out))
+    return out
+
+
+def sq_backproject(grid: Grid, optics: Optics, poses: Poses, scale: float = 1.0) -> np.ndarray:
+    """scale * diag(sum_i P_i^T C_i^2 P_i), the squared-weight backprojection."""
+    M = grid.M
+    out = np.zeros((M, M, M), dtype=np.float64)
+    g, o = grid.c(), optics.c()
+    lib().or_sq_backproject(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
+                            float(scale), _ptr(out))
+    return out
+
+
+def features(grid: Grid, optics: Optics, poses: Poses):
+    """(sum_ij C_ij^2 w_ijk, |Omega_k|) per voxel, both float64 [M][M][M]."""
+    M = grid.M
+    f2 = np.zeros((M, M, M), dtype=np.float64)
+    f3 = np.zeros((M, M, M), dtype=np.float64)
+    g, o = grid.c(), optics.c()
+    lib().or_features(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
+                      _ptr(f2), _ptr(f3))
+    return f2, f3
+
+
+# ---------------------------------------------------------------------------
+# Objective, gradient and Hessian (Sec. 3.1, eqs. (optim cp), (hessian))
+# with the CTF re-inserted as in eq. (em v) and the minibatch scaled to an
+# unbiased estimate of the full sum: f_I(v) = (N/B) sum_{i in I} 1/2 ||x_i -
+# C_i P_i v||^2 + lambda/2 ||v||^2.
+# ---------------------------------------------------------------------------
+def loss(grid, optics, poses, v, x, scale: float, lam: float) -> float:
+    r = project(grid, optics, poses, v) - _c128(x)
+    v = _c128(v)
+    return float(scale * 0.5 * np.vdot(r, r).real + 0.5 * lam * np.vdot(v, v).real)
+
+
+def gradient(grid, optics, poses, v, x, scale: float, lam: float) -> np.ndarray:
+    """scale * sum_i P_i^T C_i (C_i P_i v - x_i) + lambda v.  The complex
+    gradient convention is d/dRe + i d/dIm of the real loss."""
+    r = project(grid, optics, poses, v) - _c128(x)
+    return backproject(grid, optics, poses, r, ctf_power=1, scale=scale) + lam * _c128(v).reshape(grid.M, grid.M, grid.M)
+
+
+def hvp(grid, optics, poses, z, scale: float, lam: float) -> np.ndarray:
+    """H_I z = scale * sum_i P_i^T C_i^2 P_i z + lambda z (complex z allowed;
+    H is real, so real and imaginary parts are independent products)."""
+    M = grid.M
+    z = _c128(z).reshape(M, M, M)
+    return backproject(grid, optics, poses, project(grid, optics, poses, z), ctf_power=1, scale=scale) + lam * z
+
+
+def hutchinson_diag(grid, optics, poses, n_probe: int, seed: int, scale: float, lam: float,
+                    probe0: int = 0) -> np.ndarray:
+    """Hutchinson's estimate mean_p z_p (.) H z_p with Rademacher z_p, eq. (hutch),
+    probes probe0 .. probe0+n_probe-1."""
+    M = grid.M
+    acc = np.zeros(M ** 3)
+    for p in range(n_probe):
+        z = rademacher(seed, probe0 + p, M ** 3)
+        hz = hvp(grid, optics, poses, z, scale, lam).reshape(-1)
+        acc += z * hz.real
+    return (acc / n_probe).reshape(M, M, M)
+
+
+def exact_diag(grid, optics, poses, scale: float, lam: float) -> np.ndarray:
+    """diag(H_I) = scale * sum_ij C_ij^2 w_ijk^2 + lambda, from eq. (hessian)
+    with the trilinear weights of eq. (def tri interp)."""
+    return sq_backproject(grid, optics, poses, scale) + lam
+
+
+def shell_counts(M: int, R: int):
+    """(P_x(R), P_v(R)): pixels of the M x M grid and voxels of the M^3 grid
+    whose radius rounds to R (the Fourier shells of eq. (thresh value))."""
+    ax = np.arange(M) - M // 2
+    r2 = np.sqrt(ax[:, None] ** 2 + ax[None, :] ** 2)
+    r3 = np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2)
+    return int(np.sum(np.rint(r2) == R)), int(np.sum(np.rint(r3) == R))
+
+
+def alpha_threshold(grid: Grid, optics: Optics, defocus_all, lam: float, R: int | None = None) -> float:
+    """alpha = (P_x(R)/P_v(R)) sum_{i=1}^N |C_i(R)|^2 + lambda, eq. (thresh value),
+    at the maximum radius R = r_max, summed over all N images of the data set."""
+    R = int(round(grid.rmax)) if R is None else int(R)
+    px, pv = shell_counts(grid.M, R)
+    s = sum(ctf(optics, grid.M, float(df), float(R * R)) ** 2 for df in np.asarray(defocus_all, dtype=np.float32))
+    return px / pv * s + lam
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (Sec. 3.4): preconditioned SGD with the estimated, thresholded
+# diagonal and the stochastic Armijo line search of eq. (stochastic armijo).
+# ---------------------------------------------------------------------------
+@dataclass
+class Alg1State:
+    v: np.ndarray            # complex128 [M^3]
+    D: np.ndarray | None     # float64 [M^3]; None = plain SGD (D-hat == 1)
+    D_avg: np.ndarray | None
+    eta: float
+    k: int = 0
+
+
+def precond_update(D, D_avg, zHz, k: int, beta: float, alpha: float):
+    """Running mean of the probe samples, exponential average and
+    thresholding (Alg. 1, the three lines after drawing I_k and z):
+      D_avg <- (k-1)/k D_avg + (1/k) zHz
+      D     <- beta D + (1 - beta) D_avg
+      D_hat <- max(|D|, alpha).
+    Returns (D, D_avg, D_hat) as new arrays."""
+    D_avg = (k - 1) / k * D_avg + zHz / k
+    D = beta * D + (1.0 - beta) * D_avg
+    D_hat = np.maximum(np.abs(D), alpha)
+    return D, D_avg, D_hat
+
+
+def precond_step(v, g, D_hat, eta: float):
+    """v - eta D_hat^{-1} g (eq. (sgd step)) and ||g||^2_{D_hat^{-1}}."""
+    v = _c128(v).reshape(-1)
+    g = _c128(g).reshape(-1)
+    Dh = np.ones(v.shape) if D_hat is None else np.asarray(D_hat, dtype=np.float64).reshape(-1)
+    return v - eta * g / Dh, float(np.sum(np.abs(g) ** 2 / Dh))
+
+
+def alg1_iteration(grid, optics, poses_I, x_I, state: Alg1State, scale: float, lam: float,
+                   alpha: float, beta: float, c: float, zHz=None, D_hat_fixed=None,
+                   max_halvings: int = 30):
+    """One iteration k of Algorithm 1 on the minibatch (poses_I, x_I).
+    zHz: the probe sample z (.) H_I z for this iteration (None: no update of D,
+    e.g. plain SGD or a fixed preconditioner).  D_hat_fixed overrides D-hat
+    (learned or precomputed preconditioner).  Returns the number of halvings."""
+    state.k += 1
+    k = state.k
+    if D_hat_fixed is not None:
+        D_hat = np.asarray(D_hat_fixed, dtype=np.float64).reshape(-1)
+    elif state.D is not None:
+        if zHz is not None:
+            state.D, state.D_avg, D_hat = precond_update(state.D, state.D_avg,
+                                                         np.asarray(zHz).reshape(-1), k, beta, alpha)
+        else:
+            D_hat = np.maximum(np.abs(state.D), alpha)
+    else:
+        D_hat = None
+    g = gradient(grid, optics, poses_I, state.v, x_I, scale, lam).reshape(-1)
+    f0 = loss(grid, optics, poses_I, state.v, x_I, scale, lam)
+    eta = state.eta
+    halvings = 0
+    while True:
+        v_new, gn = precond_step(state.v, g, D_hat, eta)
+        f1 = loss(grid, optics, poses_I, v_new, x_I, scale, lam)
+        if f1 <= f0 - c * eta * gn:
+            break
+        eta /= 2.0
+        halvings += 1
+        if halvings > max_halvings:
+            raise RuntimeError("Armijo line search did not terminate")
+    state.v = v_new
+    state.eta = eta
+    return halvings
+
+
+def cg_solve(apply_H, b, precond=None, tol: float = 1e-10, max_iter: int = 1000, x0=None):
+    """Conjugate gradients for H v = b (eq. (lin sys)); H is Hermitian positive
+    definite.  precond: diagonal (array) of a Jacobi preconditioner or None."""
+    b = _c128(b).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).reshape(-1).copy()
+    r = b - apply_H(x)
+    Minv = None if precond is None else 1.0 / np.asarray(precond, dtype=np.float64).reshape(-1)
+    zr = r if Minv is None else Minv * r
+    p = zr.copy()
+    rz = np.vdot(r, zr).real
+    bn = np.linalg.norm(b)
+    for it in range(max_iter):
+        if np.linalg.norm(r) <= tol * bn:
+            return x, it
+        Ap = apply_H(p)
+        a = rz / np.vdot(p, Ap).real
+        x = x + a * p
+        r = r - a * Ap
+        zr = r if Minv is None else Minv * r
+        rz_new = np.vdot(r, zr).real
+        p = zr + (rz_new / rz) * p
+        rz = rz_new
+    return x, max_iter
+
+
+def relative_error(v, v_star, mask=None) -> float:
+    """||m (.) (v - v*)|| / ||m (.) v*||."""
+    v = _c128(v).reshape(-1)
+    vs = _c128(v_star).reshape(-1)
+    if mask is not None:
+        m = np.asarray(mask).reshape(-1)
+        v, vs = v[m], vs[m]
+    return float(np.linalg.norm(v - vs) / np.linalg.norm(vs))
+
+
+def fsc(u, v, M: int):
+    """Fourier shell correlation per integer shell, eq. (fsc)."""
+    ax = np.arange(M) - M // 2
+    r = np.rint(np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2)).astype(int)
+    u = _c128(u).reshape(M, M, M)
+    v = _c128(v).reshape(M, M, M)
+    out = []
+    for s in range(M // 2):
+        m = r == s
+        num = np.sum(u[m] * np.conj(v[m]))
+        den = np.sqrt(np.sum(np.abs(u[m]) ** 2) * np.sum(np.abs(v[m]) ** 2))
+        out.append((num / den).real if den > 0 else 0.0)
+    return np.array(out)
