@@ -1,0 +1,207 @@
+"""Benchmark: one step = one iteration of Algorithm 1 (Hutchinson arm) on a
+resident batch of 1024 images of 256 x 256 against a 256^3 complex64 Fourier
+volume -- the whole hot path: Rademacher probes and their Hessian-vector
+product, the fused minibatch gradient (forward projection, residual, loss,
+adjoint), the running-mean / exponential-average / threshold update of the
+diagonal, the preconditioned step and the Armijo line-search forward pass.
+
+Prints one JSON line.  `value` = images per second through full iterations;
+`fwd_adj_images_per_s` = images per second of one plain forward projection
+plus one adjoint of the same batch.  `roofline` is for the dominant call of
+the step, with bytes from the per-image footprint model.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "fwd+adj images/s @256³; time-to-1e-2 err: learned vs Hutchinson vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--M", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-images", type=int, default=48, help="images in the oracle's timed sample")
+    ap.add_argument("--deterministic", action="store_true")
+    return ap.parse_args()
+
+
+def disk_pixels(M, rmax):
+    ax = np.arange(M) - M // 2
+    return int(np.sum((ax[:, None] ** 2 + ax[None, :] ** 2) <= rmax * rmax))
+
+
+# Distinct voxels touched per image by trilinear stencils, as a multiple of
+# the disk pixels (measured on random rotations: 2.51 at M = 256).
+U_OVER_P = 2.51
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2311_16100_amd import binding as B
+    from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    W = synth.WORKLOADS["hires_256"]
+    M, Bsz, N = args.M, args.batch, W.N
+    grid, optics = B.Grid(M), B.Optics()
+    rmax = grid.rmax
+    P = disk_pixels(M, rmax)
+    U = U_OVER_P * P
+
+    t0 = time.time()
+    vol_true = synth.blob_volume(M, W.n_blobs, W.seed)
+    rot_all = synth.uniform_rotations(N, W.seed)
+    df_all = synth.defocus_values(N, W.defocus_um[0], W.defocus_um[1], W.seed)
+    print("[bench] inputs generated in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    v_true = torch.from_numpy(vol_true).to(dev)
+    rot_d = torch.from_numpy(rot_all).to(dev)
+    df_d = torch.from_numpy(df_all).to(dev)
+    rot_b = rot_d[:Bsz].contiguous()
+    df_b = df_d[:Bsz].contiguous()
+    # the batch of data images: noise-free projections of the ground truth
+    x_b = B.project(grid, optics, rot_b, df_b, v_true)
+    scale = N / Bsz
+    lam = 1e-2
+    alpha = B.threshold_alpha(grid, optics, rot_d, df_d, lam).item()
+    v0 = torch.zeros_like(v_true)
+    cfg = Alg1Config(deterministic=args.deterministic)
+    run = Alg1Runner(grid, optics, "hutchinson", scale, lam, alpha, cfg, v0, batch=Bsz)
+
+    # per-call event timing inside the step
+    calls = {}
+
+    def timed(name, fn):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        calls.setdefault(name, []).append((s, e))
+
+    for _ in range(args.warmup):
+        run.iteration(rot_b, df_b, x_b)
+    torch.cuda.synchronize()
+    calls.clear()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        run.iteration(rot_b, df_b, x_b)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t_start
+    ms_per_step = 1e3 * t_steps / args.steps
+    print("[bench] %d Alg.1 steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # per-call breakdown of the same step (separate, identical iterations)
+    for _ in range(args.steps):
+        st = run.state
+        g_, o_ = grid, optics
+        st.k += 1
+        timed("hutchinson_probe", lambda: B.hutchinson_diag(g_, o_, rot_b, df_b, cfg.n_probe, cfg.probe_seed, scale,
+                                                            lam, probe0=(st.k - 1) * cfg.n_probe,
+                                                            diag_out=run.zHz, workspace=run.ws_hutch))
+        timed("gradient", lambda: B.gradient(g_, o_, rot_b, df_b, st.v, x_b, scale, lam, grad_out=run.g,
+                                             loss_out=run.sc[0:1], deterministic=cfg.deterministic,
+                                             workspace=run.ws_grad))
+        timed("precond_step", lambda: B.precond_sgd_step(st.v, run.g, st.D, st.D_avg, run.zHz, st.k, cfg.beta,
+                                                         alpha, st.eta, v_out=run.v_new, stats_out=run.sc[1:3]))
+        timed("armijo_project", lambda: B.project(g_, o_, rot_b, df_b, run.v_new, subtract=x_b, out=None,
+                                                  loss=run.sc[3:4], want_out=False))
+    # plain forward + adjoint of the batch
+    y = torch.empty_like(x_b)
+    acc = torch.zeros_like(v_true)
+    for _ in range(args.steps):
+        timed("project", lambda: B.project(grid, optics, rot_b, df_b, v_true, out=y))
+        timed("backproject", lambda: B.backproject(grid, optics, rot_b, df_b, x_b, ctf_power=1, accum=acc,
+                                                   deterministic=args.deterministic))
+    torch.cuda.synchronize()
+    ms = {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in calls.items()}
+    fwd_adj = Bsz / ((ms["project"] + ms["backproject"]) * 1e-3)
+
+    # footprint model (bytes per image): gather 8U, scatter read-modify-write
+    # 16U, image read 8P, image write 8 M^2
+    model = {
+        "gradient": 8 * P + 24 * U,
+        "hutchinson_probe": 24 * U * math.ceil(cfg.n_probe / 2),
+        "armijo_project": 8 * P + 8 * U,
+        "project": 8 * M * M + 8 * U,
+        "backproject": 8 * P + 16 * U,
+    }
+    dominant = max((k for k in ("gradient", "hutchinson_probe", "armijo_project")), key=lambda k: ms[k])
+    achieved = model[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "kernel_ms": round(ms[dominant], 4), "bytes_model": "per image: gather 8U + RMW 16U + image 8P",
+                "P": P, "U": round(U)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(vol_true, rot_all, df_all, M, args.cpu_images, scale, lam, alpha)
+
+    out = {
+        "metric": METRIC,
+        "value": round(Bsz / (ms_per_step * 1e-3), 1),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hires_256: Algorithm 1 iteration (Hutchinson arm, 2 probes) on a resident batch of "
+                               "%d images of %dx%d, %d^3 complex64 volume of %d Gaussian blobs, N=%d, "
+                               "trilinear, CTF 300kV/Cs2.7/A0.1, defocus 1-3um" % (Bsz, M, M, M, W.n_blobs, N),
+                   "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic)},
+        "fwd_adj_images_per_s": round(fwd_adj, 1),
+        "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(vol, rot_all, df_all, M, n_img, scale_full, lam, alpha):
+    """One Algorithm 1 iteration of the FP64 oracle (Hutchinson arm, 2
+    probes) on n_img images of the same workload, single-threaded."""
+    import oracle
+    grid, opt = oracle.Grid(M), oracle.Optics()
+    P = oracle.Poses(rot_all[:n_img], df_all[:n_img])
+    v_true = vol.astype(np.complex128)
+    t0 = time.perf_counter()
+    x = oracle.project(grid, opt, P, v_true)
+    st = oracle.Alg1State(v=np.zeros(M ** 3, np.complex128), D=np.ones(M ** 3), D_avg=np.zeros(M ** 3), eta=1.0)
+    t1 = time.perf_counter()
+    zHz = oracle.hutchinson_diag(grid, opt, P, 2, 4, scale_full, lam).reshape(-1)
+    oracle.alg1_iteration(grid, opt, P, x, st, scale_full, lam, alpha, 0.9, 0.1, zHz=zHz)
+    t2 = time.perf_counter()
+    del t0
+    return {"value": round(n_img / (t2 - t1), 3), "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": "one Algorithm 1 iteration (2 probes) on %d images of the %d^3 workload, FP64 C + numpy, "
+                      "single thread; %.1f s" % (n_img, M, t2 - t1)}
+
+
+if __name__ == "__main__":
+    main()

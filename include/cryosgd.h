@@ -1,0 +1,206 @@
+/*
+ * cryosgd.h -- C ABI of the MI355X (gfx950) implementation of the known-pose
+ * Fourier-slice refinement of Toader, Brubaker & Lederman, "Efficient
+ * high-resolution refinement in cryo-EM with stochastic gradient descent"
+ * (arXiv:2311.16100).
+ *
+ * General rules for every entry point
+ * -----------------------------------
+ *  - Pointers to volumes, images, rotations, defocus values, probes and
+ *    results are DEVICE pointers owned by the caller.  Descriptors
+ *    (csg_grid, csg_optics, csg_poses) are HOST structs read during the call.
+ *    The library keeps no pointer after a call returns.
+ *  - Complex data is complex64 stored interleaved (re, im) as float pairs:
+ *    a "complex [K]" argument points to 2*K floats.
+ *  - Volumes are [M][M][M] complex, index ((kz+M/2)*M + ky+M/2)*M + kx+M/2
+ *    for frequencies k in {-M/2, ..., M/2-1} (DC at index M/2 on each axis).
+ *    Images are [n][M][M] complex, index (i*M + ky+M/2)*M + kx+M/2.
+ *  - Rotations are [n][3][3] float, row-major.  Pixel (kx,ky) of image i
+ *    samples the volume at p = R_i^T (kx,ky,0) = kx R_i[0,:] + ky R_i[1,:]
+ *    (the rotated volume is read at R^T r, Sec. 2.1).
+ *  - Only pixels with kx^2 + ky^2 <= r_max^2 are used ("the disk"); the
+ *    projector writes 0 elsewhere and the adjoint and the loss ignore them.
+ *    An interpolation corner outside the grid counts as zero.
+ *  - All work is enqueued on `stream` (a hipStream_t, NULL = the null
+ *    stream); calls are asynchronous unless stated.  Nothing is allocated:
+ *    scratch memory comes from the caller's `workspace` (size from
+ *    csg_workspace_bytes).
+ *  - Return value: CSG_OK, or a negative code; csg_last_error() then holds
+ *    a message (per thread).  No C++ exception crosses the ABI.
+ */
+#ifndef CRYOSGD_H
+#define CRYOSGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSG_OK 0
+#define CSG_EINVAL (-1)     /* invalid argument (shape, null pointer, range) */
+#define CSG_EHIP (-2)       /* HIP launch or runtime error */
+#define CSG_EWORKSPACE (-3) /* workspace missing or too small */
+
+/* Discretisation (Sec. 2.1 and Definition "Projection operator").
+ * M: grid side, even, 4 <= M <= 1024.
+ * r_max: disk radius in pixels, 0 <= r_max <= M/2 - 1.
+ * interp: 0 nearest neighbour (eq. (def nn interp), nearest point
+ *         floor(p + 1/2) per axis), 1 trilinear (eq. (def tri interp)). */
+typedef struct csg_grid {
+    int32_t M;
+    float r_max;
+    int32_t interp;
+} csg_grid;
+
+/* CTF C_i (Sec. 2.1: real, radially symmetric, per-image defocus).  Weak-
+ * phase model C(s) = -(sqrt(1-A^2) sin chi + A cos chi), chi = pi lambda df
+ * s^2 - (pi/2) Cs lambda^3 s^4, s = |k| / (M pixel_A), lambda the
+ * relativistic wavelength at kv.  ctf_on = 0 gives C == 1 (the CTF-free
+ * setting of Sec. 3.1). */
+typedef struct csg_optics {
+    float kv;           /* accelerating voltage, kV (> 0 if ctf_on) */
+    float cs_mm;        /* spherical aberration, mm */
+    float amp_contrast; /* amplitude contrast A, 0 <= A < 1 */
+    float pixel_A;      /* pixel size, Angstrom (> 0 if ctf_on) */
+    int32_t ctf_on;
+} csg_optics;
+
+/* Known poses phi_i (Definition "Projection operator"; no in-plane shifts)
+ * and per-image CTF parameters of a batch of n >= 0 images. */
+typedef struct csg_poses {
+    int64_t n;
+    const float *rot;       /* device [n][3][3] */
+    const float *defocus_A; /* device [n], Angstrom, underfocus > 0 */
+} csg_poses;
+
+/* Forward model without noise, eq. (fwd model): y_i = C_i P_i v.
+ *   vol      device complex [M^3]
+ *   subtract device complex [n][M][M] or NULL: if given, out = C P v - x
+ *   out      device complex [n][M][M] or NULL (then loss_accum is required)
+ *   loss_accum device double scalar or NULL: += 1/2 sum_disk |C P v - x|^2
+ *            (x = 0 when subtract is NULL).  Not zeroed by the call.
+ * out and vol must not overlap. */
+int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                const float *vol, const float *subtract, float *out, double *loss_accum,
+                void *stream);
+
+/* Adjoint / backprojection, the operator P_i^* C_i that appears in the M step
+ * (eq. (em v)) and in b = sum_i P_i^* x_i (eq. (lin sys)):
+ *   vol_accum += scale * sum_i P_i^T C_i^p img_i,  p = ctf_power in {0,1,2}.
+ *   img        device complex [n][M][M] (pixels outside the disk ignored)
+ *   vol_accum  device complex [M^3], accumulated into
+ *   deterministic 0: fast scatter (floating-point summation order varies
+ *                 between runs); 1: each voxel sums its contributions in a
+ *                 fixed order (bitwise reproducible, slower).
+ *   workspace  device scratch of at least csg_workspace_bytes(grid, n,
+ *              CSG_WS_BACKPROJECT) bytes (may be NULL when that is 0). */
+int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                    const float *img, int32_t ctf_power, float scale, float *vol_accum,
+                    int32_t deterministic, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Minibatch gradient and loss of the known-pose least-squares problem,
+ * eq. (optim cp) with the CTF re-inserted (eq. (em v)) and the batch scaled
+ * by `scale` (N/B for an unbiased estimate of the full objective):
+ *   f(v)     = scale * 1/2 sum_i ||C_i P_i v - x_i||^2 + lambda/2 ||v||^2
+ *   grad_out = scale * sum_i P_i^T C_i (C_i P_i v - x_i) + lambda v
+ * (complex gradient convention d/dRe + i d/dIm).  The residual images are
+ * never written to memory.
+ *   vol       device complex [M^3];  x device complex [n][M][M]
+ *   grad_out  device complex [M^3], overwritten (must not alias vol)
+ *   loss_out  device double scalar or NULL, overwritten with f(v).
+ *   deterministic as in csg_backproject.
+ *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_GRADIENT or
+ *             CSG_WS_GRADIENT_DETERMINISTIC). */
+int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                 const float *vol, const float *x, float scale, float lambda, float *grad_out,
+                 double *loss_out, int32_t deterministic, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* Hessian-vector product of the same objective (eq. (hessian)); H is real and
+ * independent of v, so a complex z carries two real products:
+ *   hz_out = scale * sum_i P_i^T C_i^2 P_i z + lambda z
+ *   z, hz_out device complex [M^3] (hz_out overwritten, must not alias z).
+ *   deterministic, workspace: as in csg_gradient (no workspace is needed
+ *             when deterministic = 0). */
+int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+            const float *z, float scale, float lambda, float *hz_out, int32_t deterministic,
+            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Rademacher(0.5) probe of Hutchinson's estimator (eq. (hutch)), entries
+ * +1/-1: z_k = 1 - 2 b, b = bit (k mod 128) of Philox4x32-10 (Salmon et al.,
+ * SC'11) with key (seed lo, seed hi) and counter (k/128, probe lo, probe hi,
+ * 0x52414431); within the 128-bit block bit j is bit (j mod 32) of word j/32.
+ *   z_out device float [nvox], overwritten. */
+int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, void *stream);
+
+/* Hutchinson's diagonal estimate D = mean_p z_p (.) H z_p (eq. (hutch)) over
+ * the probes probe0 .. probe0 + n_probe - 1 (as csg_rademacher), with H the
+ * minibatch Hessian of csg_hvp.  Two probes share one complex product.
+ *   diag_out device float [M^3], overwritten.
+ *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_HUTCHINSON). */
+int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                        int32_t n_probe, uint64_t seed, int64_t probe0, float scale, float lambda,
+                        float *diag_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Exact diagonal of the minibatch Hessian: diag_out = scale * sum_ij C_ij^2
+ * w_ijk^2 + lambda (squared interpolation weights; eq. (hessian) with eq.
+ * (def tri interp)).  diag_out device float [M^3], overwritten. */
+int csg_exact_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                   float scale, float lambda, float *diag_out, void *stream);
+
+/* One preconditioned SGD step of Algorithm 1 (Sec. 3.4), elementwise over
+ * nvox voxels:
+ *   if zHz != NULL (probe sample of this iteration k >= 1):
+ *       D_avg = (k-1)/k D_avg + zHz / k ;  D = beta D + (1-beta) D_avg
+ *   D_hat  = max(|D|, alpha)                (eq. (thresh)); D == NULL: D_hat = 1
+ *   v_out  = v - eta g / D_hat              (eq. (sgd step))
+ *   stats_out[0] = sum |g|^2 / D_hat        (the norm of eq. (stochastic armijo))
+ *   stats_out[1] = sum |v_out|^2
+ *   v, g, v_out device complex [nvox] (v_out may alias v only if g does not)
+ *   D, D_avg device float [nvox] updated in place (D_avg may be NULL when
+ *            zHz is NULL); Dhat_out device float [nvox] or NULL
+ *   stats_out device double [2], overwritten. */
+int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D, float *D_avg,
+                         const float *zHz, int64_t k, float beta, float alpha, float eta,
+                         float *v_out, float *Dhat_out, double *stats_out, void *stream);
+
+/* Threshold of the preconditioner, eq. (thresh value) (Sec. 3.3): the
+ * expected Hessian entry at the maximum radius R = round(r_max),
+ *   alpha = (P_x(R) / P_v(R)) * sum_{i=1}^N C_i(R)^2 + lambda,
+ * with P_x(R), P_v(R) the numbers of pixels / voxels of the grid whose radius
+ * rounds to R, and the sum over all N images of `poses` (the whole data set).
+ *   alpha_out device double scalar, overwritten. */
+int csg_threshold_alpha(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                        float lambda, double *alpha_out, void *stream);
+
+/* Per-voxel inputs of the learned preconditioner:
+ *   ctf2_accum[k]  += sum_i sum_j C_ij^2 w_ijk   (CTF^2 weight)
+ *   cover_accum[k] += |{i : some pixel of image i has w_ijk > 0}| (the size of
+ *                     the voxel mapping set Omega_k, Definition "Voxel mapping
+ *                     set", over trilinear stencils)
+ * both device float [M^3]. */
+int csg_features(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                 float *ctf2_accum, float *cover_accum, void *stream);
+
+/* Workspace sizes (bytes) for a batch of n images:
+ *   CSG_WS_BACKPROJECT             csg_backproject (either mode)
+ *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: two complex volumes
+ *   CSG_WS_GRADIENT                csg_gradient / csg_hvp, deterministic = 0
+ *   CSG_WS_GRADIENT_DETERMINISTIC  csg_gradient / csg_hvp, deterministic = 1
+ *                                  (adds one complex image per batch image)
+ * Workspaces must be 256-byte aligned.  Returns 0 for an invalid grid. */
+#define CSG_WS_BACKPROJECT 0
+#define CSG_WS_HUTCHINSON 1
+#define CSG_WS_GRADIENT 2
+#define CSG_WS_GRADIENT_DETERMINISTIC 3
+size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
+
+/* Message for the last nonzero return on the calling thread. */
+const char *csg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRYOSGD_H */

@@ -1,0 +1,314 @@
+"""Thin ctypes binding of libcryosgd (include/cryosgd.h).
+
+Argument marshalling only: every call hands device pointers of torch tensors
+and the current HIP stream to the C ABI; all arithmetic runs in the library's
+HIP kernels.  If the library is missing the import of any function here fails
+loudly -- there is no fallback.
+
+Tensors: volumes complex64 [M,M,M]; images complex64 [n,M,M]; rotations
+float32 [n,3,3]; defocus float32 [n] (Angstrom); all on the same CUDA (HIP)
+device and contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcryosgd.so")
+
+CSG_WS_BACKPROJECT = 0
+CSG_WS_HUTCHINSON = 1
+CSG_WS_GRADIENT = 2
+CSG_WS_GRADIENT_DETERMINISTIC = 3
+
+
+class CsgError(RuntimeError):
+    pass
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("r_max", ctypes.c_float), ("interp", ctypes.c_int32)]
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("kv", ctypes.c_float), ("cs_mm", ctypes.c_float), ("amp_contrast", ctypes.c_float),
+                ("pixel_A", ctypes.c_float), ("ctf_on", ctypes.c_int32)]
+
+
+class _Poses(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rot", ctypes.c_void_p), ("defocus_A", ctypes.c_void_p)]
+
+
+EXPORTS = {
+    "csg_project": [ctypes.c_void_p] * 7 + [ctypes.c_void_p],
+    "csg_backproject": [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "csg_gradient": [ctypes.c_void_p] * 5 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "csg_hvp": [ctypes.c_void_p] * 4 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "csg_rademacher": [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_hutchinson_diag": [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_float,
+                                                    ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_size_t, ctypes.c_void_p],
+    "csg_exact_diag": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_features": [ctypes.c_void_p] * 5 + [ctypes.c_void_p],
+    "csg_precond_sgd_step": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_threshold_alpha": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_workspace_bytes": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32],
+    "csg_last_error": [],
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcryosgd.so (built in-tree by paper_2311_16100_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CsgError("libcryosgd.so is not built (%s); run `python paper_2311_16100_amd/build.py`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in EXPORTS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.csg_workspace_bytes.restype = ctypes.c_size_t
+        L.csg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().csg_last_error().decode(errors="replace")
+        raise CsgError("%s failed (%d): %s" % (what, rc, msg))
+
+
+@dataclass(frozen=True)
+class Grid:
+    M: int
+    r_max: float | None = None
+    interp: int = 1
+
+    @property
+    def rmax(self) -> float:
+        return float(self.M // 2 - 1) if self.r_max is None else float(self.r_max)
+
+    def c(self) -> _Grid:
+        return _Grid(int(self.M), float(self.rmax), int(self.interp))
+
+
+@dataclass(frozen=True)
+class Optics:
+    kv: float = 300.0
+    cs_mm: float = 2.7
+    amp_contrast: float = 0.1
+    pixel_A: float = 1.0
+    ctf_on: bool = True
+
+    def c(self) -> _Optics:
+        return _Optics(self.kv, self.cs_mm, self.amp_contrast, self.pixel_A, int(self.ctf_on))
+
+
+NO_CTF = Optics(ctf_on=False)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise CsgError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise CsgError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _poses(rot: torch.Tensor, defocus: torch.Tensor) -> _Poses:
+    if rot.dtype != torch.float32 or defocus.dtype != torch.float32:
+        raise CsgError("rotations and defocus must be float32")
+    n = rot.shape[0] if rot.dim() == 3 else rot.numel() // 9
+    if rot.numel() != 9 * n or defocus.numel() != n:
+        raise CsgError("rot must be [n,3,3] and defocus [n]")
+    return _Poses(n, _ptr(rot), _ptr(defocus))
+
+
+def _cplx(t: torch.Tensor, shape, name):
+    if t.dtype != torch.complex64:
+        raise CsgError("%s must be complex64" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise CsgError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return _ptr(t)
+
+
+def workspace_bytes(grid: Grid, n: int, which: int) -> int:
+    g = grid.c()
+    return int(lib().csg_workspace_bytes(ctypes.byref(g), int(n), int(which)))
+
+
+def alloc_workspace(grid: Grid, n: int, which: int, device=None) -> torch.Tensor | None:
+    nb = workspace_bytes(grid, n, which)
+    if nb == 0:
+        return None
+    ws = torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
+    if ws.data_ptr() % 256:
+        raise CsgError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+def _ws(ws):
+    return (None, 0) if ws is None else (_ptr(ws), ws.numel())
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI without the csg_ prefix)
+# ---------------------------------------------------------------------------
+def project(grid: Grid, optics: Optics, rot, defocus, vol, subtract=None, out=None, loss=None,
+            want_out: bool = True, stream=None):
+    """C P v (- subtract) for each image; returns `out` (allocated if None)."""
+    M = grid.M
+    p = _poses(rot, defocus)
+    if want_out and out is None:
+        out = torch.empty((p.n, M, M), dtype=torch.complex64, device=vol.device)
+    g, o = grid.c(), optics.c()
+    _check(lib().csg_project(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(vol, (M, M, M), "vol"),
+                             None if subtract is None else _cplx(subtract, (p.n, M, M), "subtract"),
+                             None if out is None else _cplx(out, (p.n, M, M), "out"),
+                             None if loss is None else _ptr(loss), _stream(stream)), "csg_project")
+    return out
+
+
+def backproject(grid: Grid, optics: Optics, rot, defocus, img, ctf_power: int = 1, scale: float = 1.0,
+                accum=None, deterministic: bool = False, workspace=None, stream=None):
+    """accum += scale P^T C^p img; returns accum (zeros if None)."""
+    M = grid.M
+    p = _poses(rot, defocus)
+    if accum is None:
+        accum = torch.zeros((M, M, M), dtype=torch.complex64, device=img.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_backproject(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
+                                 _cplx(img, (p.n, M, M), "img"), int(ctf_power), float(scale),
+                                 _cplx(accum, (M, M, M), "accum"), int(bool(deterministic)), wp, wn,
+                                 _stream(stream)), "csg_backproject")
+    return accum
+
+
+def gradient(grid: Grid, optics: Optics, rot, defocus, vol, x, scale: float, lam: float, grad_out=None,
+             loss_out=None, deterministic: bool = False, workspace=None, stream=None):
+    """grad = scale P^T C (C P v - x) + lam v; loss_out (device float64 [1]) = f(v)."""
+    M = grid.M
+    p = _poses(rot, defocus)
+    if grad_out is None:
+        grad_out = torch.empty((M, M, M), dtype=torch.complex64, device=vol.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_GRADIENT_DETERMINISTIC if deterministic else CSG_WS_GRADIENT,
+                                    vol.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_gradient(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(vol, (M, M, M), "vol"),
+                              _cplx(x, (p.n, M, M), "x"), float(scale), float(lam),
+                              _cplx(grad_out, (M, M, M), "grad_out"),
+                              None if loss_out is None else _ptr(loss_out), int(bool(deterministic)), wp, wn,
+                              _stream(stream)), "csg_gradient")
+    return grad_out
+
+
+def hvp(grid: Grid, optics: Optics, rot, defocus, z, scale: float, lam: float, hz_out=None,
+        deterministic: bool = False, workspace=None, stream=None):
+    """hz = scale P^T C^2 P z + lam z."""
+    M = grid.M
+    p = _poses(rot, defocus)
+    if hz_out is None:
+        hz_out = torch.empty((M, M, M), dtype=torch.complex64, device=z.device)
+    if deterministic and workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_GRADIENT_DETERMINISTIC, z.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_hvp(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(z, (M, M, M), "z"), float(scale),
+                         float(lam), _cplx(hz_out, (M, M, M), "hz_out"), int(bool(deterministic)), wp, wn,
+                         _stream(stream)), "csg_hvp")
+    return hz_out
+
+
+def rademacher(nvox: int, seed: int, probe: int, out=None, device=None, stream=None):
+    if out is None:
+        out = torch.empty(nvox, dtype=torch.float32, device=device or "cuda")
+    _check(lib().csg_rademacher(int(nvox), int(seed), int(probe), _ptr(out), _stream(stream)), "csg_rademacher")
+    return out
+
+
+def hutchinson_diag(grid: Grid, optics: Optics, rot, defocus, n_probe: int, seed: int, scale: float, lam: float,
+                    probe0: int = 0, diag_out=None, workspace=None, stream=None):
+    M = grid.M
+    p = _poses(rot, defocus)
+    if diag_out is None:
+        diag_out = torch.empty((M, M, M), dtype=torch.float32, device=rot.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_HUTCHINSON, rot.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_hutchinson_diag(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), int(n_probe), int(seed),
+                                     int(probe0), float(scale), float(lam), _ptr(diag_out), wp, wn,
+                                     _stream(stream)), "csg_hutchinson_diag")
+    return diag_out
+
+
+def exact_diag(grid: Grid, optics: Optics, rot, defocus, scale: float, lam: float, diag_out=None, stream=None):
+    M = grid.M
+    p = _poses(rot, defocus)
+    if diag_out is None:
+        diag_out = torch.empty((M, M, M), dtype=torch.float32, device=rot.device)
+    g, o = grid.c(), optics.c()
+    _check(lib().csg_exact_diag(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), float(scale), float(lam),
+                                _ptr(diag_out), _stream(stream)), "csg_exact_diag")
+    return diag_out
+
+
+def features(grid: Grid, optics: Optics, rot, defocus, ctf2=None, cover=None, stream=None):
+    M = grid.M
+    p = _poses(rot, defocus)
+    if ctf2 is None:
+        ctf2 = torch.zeros((M, M, M), dtype=torch.float32, device=rot.device)
+    if cover is None:
+        cover = torch.zeros((M, M, M), dtype=torch.float32, device=rot.device)
+    g, o = grid.c(), optics.c()
+    _check(lib().csg_features(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _ptr(ctf2), _ptr(cover),
+                              _stream(stream)), "csg_features")
+    return ctf2, cover
+
+
+def threshold_alpha(grid: Grid, optics: Optics, rot, defocus, lam: float, alpha_out=None, stream=None):
+    """alpha of eq. (thresh value) over all images given; device float64 [1]."""
+    p = _poses(rot, defocus)
+    if alpha_out is None:
+        alpha_out = torch.empty(1, dtype=torch.float64, device=defocus.device)
+    g, o = grid.c(), optics.c()
+    _check(lib().csg_threshold_alpha(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), float(lam), _ptr(alpha_out),
+                                     _stream(stream)), "csg_threshold_alpha")
+    return alpha_out
+
+
+def precond_sgd_step(v, g, D, D_avg, zHz, k: int, beta: float, alpha: float, eta: float, v_out=None,
+                     Dhat_out=None, stats_out=None, stream=None):
+    """One step of Algorithm 1 (see include/cryosgd.h); returns (v_out, stats_out[2])."""
+    nvox = v.numel()
+    if v_out is None:
+        v_out = torch.empty_like(v)
+    if stats_out is None:
+        stats_out = torch.empty(2, dtype=torch.float64, device=v.device)
+    _check(lib().csg_precond_sgd_step(int(nvox), _ptr(v), _ptr(g), _ptr(D), _ptr(D_avg), _ptr(zHz), int(k),
+                                      float(beta), float(alpha), float(eta), _ptr(v_out), _ptr(Dhat_out),
+                                      _ptr(stats_out), _stream(stream)), "csg_precond_sgd_step")
+    return v_out, stats_out

@@ -1,0 +1,346 @@
+// api.hip -- the C ABI of libcryosgd (declared in include/cryosgd.h):
+// argument validation, workspace carving and kernel sequencing.  Every entry
+// point only enqueues work on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "../../include/cryosgd.h"
+#include "csg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return CSG_OK;
+    return fail(CSG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CSG_TRY(expr, what)                         \
+    do {                                            \
+        int _rc = hip_check((expr), (what));        \
+        if (_rc != CSG_OK) return _rc;              \
+    } while (0)
+
+// Relativistic electron wavelength in Angstrom:
+// lambda = h / sqrt(2 m0 e V (1 + e V / (2 m0 c^2))), CODATA 2018 constants.
+double electron_wavelength_A(double kv) {
+    const double planck = 6.62607015e-34, electron_mass = 9.1093837015e-31;
+    const double charge = 1.602176634e-19, light = 299792458.0;
+    const double volts = kv * 1.0e3;
+    const double p2 = 2.0 * electron_mass * charge * volts * (1.0 + charge * volts / (2.0 * electron_mass * light * light));
+    return planck / sqrt(p2) * 1.0e10;
+}
+
+int make_geom(const csg_grid *grid, const csg_optics *optics, csg::Geom *g) {
+    if (!grid) return fail(CSG_EINVAL, "grid descriptor is NULL");
+    if (!optics) return fail(CSG_EINVAL, "optics descriptor is NULL");
+    const int M = grid->M;
+    if (M < 4 || M > 1024 || (M & 1)) return fail(CSG_EINVAL, "grid side M=%d must be even and in [4, 1024]", M);
+    if (!(grid->r_max >= 0.0f) || grid->r_max > (float)(M / 2 - 1))
+        return fail(CSG_EINVAL, "r_max=%g must lie in [0, M/2-1=%d]", (double)grid->r_max, M / 2 - 1);
+    if (grid->interp != 0 && grid->interp != 1) return fail(CSG_EINVAL, "interp=%d must be 0 or 1", grid->interp);
+    g->M = M;
+    g->half = M / 2;
+    g->interp = grid->interp;
+    g->k2max = (int)floor((double)grid->r_max * (double)grid->r_max);
+    g->ctf_on = optics->ctf_on ? 1 : 0;
+    g->ctf_a = g->ctf_b = g->inv_s2 = g->phase0 = 0.0;
+    if (g->ctf_on) {
+        const double kv = optics->kv, cs = optics->cs_mm, A = optics->amp_contrast, px = optics->pixel_A;
+        if (!(kv > 0.0) || !isfinite(kv)) return fail(CSG_EINVAL, "kv=%g must be positive", kv);
+        if (!(px > 0.0) || !isfinite(px)) return fail(CSG_EINVAL, "pixel_A=%g must be positive", px);
+        if (!(A >= 0.0 && A < 1.0)) return fail(CSG_EINVAL, "amp_contrast=%g must lie in [0, 1)", A);
+        if (!(cs >= 0.0) || !isfinite(cs)) return fail(CSG_EINVAL, "cs_mm=%g must be non-negative", cs);
+        const double lam = electron_wavelength_A(kv);
+        g->ctf_a = 0.5 * lam;                          // chi/2pi = (lambda df / 2) s^2 ...
+        g->ctf_b = 0.25 * cs * 1.0e7 * lam * lam * lam; // ... - (Cs lambda^3 / 4) s^4
+        g->inv_s2 = 1.0 / ((double)M * px * (double)M * px);
+        g->phase0 = asin(A) / (2.0 * M_PI);
+    }
+    return CSG_OK;
+}
+
+int check_poses(const csg_poses *p) {
+    if (!p) return fail(CSG_EINVAL, "poses descriptor is NULL");
+    if (p->n < 0) return fail(CSG_EINVAL, "n=%lld must be non-negative", (long long)p->n);
+    if (p->n > 0 && (!p->rot || !p->defocus_A)) return fail(CSG_EINVAL, "rot and defocus_A must be non-NULL");
+    return CSG_OK;
+}
+
+int64_t nvox_of(const csg::Geom &g) { return (int64_t)g.M * g.M * g.M; }
+
+constexpr size_t kScalarBytes = 256;  // device scalars at the start of a workspace
+
+size_t image_bytes(int M, int64_t n) { return (size_t)n * (size_t)M * (size_t)M * 8u; }
+
+int need_workspace(void *ws, size_t have, size_t need, const char *who) {
+    if (need == 0) return CSG_OK;
+    if (!ws) return fail(CSG_EWORKSPACE, "%s: workspace of %zu bytes required, got NULL", who, need);
+    if (have < need) return fail(CSG_EWORKSPACE, "%s: workspace of %zu bytes required, got %zu", who, need, have);
+    if (((uintptr_t)ws & 255u) != 0) return fail(CSG_EWORKSPACE, "%s: workspace must be 256-byte aligned", who);
+    return CSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *csg_last_error(void) { return g_last_error.c_str(); }
+
+size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
+    if (!grid || grid->M < 4 || grid->M > 1024 || (grid->M & 1) || n < 0) return 0;
+    const int M = grid->M;
+    const size_t vol = (size_t)M * M * M * 8u;
+    switch (which) {
+        case CSG_WS_BACKPROJECT: return 0;
+        case CSG_WS_GRADIENT: return kScalarBytes;
+        case CSG_WS_GRADIENT_DETERMINISTIC: return kScalarBytes + image_bytes(M, n);
+        case CSG_WS_HUTCHINSON: return kScalarBytes + 2 * vol;
+        default: return 0;
+    }
+}
+
+int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *vol,
+                const float *subtract, float *out, double *loss_accum, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (poses->n == 0) return CSG_OK;
+    if (!vol) return fail(CSG_EINVAL, "csg_project: vol is NULL");
+    if (!out && !loss_accum) return fail(CSG_EINVAL, "csg_project: need out or loss_accum");
+    CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                (const float2 *)subtract, (float2 *)out, loss_accum, (hipStream_t)stream),
+            "csg_project");
+    return CSG_OK;
+}
+
+int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *img,
+                    int32_t ctf_power, float scale, float *vol_accum, int32_t deterministic, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+    (void)workspace;
+    (void)workspace_bytes;
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (ctf_power < 0 || ctf_power > 2) return fail(CSG_EINVAL, "ctf_power=%d must be 0, 1 or 2", ctf_power);
+    if (poses->n == 0) return CSG_OK;
+    if (!img || !vol_accum) return fail(CSG_EINVAL, "csg_backproject: img and vol_accum must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (deterministic)
+        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
+                                              ctf_power, scale, (float2 *)vol_accum, st),
+                "csg_backproject");
+    else
+        CSG_TRY(csg::launch_backproject_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
+                                               ctf_power, scale, (float2 *)vol_accum, st),
+                "csg_backproject");
+    return CSG_OK;
+}
+
+int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *vol,
+                 const float *x, float scale, float lambda, float *grad_out, double *loss_out, int32_t deterministic,
+                 void *workspace, size_t workspace_bytes, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!vol || !grad_out || (poses->n > 0 && !x))
+        return fail(CSG_EINVAL, "csg_gradient: vol, x and grad_out must be non-NULL");
+    if (vol == grad_out) return fail(CSG_EINVAL, "csg_gradient: grad_out must not alias vol");
+    const size_t need = csg_workspace_bytes(grid, poses->n, deterministic ? CSG_WS_GRADIENT_DETERMINISTIC : CSG_WS_GRADIENT);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_gradient"))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double *sc = (double *)workspace;  // sc[0] = 1/2 sum |r|^2, sc[1] = ||v||^2
+    const int64_t nv = nvox_of(g);
+    CSG_TRY(csg::launch_fill_f64(sc, 2, 0.0, st), "csg_gradient");
+    CSG_TRY(csg::launch_scaled_copy((float2 *)grad_out, (const float2 *)vol, lambda, nv, sc + 1, st), "csg_gradient");
+    if (poses->n > 0) {
+        if (!deterministic) {
+            CSG_TRY(csg::launch_gradient_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                                (const float2 *)x, scale, (float2 *)grad_out, sc, st),
+                    "csg_gradient");
+        } else {
+            float2 *resid = (float2 *)((char *)workspace + kScalarBytes);
+            CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                        (const float2 *)x, resid, sc, st),
+                    "csg_gradient");
+            CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, resid, 1, scale,
+                                                  (float2 *)grad_out, st),
+                    "csg_gradient");
+        }
+    }
+    if (loss_out) CSG_TRY(csg::launch_finish_loss(loss_out, sc, sc + 1, scale, lambda, st), "csg_gradient");
+    return CSG_OK;
+}
+
+int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *z, float scale,
+            float lambda, float *hz_out, int32_t deterministic, void *workspace, size_t workspace_bytes,
+            void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!z || !hz_out) return fail(CSG_EINVAL, "csg_hvp: z and hz_out must be non-NULL");
+    if (z == hz_out) return fail(CSG_EINVAL, "csg_hvp: hz_out must not alias z");
+    if (deterministic) {
+        const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_GRADIENT_DETERMINISTIC);
+        if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_hvp"))) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nv = nvox_of(g);
+    CSG_TRY(csg::launch_scaled_copy((float2 *)hz_out, (const float2 *)z, lambda, nv, nullptr, st), "csg_hvp");
+    if (poses->n == 0) return CSG_OK;
+    if (!deterministic) {
+        CSG_TRY(csg::launch_hvp_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, scale,
+                                       (float2 *)hz_out, st),
+                "csg_hvp");
+    } else {
+        float2 *img = (float2 *)((char *)workspace + kScalarBytes);
+        CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, nullptr, img,
+                                    nullptr, st),
+                "csg_hvp");
+        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, img, 1, scale,
+                                              (float2 *)hz_out, st),
+                "csg_hvp");
+    }
+    return CSG_OK;
+}
+
+int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, void *stream) {
+    if (nvox < 0) return fail(CSG_EINVAL, "csg_rademacher: nvox must be non-negative");
+    if (nvox == 0) return CSG_OK;
+    if (!z_out) return fail(CSG_EINVAL, "csg_rademacher: z_out is NULL");
+    CSG_TRY(csg::launch_rademacher(z_out, nvox, seed, (uint64_t)probe, (hipStream_t)stream), "csg_rademacher");
+    return CSG_OK;
+}
+
+int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, int32_t n_probe,
+                        uint64_t seed, int64_t probe0, float scale, float lambda, float *diag_out, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (n_probe < 1) return fail(CSG_EINVAL, "csg_hutchinson_diag: n_probe=%d must be >= 1", n_probe);
+    if (!diag_out) return fail(CSG_EINVAL, "csg_hutchinson_diag: diag_out is NULL");
+    const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_HUTCHINSON);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_hutchinson_diag"))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nv = nvox_of(g);
+    float2 *z = (float2 *)((char *)workspace + kScalarBytes);
+    float2 *hz = z + nv;
+    CSG_TRY(csg::launch_fill_f32(diag_out, nv, 0.0f, st), "csg_hutchinson_diag");
+    const float w = 1.0f / (float)n_probe;
+    for (int32_t p = 0; p < n_probe; p += 2) {
+        const int has_b = (p + 1 < n_probe) ? 1 : 0;
+        CSG_TRY(csg::launch_rademacher_pair(z, nv, seed, (uint64_t)(probe0 + p), (uint64_t)(probe0 + p + 1), has_b, st),
+                "csg_hutchinson_diag");
+        CSG_TRY(csg::launch_scaled_copy(hz, z, lambda, nv, nullptr, st), "csg_hutchinson_diag");
+        if (poses->n > 0)
+            CSG_TRY(csg::launch_hvp_atomic(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz, st),
+                    "csg_hutchinson_diag");
+        CSG_TRY(csg::launch_zhz_accum(diag_out, z, hz, nv, w, st), "csg_hutchinson_diag");
+    }
+    return CSG_OK;
+}
+
+int csg_exact_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, float scale, float lambda,
+                   float *diag_out, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!diag_out) return fail(CSG_EINVAL, "csg_exact_diag: diag_out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    CSG_TRY(csg::launch_fill_f32(diag_out, nvox_of(g), lambda, st), "csg_exact_diag");
+    if (poses->n > 0)
+        CSG_TRY(csg::launch_sq_diag(g, poses->rot, poses->defocus_A, poses->n, scale, diag_out, st), "csg_exact_diag");
+    return CSG_OK;
+}
+
+int csg_features(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, float *ctf2_accum,
+                 float *cover_accum, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!ctf2_accum || !cover_accum) return fail(CSG_EINVAL, "csg_features: outputs must be non-NULL");
+    if (poses->n == 0) return CSG_OK;
+    CSG_TRY(csg::launch_features(g, poses->rot, poses->defocus_A, poses->n, ctf2_accum, cover_accum,
+                                 (hipStream_t)stream),
+            "csg_features");
+    return CSG_OK;
+}
+
+int csg_threshold_alpha(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, float lambda,
+                        double *alpha_out, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!alpha_out) return fail(CSG_EINVAL, "csg_threshold_alpha: alpha_out is NULL");
+    const int R = (int)lrint((double)grid->r_max);
+    if (R < 1) return fail(CSG_EINVAL, "csg_threshold_alpha: r_max must round to at least 1");
+    // Shell counts: round(|k|) == R  <=>  R^2 - R + 1 <= |k|^2 <= R^2 + R
+    // (|k|^2 is an integer and |k| is never exactly R + 1/2).
+    const int64_t lo = (int64_t)R * R - R + 1, hi = (int64_t)R * R + R;
+    const int M = g.M, h = g.half;
+    int64_t px = 0, pv = 0;
+    for (int y = -h; y < h; ++y)
+        for (int x = -h; x < h; ++x) {
+            const int64_t r2 = (int64_t)x * x + (int64_t)y * y;
+            if (r2 >= lo && r2 <= hi) ++px;
+        }
+    for (int z = -h; z < h; ++z) {
+        const int64_t z2 = (int64_t)z * z;
+        if (z2 > hi) continue;
+        for (int y = -h; y < h; ++y) {
+            const int64_t yz = z2 + (int64_t)y * y;
+            if (yz > hi) continue;
+            for (int x = -h; x < h; ++x) {
+                const int64_t r2 = yz + (int64_t)x * x;
+                if (r2 >= lo && r2 <= hi) ++pv;
+            }
+        }
+    }
+    if (pv == 0) return fail(CSG_EINVAL, "csg_threshold_alpha: empty voxel shell");
+    const double ratio = (double)px / (double)pv;
+    CSG_TRY(csg::launch_alpha(g, poses->defocus_A, poses->n, R * R, ratio, lambda, alpha_out, (hipStream_t)stream),
+            "csg_threshold_alpha");
+    return CSG_OK;
+}
+
+int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D, float *D_avg, const float *zHz,
+                         int64_t k, float beta, float alpha, float eta, float *v_out, float *Dhat_out,
+                         double *stats_out, void *stream) {
+    if (nvox < 0) return fail(CSG_EINVAL, "csg_precond_sgd_step: nvox must be non-negative");
+    if (!v || !g || !v_out || !stats_out)
+        return fail(CSG_EINVAL, "csg_precond_sgd_step: v, g, v_out and stats_out must be non-NULL");
+    if (zHz && (!D || !D_avg)) return fail(CSG_EINVAL, "csg_precond_sgd_step: a probe sample needs D and D_avg");
+    if (zHz && k < 1) return fail(CSG_EINVAL, "csg_precond_sgd_step: iteration k=%lld must be >= 1", (long long)k);
+    if (v_out == g) return fail(CSG_EINVAL, "csg_precond_sgd_step: v_out must not alias g");
+    if (!(eta >= 0.0f)) return fail(CSG_EINVAL, "csg_precond_sgd_step: eta must be non-negative");
+    if (D && !(alpha >= 0.0f)) return fail(CSG_EINVAL, "csg_precond_sgd_step: alpha must be non-negative");
+    CSG_TRY(csg::launch_precond_step(nvox, (const float2 *)v, (const float2 *)g, D, D_avg, zHz, k, beta, alpha, eta,
+                                     (float2 *)v_out, Dhat_out, stats_out, (hipStream_t)stream),
+            "csg_precond_sgd_step");
+    return CSG_OK;
+}
+
+}  // extern "C"

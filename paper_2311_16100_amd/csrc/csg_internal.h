@@ -1,0 +1,46 @@
+// csg_internal.h -- host-side launchers of the kernels, called by the C ABI
+// layer (api.hip).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csg_device.h"
+
+namespace csg {
+
+// pixel-parallel kernels (pixel_kernels.hip)
+hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                          const float2 *subtract, float2 *out, double *loss, hipStream_t st);
+hipError_t launch_backproject_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                     const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st);
+hipError_t launch_gradient_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                                  const float2 *x, float scale, float2 *accum, double *loss, hipStream_t st);
+hipError_t launch_hvp_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
+                             float scale, float2 *accum, hipStream_t st);
+hipError_t launch_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
+                          float *accum, hipStream_t st);
+
+// voxel-parallel (owner computes) kernels (voxel_kernels.hip)
+hipError_t launch_backproject_owner(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                    const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st);
+hipError_t launch_features(const Geom &g, const float *rot, const float *defocus, int64_t n, float *ctf2,
+                           float *cover, hipStream_t st);
+
+// volume-wise kernels (volume_kernels.hip)
+hipError_t launch_scaled_copy(float2 *out, const float2 *in, float lam, int64_t nvox, double *norm2, hipStream_t st);
+hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_finish_loss(double *loss_out, const double *data, const double *norm2, float scale, float lam,
+                              hipStream_t st);
+hipError_t launch_rademacher(float *z, int64_t nvox, uint64_t seed, uint64_t probe, hipStream_t st);
+hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
+                                  hipStream_t st);
+hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, hipStream_t st);
+hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, double ratio, float lam,
+                        double *alpha_out, hipStream_t st);
+hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, float *D, float *D_avg,
+                               const float *zHz, int64_t k, float beta, float alpha, float eta, float2 *v_out,
+                               float *Dhat_out, double *stats, hipStream_t st);
+
+}  // namespace csg

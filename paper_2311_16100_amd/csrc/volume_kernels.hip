@@ -1,0 +1,212 @@
+// volume_kernels.hip -- streaming kernels over whole volumes: initialisation
+// of gradient / HVP outputs, Rademacher probes, Hutchinson accumulation and
+// the preconditioned SGD update of Algorithm 1.  All are HBM-bound
+// grid-stride loops in which consecutive lanes touch consecutive voxels, so
+// every wavefront access is fully coalesced.
+#include "csg_device.h"
+#include "csg_internal.h"
+
+namespace csg {
+
+static inline unsigned stream_blocks(int64_t units) {
+    int64_t b = (units + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;  // grid-stride beyond 32 blocks per CU
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// out = lam * in (complex), norm2 += sum |in|^2 (norm2 may be NULL).
+__global__ __launch_bounds__(kBlock) void scaled_copy_kernel(float2 *__restrict__ out, const float2 *__restrict__ in,
+                                                              float lam, int64_t nvox, double *norm2) {
+    __shared__ double red[16];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
+        const float2 v = in[k];
+        out[k] = make_float2(lam * v.x, lam * v.y);
+        s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    if (norm2) {
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) atomicAdd(norm2, t);
+    }
+}
+
+__global__ void fill_f64_kernel(double *p, int n, double v) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_f32_kernel(float *__restrict__ p, int64_t n, float v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
+
+// loss = scale * data + lam/2 * norm2 (all device scalars)
+__global__ void finish_loss_kernel(double *loss_out, const double *data, const double *norm2, float scale, float lam) {
+    if (threadIdx.x == 0) *loss_out = (double)scale * data[0] + 0.5 * (double)lam * norm2[0];
+}
+
+// Rademacher entries: thread t writes voxels 4t..4t+3, all inside one 128-bit
+// Philox block (k/128), using bits (k mod 128).
+__device__ __forceinline__ float4 rademacher4(uint64_t seed, uint64_t probe, int64_t k4) {
+    const int64_t k = k4 * 4;
+    const U4 r = philox4x32_10(U4{(uint32_t)(k >> 7), (uint32_t)probe, (uint32_t)(probe >> 32), kRademacherTag},
+                               (uint32_t)seed, (uint32_t)(seed >> 32));
+    const int bit = (int)(k & 127);
+    const uint32_t word = (bit < 32) ? r.x : (bit < 64) ? r.y : (bit < 96) ? r.z : r.w;
+    const uint32_t b = word >> (bit & 31);
+    return make_float4((b & 1u) ? -1.f : 1.f, (b & 2u) ? -1.f : 1.f, (b & 4u) ? -1.f : 1.f, (b & 8u) ? -1.f : 1.f);
+}
+
+__global__ __launch_bounds__(kBlock) void rademacher_kernel(float *__restrict__ z, int64_t nvox, uint64_t seed,
+                                                             uint64_t probe) {
+    const int64_t n4 = (nvox + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n4; t += stride) {
+        const float4 v = rademacher4(seed, probe, t);
+        const int64_t k = t * 4;
+        if (k + 3 < nvox) {
+            *reinterpret_cast<float4 *>(z + k) = v;
+        } else {
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+            for (int e = 0; e < 4 && k + e < nvox; ++e) z[k + e] = vv[e];
+        }
+    }
+}
+
+// Complex probe pair z = z_{pa} + i z_{pb} (z_{pb} = 0 when has_b == 0).
+__global__ __launch_bounds__(kBlock) void rademacher_pair_kernel(float2 *__restrict__ z, int64_t nvox, uint64_t seed,
+                                                                  uint64_t pa, uint64_t pb, int has_b) {
+    const int64_t n4 = (nvox + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n4; t += stride) {
+        const float4 ra = rademacher4(seed, pa, t);
+        const float4 rb = has_b ? rademacher4(seed, pb, t) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float va[4] = {ra.x, ra.y, ra.z, ra.w}, vb[4] = {rb.x, rb.y, rb.z, rb.w};
+        const int64_t k = t * 4;
+        for (int e = 0; e < 4; ++e)
+            if (k + e < nvox) z[k + e] = make_float2(va[e], vb[e]);
+    }
+}
+
+// diag += w * (Re z Re hz + Im z Im hz)
+__global__ __launch_bounds__(kBlock) void zhz_accum_kernel(float *__restrict__ diag, const float2 *__restrict__ z,
+                                                            const float2 *__restrict__ hz, int64_t nvox, float w) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
+        const float2 a = z[k], b = hz[k];
+        diag[k] = fmaf(w, fmaf(a.x, b.x, a.y * b.y), diag[k]);
+    }
+}
+
+// Algorithm 1: running mean / exponential average of the diagonal,
+// thresholding and the preconditioned step, with the two reductions the line
+// search needs.
+__global__ __launch_bounds__(kBlock) void precond_step_kernel(int64_t nvox, const float2 *__restrict__ v,
+                                                               const float2 *__restrict__ g, float *D, float *D_avg,
+                                                               const float *__restrict__ zHz, float wk_old, float wk_new,
+                                                               float beta, float alpha, float eta, float2 *v_out,
+                                                               float *Dhat_out, double *stats) {
+    __shared__ double red[16];
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
+        float dh = 1.0f;
+        if (D) {
+            float d = D[k];
+            if (zHz) {
+                const float da = fmaf(wk_old, D_avg[k], wk_new * zHz[k]);
+                D_avg[k] = da;
+                d = fmaf(beta, d, (1.0f - beta) * da);
+                D[k] = d;
+            }
+            dh = fmaxf(fabsf(d), alpha);
+        }
+        if (Dhat_out) Dhat_out[k] = dh;
+        const float2 gk = g[k], vk = v[k];
+        const float inv = 1.0f / dh;
+        const float2 o = make_float2(vk.x - eta * gk.x * inv, vk.y - eta * gk.y * inv);
+        v_out[k] = o;
+        s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh;
+        s1 += (double)o.x * o.x + (double)o.y * o.y;
+    }
+    const double t0 = block_sum(s0, red);
+    const double t1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&stats[0], t0);
+        atomicAdd(&stats[1], t1);
+    }
+}
+
+// sum_i C_i(R)^2 over the defocus values of all N images (one block,
+// fixed-order reduction), then alpha = ratio * sum + lambda.
+__global__ __launch_bounds__(kBlock) void ctf2_sum_kernel(Geom g, const float *__restrict__ defocus, int64_t n, int k2,
+                                                           double ratio, float lam, double *alpha_out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const float c = ctf_value(g, g.ctf_a * (double)defocus[i], k2);
+        s += (double)c * c;
+    }
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) *alpha_out = ratio * t + (double)lam;
+}
+
+hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, double ratio, float lam,
+                        double *alpha_out, hipStream_t st) {
+    hipLaunchKernelGGL(ctf2_sum_kernel, dim3(1), dim3(kBlock), 0, st, g, defocus, n, k2, ratio, lam, alpha_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scaled_copy(float2 *out, const float2 *in, float lam, int64_t nvox, double *norm2, hipStream_t st) {
+    hipLaunchKernelGGL(scaled_copy_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, out, in, lam, nvox, norm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(stream_blocks(n)), dim3(kBlock), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_loss(double *loss_out, const double *data, const double *norm2, float scale, float lam,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(finish_loss_kernel, dim3(1), dim3(64), 0, st, loss_out, data, norm2, scale, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_rademacher(float *z, int64_t nvox, uint64_t seed, uint64_t probe, hipStream_t st) {
+    hipLaunchKernelGGL(rademacher_kernel, dim3(stream_blocks((nvox + 3) / 4)), dim3(kBlock), 0, st, z, nvox, seed,
+                       probe);
+    return hipGetLastError();
+}
+
+hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(rademacher_pair_kernel, dim3(stream_blocks((nvox + 3) / 4)), dim3(kBlock), 0, st, z, nvox,
+                       seed, pa, pb, has_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, hipStream_t st) {
+    hipLaunchKernelGGL(zhz_accum_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, diag, z, hz, nvox, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, float *D, float *D_avg,
+                               const float *zHz, int64_t k, float beta, float alpha, float eta, float2 *v_out,
+                               float *Dhat_out, double *stats, hipStream_t st) {
+    const float wk_old = k > 0 ? (float)((double)(k - 1) / (double)k) : 0.f;
+    const float wk_new = k > 0 ? (float)(1.0 / (double)k) : 0.f;
+    hipError_t e = launch_fill_f64(stats, 2, 0.0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(precond_step_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, nvox, v, g, D, D_avg, zHz,
+                       wk_old, wk_new, beta, alpha, eta, v_out, Dhat_out, stats);
+    return hipGetLastError();
+}
+
+}  // namespace csg

@@ -1,0 +1,103 @@
+"""Algorithm 1 of the paper (Sec. 3.4): SGD preconditioned by the estimated,
+thresholded Hessian diagonal, with the stochastic Armijo line search of
+eq. (stochastic armijo).
+
+This module is a host-side loop over the C-ABI calls of libcryosgd; every
+arithmetic step (gradient, Hessian-vector probes, the running mean and
+exponential average of the diagonal, thresholding, the step, the line-search
+losses) runs in the library's kernels.  The only host work is the line
+search's decision, which needs one read-back of four device scalars per trial.
+
+Arms (same loop, same step-size rule):
+  "hutchinson"  D estimated on the fly from Rademacher probes (Algorithm 1)
+  "fixed"       a given diagonal D held fixed (precomputed / learned / exact)
+  "plain"       D_hat = 1 (no preconditioner)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from . import binding as B
+
+
+@dataclass
+class Alg1Config:
+    beta: float = 0.9        # exponential-average weight of eq. (exp avg update)
+    c: float = 0.1           # sufficient-decrease constant of eq. (stochastic armijo)
+    eta0: float = 1.0        # initial step size
+    n_probe: int = 2         # Rademacher probes per iteration (one complex product)
+    max_halvings: int = 30
+    probe_seed: int = 4
+    deterministic: bool = False
+
+
+@dataclass
+class Alg1State:
+    v: torch.Tensor                 # complex64 [M,M,M]
+    D: torch.Tensor | None          # float32 [M,M,M] (None: plain SGD)
+    D_avg: torch.Tensor | None
+    eta: float
+    k: int = 0
+    halvings: list = field(default_factory=list)
+
+
+class Alg1Runner:
+    """Owns the device buffers of one run; `iteration` performs one k."""
+
+    def __init__(self, grid: B.Grid, optics: B.Optics, arm: str, scale: float, lam: float, alpha: float,
+                 cfg: Alg1Config, v0: torch.Tensor, D_fixed: torch.Tensor | None = None, batch: int = 0):
+        assert arm in ("hutchinson", "fixed", "plain")
+        self.grid, self.optics, self.arm = grid, optics, arm
+        self.scale, self.lam, self.alpha, self.cfg = float(scale), float(lam), float(alpha), cfg
+        M = grid.M
+        dev = v0.device
+        if arm == "hutchinson":
+            D = torch.ones((M, M, M), dtype=torch.float32, device=dev)
+            Da = torch.zeros((M, M, M), dtype=torch.float32, device=dev)
+        elif arm == "fixed":
+            D, Da = D_fixed.contiguous(), None
+        else:
+            D, Da = None, None
+        self.state = Alg1State(v=v0.clone(), D=D, D_avg=Da, eta=cfg.eta0)
+        self.g = torch.empty_like(v0)
+        self.v_new = torch.empty_like(v0)
+        self.zHz = torch.empty((M, M, M), dtype=torch.float32, device=dev) if arm == "hutchinson" else None
+        # scalars: [0] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data term of f(v')
+        self.sc = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
+                                         else B.CSG_WS_GRADIENT, dev)
+        self.ws_hutch = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev) if arm == "hutchinson" else None
+
+    def iteration(self, rot_I, df_I, x_I) -> int:
+        st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
+        st.k += 1
+        if self.arm == "hutchinson":
+            # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
+            B.hutchinson_diag(g, o, rot_I, df_I, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
+                              probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
+        B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g, loss_out=self.sc[0:1],
+                   deterministic=cfg.deterministic, workspace=self.ws_grad)
+        eta = st.eta
+        halvings = 0
+        first = True
+        while True:
+            B.precond_sgd_step(st.v, self.g, st.D, st.D_avg, self.zHz if first else None, st.k, cfg.beta,
+                               self.alpha if st.D is not None else 0.0, eta, v_out=self.v_new,
+                               stats_out=self.sc[1:3])
+            first = False
+            self.sc[3:4].zero_()
+            B.project(g, o, rot_I, df_I, self.v_new, subtract=x_I, out=None, loss=self.sc[3:4], want_out=False)
+            f0, gn, vn2, l1 = self.sc.tolist()
+            f1 = self.scale * l1 + 0.5 * self.lam * vn2
+            if f1 <= f0 - cfg.c * eta * gn:
+                break
+            eta *= 0.5
+            halvings += 1
+            if halvings > cfg.max_halvings:
+                raise RuntimeError("Armijo line search did not terminate after %d halvings" % halvings)
+        st.v, self.v_new = self.v_new, st.v
+        st.eta = eta
+        st.halvings.append(halvings)
+        return halvings

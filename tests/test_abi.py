@@ -1,0 +1,92 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/cryosgd.h declares, and rejects invalid arguments on the host before
+any GPU work is enqueued (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cryosgd.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(csg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2311_16100_amd import binding
+    binding.lib()
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("csg_project", "csg_backproject", "csg_hvp", "csg_hutchinson_diag", "csg_precond_sgd_step",
+                     "csg_gradient", "csg_workspace_bytes", "csg_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(b):
+    lib = ctypes.CDLL(b.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # and the binding knows every one of them
+    assert set(declared_functions()) <= set(b.EXPORTS)
+
+
+def test_workspace_sizes(b):
+    g = b.Grid(256)
+    vol = 256 ** 3 * 8
+    assert b.workspace_bytes(g, 1024, b.CSG_WS_HUTCHINSON) >= 2 * vol
+    assert b.workspace_bytes(g, 1024, b.CSG_WS_GRADIENT_DETERMINISTIC) >= 1024 * 256 * 256 * 8
+    assert b.workspace_bytes(g, 1024, b.CSG_WS_GRADIENT) > 0
+    assert b.workspace_bytes(b.Grid(7), 1, b.CSG_WS_HUTCHINSON) == 0
+
+
+def _call_project(b, grid, optics, n=1):
+    L = b.lib()
+    p = b._Poses(n, None, None)
+    return L.csg_project(ctypes.byref(grid), ctypes.byref(optics), ctypes.byref(p), None, None, None, None, None)
+
+
+@pytest.mark.parametrize("M,rmax,interp", [(7, 2.0, 1), (2, 0.0, 1), (2048, 10.0, 1), (32, 16.0, 1),
+                                           (32, -1.0, 1), (32, 10.0, 2)])
+def test_invalid_grid_rejected(b, M, rmax, interp):
+    rc = _call_project(b, b._Grid(M, rmax, interp), b.Optics().c())
+    assert rc == -1
+    assert b.lib().csg_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("kv", 0.0), ("pixel_A", -1.0), ("amp_contrast", 1.0), ("cs_mm", -2.0)])
+def test_invalid_optics_rejected(b, field, value):
+    o = b.Optics().c()
+    setattr(o, field, value)
+    assert _call_project(b, b.Grid(32).c(), o) == -1
+
+
+def test_null_pointers_rejected(b):
+    # n > 0 with NULL rotations
+    assert _call_project(b, b.Grid(32).c(), b.Optics().c(), n=3) == -1
+    assert b"non-NULL" in b.lib().csg_last_error()
+    L = b.lib()
+    stats = None
+    assert L.csg_precond_sgd_step(10, None, None, None, None, None, 1, 0.9, 1.0, 1.0, None, None, stats, None) == -1
+    assert L.csg_rademacher(-1, 0, 0, None, None) == -1
+    # a zero-length request is a no-op and succeeds without touching the GPU
+    assert L.csg_rademacher(0, 0, 0, None, None) == 0
+    p = b._Poses(0, None, None)
+    g, o = b.Grid(16).c(), b.Optics().c()
+    assert L.csg_project(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, None, None, None, None) == 0
+
+
+def test_bad_ctf_power_rejected(b):
+    L = b.lib()
+    g, o = b.Grid(16).c(), b.Optics().c()
+    p = b._Poses(0, None, None)
+    assert L.csg_backproject(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, 3, 1.0, None, 0, None, 0,
+                             None) == -1

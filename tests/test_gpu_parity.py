@@ -1,0 +1,279 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on the
+same seeded float32 inputs.
+
+Tolerances (relative L2 over the whole output): project 1e-5; backproject,
+gradient, HVP, Hutchinson and the exact diagonal 1e-4; integer outputs
+(Rademacher probes, coverage counts) bit-exact; the deterministic adjoint
+bitwise reproducible.  Sizes span several pixel chunks and voxel bricks with
+ragged tails (M = 36: 1296 pixels per image = 5 chunks of 256 + 16; 4.5
+bricks of 8 per axis), two image-cull rounds of 256 in the voxel kernels
+(n = 300), and the benchmark's full 256^3 / 1024-image configuration.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128).reshape(-1)
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2311_16100_amd import binding
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    binding.lib()
+    return binding
+
+
+def make_case(M, n, seed, interp=1, ctf=True, blob=False, rmax=None, poses="uniform"):
+    grid_o = oracle.Grid(M, r_max=rmax, interp=interp)
+    opt_o = oracle.Optics() if ctf else oracle.NO_CTF
+    rot = synth.uniform_rotations(n, seed) if poses == "uniform" else synth.vmf_rotations(n, 10.0, seed)
+    df = synth.defocus_values(n, 0.5, 4.0, seed)
+    if blob:
+        vol = synth.blob_volume(M, 12, seed)
+    else:
+        vol = synth.random_complex((M, M, M), seed, stream=11)
+    img = synth.random_complex((n, M, M), seed, stream=12)
+    return grid_o, opt_o, oracle.Poses(rot, df), vol, img
+
+
+def to_dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def gpu_desc(b, grid_o, opt_o):
+    g = b.Grid(grid_o.M, r_max=grid_o.rmax, interp=grid_o.interp)
+    o = b.Optics() if opt_o.ctf_on else b.NO_CTF
+    return g, o
+
+
+CASES = [
+    dict(M=36, n=37, seed=1, interp=1, ctf=True),
+    dict(M=36, n=37, seed=2, interp=0, ctf=True),
+    dict(M=32, n=20, seed=3, interp=1, ctf=False, blob=True),
+    dict(M=16, n=300, seed=4, interp=1, ctf=True),
+    dict(M=8, n=5, seed=5, interp=1, ctf=True),
+    dict(M=4, n=3, seed=6, interp=1, ctf=True),
+    dict(M=32, n=24, seed=7, interp=1, ctf=True, poses="vmf"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+def test_project_parity(b, case):
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    out = b.project(g, o, rot, df, v).cpu().numpy()
+    want = oracle.project(grid_o, opt_o, P, vol)
+    assert rel(out, want) <= 1e-5
+    # residual form with the loss accumulated in double
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    res = b.project(g, o, rot, df, v, subtract=x, loss=loss).cpu().numpy()
+    mask = np.abs(want) > 0
+    want_r = np.where(mask | (np.abs(res) > 0), want - img, 0)
+    # pixels outside the disk are zero in both
+    disk = _disk(grid_o)
+    want_r = (want - img) * disk[None]
+    assert rel(res, want_r) <= 1e-5
+    want_loss = 0.5 * np.sum(np.abs(want_r) ** 2)
+    assert loss.item() == pytest.approx(want_loss, rel=1e-5)
+
+
+def _disk(grid_o):
+    M = grid_o.M
+    ax = np.arange(M) - M // 2
+    return (ax[:, None] ** 2 + ax[None, :] ** 2) <= grid_o.rmax ** 2
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+@pytest.mark.parametrize("power", [0, 1, 2])
+def test_backproject_parity(b, case, power):
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, x, acc0 = to_dev(P.rot, P.defocus, img, vol)
+    want = oracle.backproject(grid_o, opt_o, P, img, ctf_power=power, scale=1.7, accum=vol)
+    for det in (False, True):
+        acc = acc0.clone()
+        b.backproject(g, o, rot, df, x, ctf_power=power, scale=1.7, accum=acc, deterministic=det)
+        assert rel(acc.cpu().numpy(), want) <= 1e-4, det
+
+
+def test_deterministic_backproject_is_bitwise_reproducible(b):
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=300, seed=9)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, x = to_dev(P.rot, P.defocus, img)
+    outs = []
+    for _ in range(3):
+        acc = torch.zeros((36, 36, 36), dtype=torch.complex64, device="cuda")
+        b.backproject(g, o, rot, df, x, ctf_power=1, accum=acc, deterministic=True)
+        outs.append(acc.cpu().numpy())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
+    acc = torch.zeros((36, 36, 36), dtype=torch.complex64, device="cuda")
+    b.backproject(g, o, rot, df, x, ctf_power=1, accum=acc, deterministic=False)
+    assert rel(acc.cpu().numpy(), outs[0]) <= 1e-5
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+def test_gradient_and_loss_parity(b, case):
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    scale, lam = 3.5, 0.2
+    disk = _disk(grid_o)
+    img_d = img * disk[None]
+    want_g = oracle.gradient(grid_o, opt_o, P, vol, img_d, scale, lam)
+    want_f = oracle.loss(grid_o, opt_o, P, vol, img_d, scale, lam)
+    for det in (False, True):
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gr = b.gradient(g, o, rot, df, v, x, scale, lam, loss_out=loss, deterministic=det)
+        assert rel(gr.cpu().numpy(), want_g) <= 1e-4, det
+        assert loss.item() == pytest.approx(want_f, rel=1e-5), det
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+def test_hvp_parity(b, case):
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, z = to_dev(P.rot, P.defocus, vol)
+    want = oracle.hvp(grid_o, opt_o, P, vol, 2.0, 0.3)
+    for det in (False, True):
+        hz = b.hvp(g, o, rot, df, z, 2.0, 0.3, deterministic=det)
+        assert rel(hz.cpu().numpy(), want) <= 1e-4, det
+
+
+def test_rademacher_bit_exact(b):
+    for nvox, seed, probe in ((36 ** 3, 5, 0), (1000, 2 ** 40 + 7, 3), (130, 1, 2 ** 33 + 1), (5, 9, 9)):
+        z = b.rademacher(nvox, seed, probe).cpu().numpy()
+        assert np.array_equal(z, oracle.rademacher(seed, probe, nvox).astype(np.float32))
+
+
+@pytest.mark.parametrize("n_probe", [1, 4, 5])
+def test_hutchinson_parity(b, n_probe):
+    grid_o, opt_o, P, vol, img = make_case(M=16, n=40, seed=21)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df = to_dev(P.rot, P.defocus)
+    got = b.hutchinson_diag(g, o, rot, df, n_probe, seed=77, scale=2.5, lam=0.1, probe0=3).cpu().numpy()
+    want = oracle.hutchinson_diag(grid_o, opt_o, P, n_probe, 77, 2.5, 0.1, probe0=3)
+    assert rel(got, want) <= 1e-4
+
+
+@pytest.mark.parametrize("interp", [0, 1])
+def test_exact_diag_and_features_parity(b, interp):
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=37, seed=31, interp=interp)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df = to_dev(P.rot, P.defocus)
+    d = b.exact_diag(g, o, rot, df, 1.5, 0.25).cpu().numpy()
+    assert rel(d, oracle.exact_diag(grid_o, opt_o, P, 1.5, 0.25)) <= 1e-4
+    f2, f3 = b.features(g, o, rot, df)
+    w2, w3 = oracle.features(grid_o, opt_o, P)
+    assert rel(f2.cpu().numpy(), w2) <= 1e-4
+    assert np.array_equal(f3.cpu().numpy(), w3.astype(np.float32))
+
+
+def test_precond_step_parity(b):
+    n = 36 ** 3 + 5
+    g0 = np.random.default_rng(3)
+    v = synth.random_complex(n, 1).astype(np.complex64)
+    gr = synth.random_complex(n, 2).astype(np.complex64)
+    D = (g0.uniform(-1, 3, n)).astype(np.float32)
+    Da = (g0.uniform(0, 2, n)).astype(np.float32)
+    zHz = (g0.uniform(-1, 4, n)).astype(np.float32)
+    k, beta, alpha, eta = 7, 0.9, 0.3, 0.7
+    vd, gd, Dd, Dad, zd = to_dev(v, gr, D, Da, zHz)
+    Dh = torch.empty(n, dtype=torch.float32, device="cuda")
+    vo, st = b.precond_sgd_step(vd, gd, Dd, Dad, zd, k, beta, alpha, eta, Dhat_out=Dh)
+    wD, wDa, wDh = oracle.precond_update(D.astype(np.float64), Da.astype(np.float64), zHz.astype(np.float64),
+                                         k, beta, alpha)
+    wv, wgn = oracle.precond_step(v, gr, wDh, eta)
+    assert np.allclose(Dd.cpu().numpy(), wD, rtol=1e-6, atol=1e-6)
+    assert np.allclose(Dad.cpu().numpy(), wDa, rtol=1e-6, atol=1e-6)
+    assert np.allclose(Dh.cpu().numpy(), wDh, rtol=1e-6, atol=1e-6)
+    assert rel(vo.cpu().numpy(), wv) <= 1e-6
+    s = st.cpu().numpy()
+    assert s[0] == pytest.approx(wgn, rel=1e-6)
+    assert s[1] == pytest.approx(np.sum(np.abs(wv) ** 2), rel=1e-6)
+    # plain SGD (D = NULL) and a fixed preconditioner (no probe sample)
+    vo2, st2 = b.precond_sgd_step(vd, gd, None, None, None, 0, beta, alpha, eta)
+    wv2, wgn2 = oracle.precond_step(v, gr, None, eta)
+    assert rel(vo2.cpu().numpy(), wv2) <= 1e-6 and st2[0].item() == pytest.approx(wgn2, rel=1e-6)
+
+
+def test_empty_and_degenerate_inputs(b):
+    M = 16
+    g, o = b.Grid(M), b.Optics()
+    rot = torch.zeros((0, 3, 3), device="cuda")
+    df = torch.zeros(0, device="cuda")
+    v = torch.ones((M, M, M), dtype=torch.complex64, device="cuda")
+    out = b.project(g, o, rot, df, v)
+    assert out.shape == (0, M, M)
+    acc = torch.zeros_like(v)
+    b.backproject(g, o, rot, df, torch.zeros((0, M, M), dtype=torch.complex64, device="cuda"), accum=acc)
+    assert torch.count_nonzero(acc).item() == 0
+    # lambda z alone when the batch is empty
+    hz = b.hvp(g, o, rot, df, v, 1.0, 0.5)
+    assert torch.allclose(hz, 0.5 * v)
+    # r_max = 0: only the DC pixel is used, C(0) = -A
+    P = oracle.Poses(synth.uniform_rotations(3, 1), synth.defocus_values(3, 1, 2, 1))
+    rd, dd = to_dev(P.rot, P.defocus)
+    g0 = b.Grid(M, r_max=0.0)
+    out = b.project(g0, o, rd, dd, v).cpu().numpy()
+    assert np.count_nonzero(out) == 3
+    assert np.allclose(out[:, M // 2, M // 2], -0.1, atol=1e-7)
+    # invalid input is rejected, not run
+    with pytest.raises(b.CsgError):
+        b.project(b.Grid(M, r_max=float(M)), o, rd, dd, v)
+    with pytest.raises(b.CsgError):
+        b.project(g, o, rd, dd, torch.ones((M, M, M + 2), dtype=torch.complex64, device="cuda"))
+
+
+# ---------------------------------------------------------------------------
+# Full size: 256^3 volume, a batch of 1024 images of 256 x 256 -- the
+# configuration the benchmark times, in the same launch configuration.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def full(b):
+    M, n = 256, 1024
+    grid_o = oracle.Grid(M)
+    P = oracle.Poses(synth.uniform_rotations(n, 3000), synth.defocus_values(n, 1.0, 3.0, 3000))
+    vol = synth.blob_volume(M, 1000, 3000)
+    rot, df, v = to_dev(P.rot, P.defocus, vol)
+    return grid_o, P, vol, rot, df, v
+
+
+def test_full_size_project_sampled(b, full):
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    out = b.project(g, o, rot, df, v)
+    torch.cuda.synchronize()
+    idx = [0, 1, 511, 1023]
+    want = oracle.project(grid_o, oracle.Optics(), P.subset(idx), vol)
+    got = out[idx].cpu().numpy()
+    assert rel(got, want) <= 1e-5
+
+
+def test_full_size_backproject_and_adjoint(b, full):
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    n = P.n
+    x = torch.from_numpy(synth.random_complex((n, 256, 256), 5, stream=13)).cuda()
+    acc = b.backproject(g, o, rot, df, x, ctf_power=1)
+    # sampled against the oracle: the subset {0..31} backprojected alone
+    sub = list(range(32))
+    acc_sub = b.backproject(g, o, rot[sub].contiguous(), df[sub].contiguous(), x[sub].contiguous(), ctf_power=1)
+    want_sub = oracle.backproject(grid_o, oracle.Optics(), P.subset(sub), x[sub].cpu().numpy(), ctf_power=1)
+    assert rel(acc_sub.cpu().numpy(), want_sub) <= 1e-4
+    # adjoint identity of the full batch, inner products in double
+    Av = b.project(g, o, rot, df, v)
+    lhs = torch.vdot(Av.reshape(-1).to(torch.complex128), x.reshape(-1).to(torch.complex128))
+    rhs = torch.vdot(v.reshape(-1).to(torch.complex128), acc.reshape(-1).to(torch.complex128))
+    assert abs((lhs - rhs).item()) <= 1e-5 * abs(lhs.item())
