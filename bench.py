@@ -126,14 +126,15 @@ def main():
         timed("precond_step", lambda: B.precond_sgd_step(st.v, run.g, st.D, st.D_avg, run.zHz, st.k, cfg.beta,
                                                          alpha, st.eta, v_out=run.v_new, stats_out=run.sc[1:3]))
         timed("armijo_project", lambda: B.project(g_, o_, rot_b, df_b, run.v_new, subtract=x_b, out=None,
-                                                  loss=run.sc[3:4], want_out=False))
+                                                  loss=run.sc[3:4], want_out=False, workspace=run.ws_proj))
     # plain forward + adjoint of the batch
     y = torch.empty_like(x_b)
     acc = torch.zeros_like(v_true)
+    ws_bp = B.alloc_workspace(grid, Bsz, B.CSG_WS_BACKPROJECT, dev)
     for _ in range(args.steps):
-        timed("project", lambda: B.project(grid, optics, rot_b, df_b, v_true, out=y))
+        timed("project", lambda: B.project(grid, optics, rot_b, df_b, v_true, out=y, workspace=run.ws_proj))
         timed("backproject", lambda: B.backproject(grid, optics, rot_b, df_b, x_b, ctf_power=1, accum=acc,
-                                                   deterministic=args.deterministic))
+                                                   deterministic=args.deterministic, workspace=ws_bp))
     torch.cuda.synchronize()
     ms = {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in calls.items()}
     fwd_adj = Bsz / ((ms["project"] + ms["backproject"]) * 1e-3)

@@ -81,10 +81,11 @@ typedef struct csg_poses {
  *   out      device complex [n][M][M] or NULL (then loss_accum is required)
  *   loss_accum device double scalar or NULL: += 1/2 sum_disk |C P v - x|^2
  *            (x = 0 when subtract is NULL).  Not zeroed by the call.
+ *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_PROJECT) bytes.
  * out and vol must not overlap. */
 int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
                 const float *vol, const float *subtract, float *out, double *loss_accum,
-                void *stream);
+                void *workspace, size_t workspace_bytes, void *stream);
 
 /* Adjoint / backprojection, the operator P_i^* C_i that appears in the M step
  * (eq. (em v)) and in b = sum_i P_i^* x_i (eq. (lin sys)):
@@ -122,8 +123,7 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
  * independent of v, so a complex z carries two real products:
  *   hz_out = scale * sum_i P_i^T C_i^2 P_i z + lambda z
  *   z, hz_out device complex [M^3] (hz_out overwritten, must not alias z).
- *   deterministic, workspace: as in csg_gradient (no workspace is needed
- *             when deterministic = 0). */
+ *   deterministic, workspace: as in csg_gradient. */
 int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
             const float *z, float scale, float lambda, float *hz_out, int32_t deterministic,
             void *workspace, size_t workspace_bytes, void *stream);
@@ -185,6 +185,7 @@ int csg_features(const csg_grid *grid, const csg_optics *optics, const csg_poses
                  float *ctf2_accum, float *cover_accum, void *stream);
 
 /* Workspace sizes (bytes) for a batch of n images:
+ *   CSG_WS_PROJECT                 csg_project
  *   CSG_WS_BACKPROJECT             csg_backproject (either mode)
  *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: two complex volumes
  *   CSG_WS_GRADIENT                csg_gradient / csg_hvp, deterministic = 0
@@ -195,6 +196,7 @@ int csg_features(const csg_grid *grid, const csg_optics *optics, const csg_poses
 #define CSG_WS_HUTCHINSON 1
 #define CSG_WS_GRADIENT 2
 #define CSG_WS_GRADIENT_DETERMINISTIC 3
+#define CSG_WS_PROJECT 4
 size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
 
 /* Message for the last nonzero return on the calling thread. */

@@ -24,6 +24,7 @@ CSG_WS_BACKPROJECT = 0
 CSG_WS_HUTCHINSON = 1
 CSG_WS_GRADIENT = 2
 CSG_WS_GRADIENT_DETERMINISTIC = 3
+CSG_WS_PROJECT = 4
 
 
 class CsgError(RuntimeError):
@@ -44,7 +45,7 @@ class _Poses(ctypes.Structure):
 
 
 EXPORTS = {
-    "csg_project": [ctypes.c_void_p] * 7 + [ctypes.c_void_p],
+    "csg_project": [ctypes.c_void_p] * 7 + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "csg_backproject": [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "csg_gradient": [ctypes.c_void_p] * 5 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
@@ -175,17 +176,20 @@ def _ws(ws):
 # Entry points (same names as the C ABI without the csg_ prefix)
 # ---------------------------------------------------------------------------
 def project(grid: Grid, optics: Optics, rot, defocus, vol, subtract=None, out=None, loss=None,
-            want_out: bool = True, stream=None):
+            want_out: bool = True, workspace=None, stream=None):
     """C P v (- subtract) for each image; returns `out` (allocated if None)."""
     M = grid.M
     p = _poses(rot, defocus)
     if want_out and out is None:
         out = torch.empty((p.n, M, M), dtype=torch.complex64, device=vol.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_PROJECT, vol.device)
     g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
     _check(lib().csg_project(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(vol, (M, M, M), "vol"),
                              None if subtract is None else _cplx(subtract, (p.n, M, M), "subtract"),
                              None if out is None else _cplx(out, (p.n, M, M), "out"),
-                             None if loss is None else _ptr(loss), _stream(stream)), "csg_project")
+                             None if loss is None else _ptr(loss), wp, wn, _stream(stream)), "csg_project")
     return out
 
 
@@ -196,6 +200,8 @@ def backproject(grid: Grid, optics: Optics, rot, defocus, img, ctf_power: int = 
     p = _poses(rot, defocus)
     if accum is None:
         accum = torch.zeros((M, M, M), dtype=torch.complex64, device=img.device)
+    if workspace is None and not deterministic:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_BACKPROJECT, img.device)
     g, o = grid.c(), optics.c()
     wp, wn = _ws(workspace)
     _check(lib().csg_backproject(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
@@ -232,8 +238,9 @@ def hvp(grid: Grid, optics: Optics, rot, defocus, z, scale: float, lam: float, h
     p = _poses(rot, defocus)
     if hz_out is None:
         hz_out = torch.empty((M, M, M), dtype=torch.complex64, device=z.device)
-    if deterministic and workspace is None:
-        workspace = alloc_workspace(grid, p.n, CSG_WS_GRADIENT_DETERMINISTIC, z.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_GRADIENT_DETERMINISTIC if deterministic else CSG_WS_GRADIENT,
+                                    z.device)
     g, o = grid.c(), optics.c()
     wp, wn = _ws(workspace)
     _check(lib().csg_hvp(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(z, (M, M, M), "z"), float(scale),

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcryosgd.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "pixel_kernels.hip", "voxel_kernels.hip", "volume_kernels.hip", "mlp_kernels.hip"]
+SOURCES = ["api.hip", "pixel_kernels.hip", "brick_kernels.hip", "voxel_kernels.hip", "volume_kernels.hip",
+           "mlp_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -105,17 +105,20 @@ size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
     if (!grid || grid->M < 4 || grid->M > 1024 || (grid->M & 1) || n < 0) return 0;
     const int M = grid->M;
     const size_t vol = (size_t)M * M * M * 8u;
+    const size_t bricks = csg::brick_workspace_bytes(M, n);
     switch (which) {
-        case CSG_WS_BACKPROJECT: return 0;
-        case CSG_WS_GRADIENT: return kScalarBytes;
+        case CSG_WS_PROJECT: return bricks;
+        case CSG_WS_BACKPROJECT: return bricks;
+        case CSG_WS_GRADIENT: return kScalarBytes + bricks;
         case CSG_WS_GRADIENT_DETERMINISTIC: return kScalarBytes + image_bytes(M, n);
-        case CSG_WS_HUTCHINSON: return kScalarBytes + 2 * vol;
+        case CSG_WS_HUTCHINSON: return kScalarBytes + 2 * vol + bricks;
         default: return 0;
     }
 }
 
 int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *vol,
-                const float *subtract, float *out, double *loss_accum, void *stream) {
+                const float *subtract, float *out, double *loss_accum, void *workspace, size_t workspace_bytes,
+                void *stream) {
     csg::Geom g;
     int rc = make_geom(grid, optics, &g);
     if (rc) return rc;
@@ -123,8 +126,12 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
     if (poses->n == 0) return CSG_OK;
     if (!vol) return fail(CSG_EINVAL, "csg_project: vol is NULL");
     if (!out && !loss_accum) return fail(CSG_EINVAL, "csg_project: need out or loss_accum");
-    CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
-                                (const float2 *)subtract, (float2 *)out, loss_accum, (hipStream_t)stream),
+    if (out && out == vol) return fail(CSG_EINVAL, "csg_project: out must not alias vol");
+    const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_PROJECT);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_project"))) return rc;
+    CSG_TRY(csg::launch_brick_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                      (const float2 *)subtract, (float2 *)out, loss_accum, workspace,
+                                      (hipStream_t)stream),
             "csg_project");
     return CSG_OK;
 }
@@ -132,8 +139,6 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
 int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *img,
                     int32_t ctf_power, float scale, float *vol_accum, int32_t deterministic, void *workspace,
                     size_t workspace_bytes, void *stream) {
-    (void)workspace;
-    (void)workspace_bytes;
     csg::Geom g;
     int rc = make_geom(grid, optics, &g);
     if (rc) return rc;
@@ -142,14 +147,17 @@ int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_po
     if (poses->n == 0) return CSG_OK;
     if (!img || !vol_accum) return fail(CSG_EINVAL, "csg_backproject: img and vol_accum must be non-NULL");
     hipStream_t st = (hipStream_t)stream;
-    if (deterministic)
+    if (deterministic) {
         CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
                                               ctf_power, scale, (float2 *)vol_accum, st),
                 "csg_backproject");
-    else
-        CSG_TRY(csg::launch_backproject_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
-                                               ctf_power, scale, (float2 *)vol_accum, st),
+    } else {
+        const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT);
+        if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_backproject"))) return rc;
+        CSG_TRY(csg::launch_brick_backproject(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
+                                              ctf_power, scale, (float2 *)vol_accum, workspace, st),
                 "csg_backproject");
+    }
     return CSG_OK;
 }
 
@@ -172,8 +180,9 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
     CSG_TRY(csg::launch_scaled_copy((float2 *)grad_out, (const float2 *)vol, lambda, nv, sc + 1, st), "csg_gradient");
     if (poses->n > 0) {
         if (!deterministic) {
-            CSG_TRY(csg::launch_gradient_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
-                                                (const float2 *)x, scale, (float2 *)grad_out, sc, st),
+            CSG_TRY(csg::launch_brick_gradient(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                               (const float2 *)x, scale, (float2 *)grad_out, sc,
+                                               (char *)workspace + kScalarBytes, st),
                     "csg_gradient");
         } else {
             float2 *resid = (float2 *)((char *)workspace + kScalarBytes);
@@ -198,8 +207,9 @@ int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *pos
     if ((rc = check_poses(poses))) return rc;
     if (!z || !hz_out) return fail(CSG_EINVAL, "csg_hvp: z and hz_out must be non-NULL");
     if (z == hz_out) return fail(CSG_EINVAL, "csg_hvp: hz_out must not alias z");
-    if (deterministic) {
-        const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_GRADIENT_DETERMINISTIC);
+    {
+        const size_t need = csg_workspace_bytes(grid, poses->n, deterministic ? CSG_WS_GRADIENT_DETERMINISTIC
+                                                                              : CSG_WS_GRADIENT);
         if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_hvp"))) return rc;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -207,8 +217,8 @@ int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *pos
     CSG_TRY(csg::launch_scaled_copy((float2 *)hz_out, (const float2 *)z, lambda, nv, nullptr, st), "csg_hvp");
     if (poses->n == 0) return CSG_OK;
     if (!deterministic) {
-        CSG_TRY(csg::launch_hvp_atomic(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, scale,
-                                       (float2 *)hz_out, st),
+        CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, scale,
+                                      (float2 *)hz_out, (char *)workspace + kScalarBytes, st),
                 "csg_hvp");
     } else {
         float2 *img = (float2 *)((char *)workspace + kScalarBytes);
@@ -253,7 +263,8 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
                 "csg_hutchinson_diag");
         CSG_TRY(csg::launch_scaled_copy(hz, z, lambda, nv, nullptr, st), "csg_hutchinson_diag");
         if (poses->n > 0)
-            CSG_TRY(csg::launch_hvp_atomic(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz, st),
+            CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz,
+                                          (char *)(hz + nv), st),
                     "csg_hutchinson_diag");
         CSG_TRY(csg::launch_zhz_accum(diag_out, z, hz, nv, w, st), "csg_hutchinson_diag");
     }

@@ -1,0 +1,494 @@
+// brick_kernels.hip -- brick-binned forward projection and adjoint.
+//
+// The volume is cut into 16^3 bricks.  A cull kernel lists, per brick and in
+// image order, the images whose slice plane reaches the brick.  A work item is
+// one brick and up to 256 of its images; its block
+//   - stages the brick plus a one-voxel halo of the gathered volume in LDS
+//     (18^3 complex values), so every trilinear gather is 8 LDS reads;
+//   - accumulates the adjoint into an LDS copy of the brick with LDS float
+//     atomics, and writes it to HBM once per voxel at the end (a plain
+//     read-modify-write when the brick has a single work item, global atomics
+//     only for the few central bricks that more than 256 images cross).
+// The pixels of an image that matter for a brick are found row by row: for
+// image row ky the sample points form a line, and the pixels whose cell
+// reaches the brick's box form an interval of kx, computed by clipping the
+// line against the box.  Eight images x 32 rows fill the 256 lanes; a block
+// scan turns the row intervals into one flat pixel range that the lanes walk
+// together, so neighbouring lanes take neighbouring pixels of a row (coalesced
+// image reads and writes).
+//
+// A pixel is "touching" a brick when one of its eight cell corners lies in
+// the brick, and "owned" by the brick that contains its base corner
+// floor(g).  The adjoint adds, for every touching pixel, the corners inside
+// the brick -- so each (pixel, corner) contribution is added exactly once over
+// all bricks; forward outputs and loss terms are produced by the owner only.
+//
+// Modes:
+//   kBProject      out = C P v (- x) for owned pixels; loss
+//   kBBackproject  accum += scale C^p img
+//   kBGradient     r = C P v - x; loss (owner); accum += scale C r
+//   kBHvp          accum += scale C^2 P z
+#include "csg_device.h"
+#include "csg_internal.h"
+
+namespace csg {
+
+constexpr int BS = 16;           // brick side
+constexpr int BH = BS + 2;       // staged side: one halo voxel below and above
+constexpr int ROWS = 32;         // row slots per image (a brick spans <= 30 rows)
+constexpr int GIMG = kBlock / ROWS;  // images per group
+constexpr int CHUNK = 256;       // images per work item
+constexpr float kClipEps = 1e-2f;
+
+enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3 };
+
+struct BrickArgs {
+    Geom g;
+    const float *rot;
+    const float *defocus;
+    int64_t n;          // images of this sub-batch
+    const float2 *src;  // gathered volume
+    const float2 *img;  // x (project subtract / gradient) or adjoint input
+    float2 *out;        // projected images
+    float2 *accum;      // adjoint target
+    double *loss;
+    float scale;
+    int ctf_power;
+    const int *counts;  // [nb]
+    const int *lists;   // [nb][stride]
+    int stride;
+    int nbx, nb;
+};
+
+__device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
+    o[0] = (b % nbx) * BS;
+    o[1] = ((b / nbx) % nbx) * BS;
+    o[2] = (b / (nbx * nbx)) * BS;
+}
+
+// ---------------------------------------------------------------------------
+// Cull: lists[b] = images whose plane meets the box of cells touching brick b
+// (grid coordinates [b0 - 1, b0 + BS]^3), in increasing image order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float *rot, int64_t n, int nbx,
+                                                             int *counts, int *lists, int stride) {
+    __shared__ int wave_count[kBlock / 64];
+    const int b = blockIdx.x;
+    int o[3];
+    brick_origin(b, nbx, o);
+    float c[3], hw[3];
+    float dist2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float lo = (float)(o[d] - 1 - g.half), hi = (float)(o[d] + BS - g.half);
+        c[d] = 0.5f * (lo + hi);
+        hw[d] = 0.5f * (hi - lo);
+        const float near = fmaxf(fmaxf(lo, -hi), 0.f);  // distance of the box to the origin along d
+        dist2 += near * near;
+    }
+    // sample points lie within |p| <= r_max; the box must come that close
+    const float rmax = sqrtf((float)g.k2max) + 2.0f;
+    const bool reachable = dist2 <= rmax * rmax;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int total = 0;
+    for (int64_t base = 0; base < n; base += kBlock) {
+        const int64_t i = base + threadIdx.x;
+        bool keep = false;
+        if (reachable && i < n) {
+            const float e0 = rot[i * 9 + 6], e1 = rot[i * 9 + 7], e2 = rot[i * 9 + 8];
+            const float h = e0 * c[0] + e1 * c[1] + e2 * c[2];
+            const float reach = fabsf(e0) * hw[0] + fabsf(e1) * hw[1] + fabsf(e2) * hw[2];
+            keep = fabsf(h) <= reach + kClipEps;
+        }
+        const uint64_t mask = __ballot(keep);
+        if (lane == 0) wave_count[wv] = __popcll(mask);
+        __syncthreads();
+        int off = total;
+        for (int w = 0; w < wv; ++w) off += wave_count[w];
+        if (keep) lists[(int64_t)b * stride + off + __popcll(mask & ((1ull << lane) - 1ull))] = (int)i;
+        for (int w = 0; w < kBlock / 64; ++w) total += wave_count[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[b] = total;
+}
+
+// Exclusive scan of one int per thread over the block; returns the prefix and
+// writes the total to *total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sums[wv] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wv) base += wave_sums[w];
+        tot += wave_sums[w];
+    }
+    *total = tot;
+    return base + x - v;
+}
+
+// Interval of kx for which the sample point of row ky lies in the box
+// [lo, hi) (grid coordinates) on every axis, widened by kClipEps.
+__device__ __forceinline__ void clip_row(const float e1[3], const float e2[3], float half, int ky, const float lo[3],
+                                         const float hi[3], int &kx0, int &kx1) {
+    float a = -1e30f, b = 1e30f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float c = fmaf((float)ky, e2[d], half);
+        if (fabsf(e1[d]) < 1e-7f) {
+            if (c < lo[d] - kClipEps || c >= hi[d] + kClipEps) {
+                a = 1e30f;
+                b = -1e30f;
+            }
+        } else {
+            const float inv = 1.0f / e1[d];
+            const float t0 = (lo[d] - c) * inv, t1 = (hi[d] - c) * inv;
+            a = fmaxf(a, fminf(t0, t1));
+            b = fminf(b, fmaxf(t0, t1));
+        }
+    }
+    kx0 = (int)fmaxf(ceilf(a - kClipEps), -1e6f);
+    kx1 = (int)fminf(floorf(b + kClipEps), 1e6f);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
+    constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
+    constexpr bool SCATTER = MODE != kBProject;
+    constexpr bool OWNER_ONLY = MODE == kBProject;
+    __shared__ float2 vh[GATHER ? BH * BH * BH : 1];
+    __shared__ float acc_re[SCATTER ? BS * BS * BS : 1];
+    __shared__ float acc_im[SCATTER ? BS * BS * BS : 1];
+    __shared__ int seg_start[kBlock + 1];
+    __shared__ int seg_kx0[kBlock];
+    __shared__ int seg_ky[kBlock];
+    __shared__ float img_e[GIMG][6];
+    __shared__ double img_a[GIMG];
+    __shared__ int img_idx[GIMG];
+    __shared__ int wave_sums[kBlock / 64];
+    __shared__ double red[16];
+
+    const Geom &g = a.g;
+    const int M = g.M;
+    const int brick = blockIdx.x % a.nb;
+    const int chunk = blockIdx.x / a.nb;
+    const int count = a.counts[brick];
+    const int first = chunk * CHUNK;
+    if (first >= count) return;  // uniform: no work item here
+    const int n_img = min(CHUNK, count - first);
+    const bool single = count <= CHUNK;
+    int o[3];
+    brick_origin(brick, a.nbx, o);
+
+    if (GATHER) {
+        for (int t = threadIdx.x; t < BH * BH * BH; t += kBlock) {
+            const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
+            const int qx = o[0] - 1 + hx, qy = o[1] - 1 + hy, qz = o[2] - 1 + hz;
+            float2 v = make_float2(0.f, 0.f);
+            if (in_grid(qx, M) && in_grid(qy, M) && in_grid(qz, M)) v = a.src[((int64_t)qz * M + qy) * M + qx];
+            vh[t] = v;
+        }
+    }
+    if (SCATTER) {
+        for (int t = threadIdx.x; t < BS * BS * BS; t += kBlock) {
+            acc_re[t] = 0.f;
+            acc_im[t] = 0.f;
+        }
+    }
+    // enumeration box (grid coordinates): owned pixels have floor(g) in the
+    // brick, touching pixels have floor(g) in [b0 - 1, b0 + BS - 1]
+    float lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = (float)(OWNER_ONLY ? o[d] : o[d] - 1);
+        hi[d] = (float)(o[d] + BS);
+    }
+    const float halff = (float)g.half;
+    const int kymax = (int)floorf(sqrtf((float)g.k2max) + 1e-4f);
+    const int *list = a.lists + (int64_t)brick * a.stride + first;
+    double lsum = 0.0;
+    __syncthreads();
+
+    for (int gi = 0; gi < n_img; gi += GIMG) {
+        // ---- row segments of GIMG images x ROWS rows, one per thread
+        const int s = threadIdx.x / ROWS, r = threadIdx.x % ROWS;
+        int len = 0, kx0 = 0, ky = 0;
+        if (gi + s < n_img) {
+            const int ii = list[gi + s];
+            float e1[3], e2[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                e1[d] = a.rot[(int64_t)ii * 9 + d];
+                e2[d] = a.rot[(int64_t)ii * 9 + 3 + d];
+            }
+            if (r == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    img_e[s][d] = e1[d];
+                    img_e[s][3 + d] = e2[d];
+                }
+                img_a[s] = g.ctf_a * (double)a.defocus[ii];
+                img_idx[s] = ii;
+            }
+            // rows: range of e2 . (g - half) over the box
+            float ylo = 0.f, yhi = 0.f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const float u = e2[d] * (lo[d] - halff), w = e2[d] * (hi[d] - halff);
+                ylo += fminf(u, w);
+                yhi += fmaxf(u, w);
+            }
+            const int ky_lo = max((int)ceilf(ylo - kClipEps), -kymax);
+            const int ky_hi = min((int)floorf(yhi + kClipEps), kymax);
+            ky = ky_lo + r;
+            if (ky <= ky_hi) {
+                int x0, x1;
+                clip_row(e1, e2, halff, ky, lo, hi, x0, x1);
+                // the disk: |kx| <= floor(sqrt(k2max - ky^2))
+                const int rem = g.k2max - ky * ky;
+                int kxm = (int)sqrtf((float)rem);
+                while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
+                while (kxm * kxm > rem) --kxm;
+                x0 = max(x0, -kxm);
+                x1 = min(x1, kxm);
+                if (x1 >= x0) {
+                    len = x1 - x0 + 1;
+                    kx0 = x0;
+                }
+            }
+        }
+        int T;
+        const int pre = block_exclusive_scan(len, wave_sums, &T);
+        seg_start[threadIdx.x] = pre;
+        seg_kx0[threadIdx.x] = kx0;
+        seg_ky[threadIdx.x] = ky;
+        if (threadIdx.x == 0) seg_start[kBlock] = T;
+        __syncthreads();
+
+        // ---- walk the flat pixel range
+        for (int f = threadIdx.x; f < T; f += kBlock) {
+            // last segment whose start is <= f
+            int lo_s = 0, hi_s = kBlock;  // seg_start[lo_s] <= f < seg_start[hi_s]
+            while (hi_s - lo_s > 1) {
+                const int mid = (lo_s + hi_s) >> 1;
+                if (seg_start[mid] <= f) lo_s = mid; else hi_s = mid;
+            }
+            const int sl = lo_s;
+            const int is = sl / ROWS;
+            const int pky = seg_ky[sl];
+            const int pkx = seg_kx0[sl] + (f - seg_start[sl]);
+            float e1[3], e2[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                e1[d] = img_e[is][d];
+                e2[d] = img_e[is][3 + d];
+            }
+            const Cell cl = sample_cell(g, e1, e2, pkx, pky);
+            int l[3];
+            bool inside = true, owned = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                l[d] = cl.f[d] - o[d];  // base corner relative to the brick
+                inside = inside && l[d] >= -1 && l[d] <= BS - 1;
+                owned = owned && l[d] >= 0 && l[d] <= BS - 1;
+            }
+            if (OWNER_ONLY ? !owned : !inside) continue;
+            const int k2 = pkx * pkx + pky * pky;
+            const float C = ctf_value(g, img_a[is], k2);
+            const int64_t j = ((int64_t)img_idx[is] * M + (pky + g.half)) * (int64_t)M + (pkx + g.half);
+            float wx[2] = {1.0f - cl.t[0], cl.t[0]};
+            float wy[2] = {1.0f - cl.t[1], cl.t[1]};
+            float wz[2] = {1.0f - cl.t[2], cl.t[2]};
+            // corners outside the grid are dropped
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (!in_grid(cl.f[0] + e, M)) wx[e] = 0.f;
+                if (!in_grid(cl.f[1] + e, M)) wy[e] = 0.f;
+                if (!in_grid(cl.f[2] + e, M)) wz[e] = 0.f;
+            }
+            float2 acc = make_float2(0.f, 0.f);
+            if (GATHER) {
+                // halo index of the base corner: l + 1 in [0, BS]
+                const int hb = ((l[2] + 1) * BH + (l[1] + 1)) * BH + (l[0] + 1);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                    const float w = wx[ax] * wy[ay] * wz[az];
+                    const float2 v = vh[hb + (az * BH + ay) * BH + ax];
+                    acc.x = fmaf(w, v.x, acc.x);
+                    acc.y = fmaf(w, v.y, acc.y);
+                }
+            }
+            float2 val = make_float2(0.f, 0.f);
+            if (MODE == kBProject) {
+                float2 y = make_float2(C * acc.x, C * acc.y);
+                if (a.img) {
+                    const float2 x = a.img[j];
+                    y.x -= x.x;
+                    y.y -= x.y;
+                }
+                if (a.out) a.out[j] = y;
+                lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
+            } else if (MODE == kBBackproject) {
+                const float2 x = a.img[j];
+                const float fct = a.scale * ctf_pow(C, a.ctf_power);
+                val = make_float2(fct * x.x, fct * x.y);
+            } else if (MODE == kBGradient) {
+                const float2 x = a.img[j];
+                const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
+                if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                const float fct = a.scale * C;
+                val = make_float2(fct * rr.x, fct * rr.y);
+            } else if (MODE == kBHvp) {
+                const float fct = a.scale * C * C;
+                val = make_float2(fct * acc.x, fct * acc.y);
+            }
+            if (SCATTER) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                    const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
+                    if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS && (unsigned)lz < (unsigned)BS) {
+                        const float w = wx[ax] * wy[ay] * wz[az];
+                        const int li = (lz * BS + ly) * BS + lx;
+                        atomicAdd(&acc_re[li], w * val.x);
+                        atomicAdd(&acc_im[li], w * val.y);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // segments are rebuilt for the next group
+    }
+
+    if (SCATTER) {
+        for (int t = threadIdx.x; t < BS * BS * BS; t += kBlock) {
+            const int qx = o[0] + t % BS, qy = o[1] + (t / BS) % BS, qz = o[2] + t / (BS * BS);
+            if (!(qx < M && qy < M && qz < M)) continue;
+            const float re = acc_re[t], im = acc_im[t];
+            float2 *p = a.accum + ((int64_t)qz * M + qy) * M + qx;
+            if (single) {
+                float2 v = *p;
+                v.x += re;
+                v.y += im;
+                *p = v;
+            } else if (re != 0.f || im != 0.f) {
+                atomicAdd(&p->x, re);
+                atomicAdd(&p->y, im);
+            }
+        }
+    }
+    if ((MODE == kBProject || MODE == kBGradient) && a.loss) {
+        const double t = block_sum(lsum, red);
+        if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
+    }
+}
+
+// Zero the pixels outside the disk (the brick kernels write only the disk).
+__global__ __launch_bounds__(kBlock) void zero_outside_disk_kernel(float2 *out, int64_t n, int M, int half,
+                                                                    int k2max) {
+    const int64_t total = n * (int64_t)M * M;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int pix = (int)(t % ((int64_t)M * M));
+        const int ky = pix / M - half, kx = pix % M - half;
+        if (kx * kx + ky * ky > k2max) out[t] = make_float2(0.f, 0.f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+int brick_count(int M) {
+    const int nbx = (M + BS - 1) / BS;
+    return nbx * nbx * nbx;
+}
+
+size_t brick_workspace_bytes(int M, int64_t n) {
+    const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
+    const size_t nb = (size_t)brick_count(M);
+    const size_t counts = (nb * 4 + 255) / 256 * 256;
+    return counts + nb * (size_t)(sub > 0 ? sub : 1) * 4;
+}
+
+template <int MODE>
+static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *src,
+                                 const float2 *img, float2 *out, float2 *accum, double *loss, float scale,
+                                 int ctf_power, void *ws, hipStream_t st) {
+    const int M = g.M;
+    const int nbx = (M + BS - 1) / BS;
+    const int nb = nbx * nbx * nbx;
+    int *counts = (int *)ws;
+    int *lists = (int *)((char *)ws + ((size_t)nb * 4 + 255) / 256 * 256);
+    const int64_t img_stride = (int64_t)M * M;
+    for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
+        const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
+        const int stride = (int)ns;
+        hipLaunchKernelGGL(brick_cull_kernel, dim3(nb), dim3(kBlock), 0, st, g, rot + s0 * 9, ns, nbx, counts, lists,
+                           stride);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        BrickArgs a{};
+        a.g = g;
+        a.rot = rot + s0 * 9;
+        a.defocus = defocus + s0;
+        a.n = ns;
+        a.src = src;
+        a.img = img ? img + s0 * img_stride : nullptr;
+        a.out = out ? out + s0 * img_stride : nullptr;
+        a.accum = accum;
+        a.loss = loss;
+        a.scale = scale;
+        a.ctf_power = ctf_power;
+        a.counts = counts;
+        a.lists = lists;
+        a.stride = stride;
+        a.nbx = nbx;
+        a.nb = nb;
+        const int64_t chunks = (ns + CHUNK - 1) / CHUNK;
+        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBlock), 0, st, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                                const float2 *subtract, float2 *out, double *loss, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws, st);
+    if (e != hipSuccess || !out) return e;
+    const int64_t total = n * (int64_t)g.M * g.M;
+    int64_t blocks = (total + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(zero_outside_disk_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, out, n, g.M, g.half,
+                       g.k2max);
+    return hipGetLastError();
+}
+
+hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                    const float2 *img, int ctf_power, float scale, float2 *accum, void *ws,
+                                    hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    return run_brick_mode<kBBackproject>(g, rot, defocus, n, nullptr, img, nullptr, accum, nullptr, scale, ctf_power,
+                                         ws, st);
+}
+
+hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                                 const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    return run_brick_mode<kBGradient>(g, rot, defocus, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
+}
+
+hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
+                            float scale, float2 *accum, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    return run_brick_mode<kBHvp>(g, rot, defocus, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
+}
+
+}  // namespace csg

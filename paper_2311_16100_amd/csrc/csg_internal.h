@@ -9,6 +9,23 @@
 
 namespace csg {
 
+// Images per launch of the brick kernels; larger batches are processed in
+// sub-batches of this size (it bounds the per-brick image lists).
+constexpr int64_t kBrickSubBatch = 2048;
+
+// brick-binned kernels (brick_kernels.hip)
+int brick_count(int M);
+size_t brick_workspace_bytes(int M, int64_t n);
+hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                                const float2 *subtract, float2 *out, double *loss, void *ws, hipStream_t st);
+hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                    const float2 *img, int ctf_power, float scale, float2 *accum, void *ws,
+                                    hipStream_t st);
+hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
+                                 const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st);
+hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
+                            float scale, float2 *accum, void *ws, hipStream_t st);
+
 // pixel-parallel kernels (pixel_kernels.hip)
 hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
                           const float2 *subtract, float2 *out, double *loss, hipStream_t st);

@@ -69,6 +69,7 @@ class Alg1Runner:
         self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
                                          else B.CSG_WS_GRADIENT, dev)
         self.ws_hutch = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev) if arm == "hutchinson" else None
+        self.ws_proj = B.alloc_workspace(grid, batch, B.CSG_WS_PROJECT, dev)
 
     def iteration(self, rot_I, df_I, x_I) -> int:
         st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
@@ -88,7 +89,8 @@ class Alg1Runner:
                                stats_out=self.sc[1:3])
             first = False
             self.sc[3:4].zero_()
-            B.project(g, o, rot_I, df_I, self.v_new, subtract=x_I, out=None, loss=self.sc[3:4], want_out=False)
+            B.project(g, o, rot_I, df_I, self.v_new, subtract=x_I, out=None, loss=self.sc[3:4], want_out=False,
+                      workspace=self.ws_proj)
             f0, gn, vn2, l1 = self.sc.tolist()
             f1 = self.scale * l1 + 0.5 * self.lam * vn2
             if f1 <= f0 - cfg.c * eta * gn:

@@ -208,6 +208,19 @@ def test_precond_step_parity(b):
     assert rel(vo2.cpu().numpy(), wv2) <= 1e-6 and st2[0].item() == pytest.approx(wgn2, rel=1e-6)
 
 
+def test_sub_batches_beyond_2048_images(b):
+    # the brick kernels process at most 2048 images per launch; larger
+    # batches run in sub-batches that accumulate into the same outputs
+    grid_o, opt_o, P, vol, img = make_case(M=16, n=2100, seed=41)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    assert rel(b.project(g, o, rot, df, v).cpu().numpy(), oracle.project(grid_o, opt_o, P, vol)) <= 1e-5
+    acc = b.backproject(g, o, rot, df, x, ctf_power=1, scale=0.5)
+    assert rel(acc.cpu().numpy(), oracle.backproject(grid_o, opt_o, P, img, 1, 0.5)) <= 1e-4
+    hz = b.hvp(g, o, rot, df, v, 1.0, 0.1)
+    assert rel(hz.cpu().numpy(), oracle.hvp(grid_o, opt_o, P, vol, 1.0, 0.1)) <= 1e-4
+
+
 def test_empty_and_degenerate_inputs(b):
     M = 16
     g, o = b.Grid(M), b.Optics()
