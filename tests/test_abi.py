@@ -51,7 +51,8 @@ def test_workspace_sizes(b):
 def _call_project(b, grid, optics, n=1):
     L = b.lib()
     p = b._Poses(n, None, None)
-    return L.csg_project(ctypes.byref(grid), ctypes.byref(optics), ctypes.byref(p), None, None, None, None, None)
+    return L.csg_project(ctypes.byref(grid), ctypes.byref(optics), ctypes.byref(p), None, None, None, None, None, 0,
+                         None)
 
 
 @pytest.mark.parametrize("M,rmax,interp", [(7, 2.0, 1), (2, 0.0, 1), (2048, 10.0, 1), (32, 16.0, 1),
@@ -81,7 +82,8 @@ def test_null_pointers_rejected(b):
     assert L.csg_rademacher(0, 0, 0, None, None) == 0
     p = b._Poses(0, None, None)
     g, o = b.Grid(16).c(), b.Optics().c()
-    assert L.csg_project(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, None, None, None, None) == 0
+    assert L.csg_project(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, None, None, None, None, 0,
+                         None) == 0
 
 
 def test_bad_ctf_power_rejected(b):
