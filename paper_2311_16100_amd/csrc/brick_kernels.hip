@@ -458,9 +458,12 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     return hipSuccess;
 }
 
+// The brick kernels implement trilinear interpolation; nearest-neighbour
+// grids (the exact-pin mode of Sec. 3.1) use the pixel-parallel kernels.
 hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
                                 const float2 *subtract, float2 *out, double *loss, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
+    if (g.interp == 0) return launch_project(g, rot, defocus, n, vol, subtract, out, loss, st);
     hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws, st);
     if (e != hipSuccess || !out) return e;
     const int64_t total = n * (int64_t)g.M * g.M;
@@ -475,6 +478,7 @@ hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float
                                     const float2 *img, int ctf_power, float scale, float2 *accum, void *ws,
                                     hipStream_t st) {
     if (n == 0) return hipSuccess;
+    if (g.interp == 0) return launch_backproject_atomic(g, rot, defocus, n, img, ctf_power, scale, accum, st);
     return run_brick_mode<kBBackproject>(g, rot, defocus, n, nullptr, img, nullptr, accum, nullptr, scale, ctf_power,
                                          ws, st);
 }
@@ -482,12 +486,14 @@ hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float
 hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
                                  const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
+    if (g.interp == 0) return launch_gradient_atomic(g, rot, defocus, n, vol, x, scale, accum, loss, st);
     return run_brick_mode<kBGradient>(g, rot, defocus, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
                             float scale, float2 *accum, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
+    if (g.interp == 0) return launch_hvp_atomic(g, rot, defocus, n, z, scale, accum, st);
     return run_brick_mode<kBHvp>(g, rot, defocus, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
 }
 
