@@ -35,8 +35,15 @@ namespace csg {
 
 constexpr int BS = 16;           // brick side
 constexpr int BH = BS + 2;       // staged side: one halo voxel below and above
+// LDS strides are odd (in elements) so that lanes stepping along any axis of
+// the brick fall into different banks.
+constexpr int AR = BS + 1;       // accumulator row stride
+constexpr int AP = AR * AR;      // accumulator plane stride (289)
+constexpr int VR = BH + 1;       // staged-volume row stride (19)
+constexpr int VP = VR * VR;      // staged-volume plane stride (361)
+constexpr int kBT = 512;         // threads per brick block (8 waves)
 constexpr int ROWS = 32;         // row slots per image (a brick spans <= 30 rows)
-constexpr int GIMG = kBlock / ROWS;  // images per group
+constexpr int GIMG = kBT / ROWS; // images per group
 constexpr int CHUNK = 256;       // images per work item
 constexpr float kClipEps = 1e-2f;
 
@@ -116,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float 
 // writes the total to *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NW = kBT / 64;
     int x = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -125,7 +133,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *
     if (lane == 63) wave_sums[wv] = x;
     __syncthreads();
     int base = 0, tot = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NW; ++w) {
         if (w < wv) base += wave_sums[w];
         tot += wave_sums[w];
     }
@@ -158,20 +166,20 @@ __device__ __forceinline__ void clip_row(const float e1[3], const float e2[3], f
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
+__global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool OWNER_ONLY = MODE == kBProject;
-    __shared__ float2 vh[GATHER ? BH * BH * BH : 1];
-    __shared__ float acc_re[SCATTER ? BS * BS * BS : 1];
-    __shared__ float acc_im[SCATTER ? BS * BS * BS : 1];
-    __shared__ int seg_start[kBlock + 1];
-    __shared__ int seg_kx0[kBlock];
-    __shared__ int seg_ky[kBlock];
+    __shared__ float2 vh[GATHER ? BH * VP : 1];
+    __shared__ float acc_re[SCATTER ? BS * AP : 1];
+    __shared__ float acc_im[SCATTER ? BS * AP : 1];
+    __shared__ int seg_start[kBT + 1];
+    __shared__ int seg_kx0[kBT];
+    __shared__ int seg_ky[kBT];
     __shared__ float img_e[GIMG][6];
     __shared__ double img_a[GIMG];
     __shared__ int img_idx[GIMG];
-    __shared__ int wave_sums[kBlock / 64];
+    __shared__ int wave_sums[kBT / 64];
     __shared__ double red[16];
 
     const Geom &g = a.g;
@@ -187,16 +195,16 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
     brick_origin(brick, a.nbx, o);
 
     if (GATHER) {
-        for (int t = threadIdx.x; t < BH * BH * BH; t += kBlock) {
+        for (int t = threadIdx.x; t < BH * BH * BH; t += kBT) {
             const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
             const int qx = o[0] - 1 + hx, qy = o[1] - 1 + hy, qz = o[2] - 1 + hz;
             float2 v = make_float2(0.f, 0.f);
             if (in_grid(qx, M) && in_grid(qy, M) && in_grid(qz, M)) v = a.src[((int64_t)qz * M + qy) * M + qx];
-            vh[t] = v;
+            vh[(hz * VR + hy) * VR + hx] = v;
         }
     }
     if (SCATTER) {
-        for (int t = threadIdx.x; t < BS * BS * BS; t += kBlock) {
+        for (int t = threadIdx.x; t < BS * AP; t += kBT) {
             acc_re[t] = 0.f;
             acc_im[t] = 0.f;
         }
@@ -268,13 +276,13 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
         seg_start[threadIdx.x] = pre;
         seg_kx0[threadIdx.x] = kx0;
         seg_ky[threadIdx.x] = ky;
-        if (threadIdx.x == 0) seg_start[kBlock] = T;
+        if (threadIdx.x == 0) seg_start[kBT] = T;
         __syncthreads();
 
         // ---- walk the flat pixel range
-        for (int f = threadIdx.x; f < T; f += kBlock) {
+        for (int f = threadIdx.x; f < T; f += kBT) {
             // last segment whose start is <= f
-            int lo_s = 0, hi_s = kBlock;  // seg_start[lo_s] <= f < seg_start[hi_s]
+            int lo_s = 0, hi_s = kBT;  // seg_start[lo_s] <= f < seg_start[hi_s]
             while (hi_s - lo_s > 1) {
                 const int mid = (lo_s + hi_s) >> 1;
                 if (seg_start[mid] <= f) lo_s = mid; else hi_s = mid;
@@ -315,12 +323,12 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
             float2 acc = make_float2(0.f, 0.f);
             if (GATHER) {
                 // halo index of the base corner: l + 1 in [0, BS]
-                const int hb = ((l[2] + 1) * BH + (l[1] + 1)) * BH + (l[0] + 1);
+                const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                     const float w = wx[ax] * wy[ay] * wz[az];
-                    const float2 v = vh[hb + (az * BH + ay) * BH + ax];
+                    const float2 v = vh[hb + az * VP + ay * VR + ax];
                     acc.x = fmaf(w, v.x, acc.x);
                     acc.y = fmaf(w, v.y, acc.y);
                 }
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
                     const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
                     if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS && (unsigned)lz < (unsigned)BS) {
                         const float w = wx[ax] * wy[ay] * wz[az];
-                        const int li = (lz * BS + ly) * BS + lx;
+                        const int li = lz * AP + ly * AR + lx;
                         atomicAdd(&acc_re[li], w * val.x);
                         atomicAdd(&acc_im[li], w * val.y);
                     }
@@ -367,10 +375,12 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
     }
 
     if (SCATTER) {
-        for (int t = threadIdx.x; t < BS * BS * BS; t += kBlock) {
-            const int qx = o[0] + t % BS, qy = o[1] + (t / BS) % BS, qz = o[2] + t / (BS * BS);
+        for (int t = threadIdx.x; t < BS * BS * BS; t += kBT) {
+            const int tx = t % BS, ty = (t / BS) % BS, tz = t / (BS * BS);
+            const int qx = o[0] + tx, qy = o[1] + ty, qz = o[2] + tz;
             if (!(qx < M && qy < M && qz < M)) continue;
-            const float re = acc_re[t], im = acc_im[t];
+            const int li = tz * AP + ty * AR + tx;
+            const float re = acc_re[li], im = acc_im[li];
             float2 *p = a.accum + ((int64_t)qz * M + qy) * M + qx;
             if (single) {
                 float2 v = *p;
@@ -390,14 +400,17 @@ __global__ __launch_bounds__(kBlock) void brick_kernel(BrickArgs a) {
 }
 
 // Zero the pixels outside the disk (the brick kernels write only the disk).
+// One thread per (image row, pixel); only the pixels outside the disk are
+// stored.
 __global__ __launch_bounds__(kBlock) void zero_outside_disk_kernel(float2 *out, int64_t n, int M, int half,
                                                                     int k2max) {
-    const int64_t total = n * (int64_t)M * M;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        const int pix = (int)(t % ((int64_t)M * M));
-        const int ky = pix / M - half, kx = pix % M - half;
-        if (kx * kx + ky * ky > k2max) out[t] = make_float2(0.f, 0.f);
+    const int64_t rows = n * (int64_t)M;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int ky = (int)(row % M) - half;
+        for (int x = threadIdx.x; x < M; x += blockDim.x) {
+            const int kx = x - half;
+            if (kx * kx + ky * ky > k2max) out[row * M + x] = make_float2(0.f, 0.f);
+        }
     }
 }
 
@@ -451,7 +464,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.nbx = nbx;
         a.nb = nb;
         const int64_t chunks = (ns + CHUNK - 1) / CHUNK;
-        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBT), 0, st, a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -466,9 +479,8 @@ hipError_t launch_brick_project(const Geom &g, const float *rot, const float *de
     if (g.interp == 0) return launch_project(g, rot, defocus, n, vol, subtract, out, loss, st);
     hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws, st);
     if (e != hipSuccess || !out) return e;
-    const int64_t total = n * (int64_t)g.M * g.M;
-    int64_t blocks = (total + kBlock - 1) / kBlock;
-    if (blocks > 16384) blocks = 16384;
+    int64_t blocks = n * (int64_t)g.M;
+    if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(zero_outside_disk_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, out, n, g.M, g.half,
                        g.k2max);
     return hipGetLastError();

@@ -15,6 +15,15 @@ static inline unsigned stream_blocks(int64_t units) {
     return (unsigned)b;
 }
 
+// Kernels that end in a double-precision atomic per block use fewer, longer
+// blocks (16 waves per CU) to keep those atomics few.
+static inline unsigned reduce_blocks(int64_t units) {
+    int64_t b = (units + kBlock - 1) / kBlock;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
 // out = lam * in (complex), norm2 += sum |in|^2 (norm2 may be NULL).
 __global__ __launch_bounds__(kBlock) void scaled_copy_kernel(float2 *__restrict__ out, const float2 *__restrict__ in,
                                                               float lam, int64_t nvox, double *norm2) {
@@ -159,7 +168,8 @@ hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, 
 }
 
 hipError_t launch_scaled_copy(float2 *out, const float2 *in, float lam, int64_t nvox, double *norm2, hipStream_t st) {
-    hipLaunchKernelGGL(scaled_copy_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, out, in, lam, nvox, norm2);
+    hipLaunchKernelGGL(scaled_copy_kernel, dim3(norm2 ? reduce_blocks(nvox) : stream_blocks(nvox)), dim3(kBlock), 0,
+                       st, out, in, lam, nvox, norm2);
     return hipGetLastError();
 }
 
@@ -204,7 +214,7 @@ hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, f
     const float wk_new = k > 0 ? (float)(1.0 / (double)k) : 0.f;
     hipError_t e = launch_fill_f64(stats, 2, 0.0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(precond_step_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, nvox, v, g, D, D_avg, zHz,
+    hipLaunchKernelGGL(precond_step_kernel, dim3(reduce_blocks(nvox)), dim3(kBlock), 0, st, nvox, v, g, D, D_avg, zHz,
                        wk_old, wk_new, beta, alpha, eta, v_out, Dhat_out, stats);
     return hipGetLastError();
 }
