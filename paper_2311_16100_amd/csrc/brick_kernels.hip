@@ -1,14 +1,17 @@
 // brick_kernels.hip -- brick-binned forward projection and adjoint.
 //
-// The volume is cut into 16^3 bricks.  A cull kernel lists, per brick and in
+// The volume is cut into 12^3 bricks.  A cull kernel lists, per brick and in
 // image order, the images whose slice plane reaches the brick.  A work item is
 // one brick and up to 256 of its images; its block
 //   - stages the brick plus a one-voxel halo of the gathered volume in LDS
-//     (18^3 complex values), so every trilinear gather is 8 LDS reads;
-//   - accumulates the adjoint into an LDS copy of the brick with LDS float
-//     atomics, and writes it to HBM once per voxel at the end (a plain
-//     read-modify-write when the brick has a single work item, global atomics
-//     only for the few central bricks that more than 256 images cross).
+//     (14^3 complex values), so every trilinear gather is 8 LDS reads;
+//   - accumulates the adjoint into an LDS copy of the brick with double-
+//     precision LDS atomics, and writes it to HBM once per voxel at the end (a
+//     plain read-modify-write when the brick has a single work item, global
+//     atomics only for the few central bricks that more than 256 images
+//     cross).  On gfx950 the LDS double atomic add sustains about 20x the lane
+//     rate of the single-precision one, so the wider accumulator is also the
+//     faster one.
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
@@ -33,7 +36,10 @@
 
 namespace csg {
 
-constexpr int BS = 16;           // brick side
+#ifndef CSG_BRICK_SIDE
+#define CSG_BRICK_SIDE 12
+#endif
+constexpr int BS = CSG_BRICK_SIDE;  // brick side
 constexpr int BH = BS + 2;       // staged side: one halo voxel below and above
 // LDS strides are odd (in elements) so that lanes stepping along any axis of
 // the brick fall into different banks.
@@ -42,9 +48,10 @@ constexpr int AP = AR * AR;      // accumulator plane stride (289)
 constexpr int VR = BH + 1;       // staged-volume row stride (19)
 constexpr int VP = VR * VR;      // staged-volume plane stride (361)
 constexpr int kBT = 512;         // threads per brick block (8 waves)
-constexpr int ROWS = 32;         // row slots per image (a brick spans <= 30 rows)
+constexpr int ROWS = 32;         // row slots per image (a brick spans <= 24 rows)
 constexpr int GIMG = kBT / ROWS; // images per group
-constexpr int CHUNK = 256;       // images per work item
+constexpr int CHUNK_ADJ = 256;   // images per work item of the adjoint modes
+constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
 enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3 };
@@ -65,6 +72,7 @@ struct BrickArgs {
     const int *lists;   // [nb][stride]
     int stride;
     int nbx, nb;
+    int nchunks;        // work items per brick at most
 };
 
 __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
@@ -165,27 +173,40 @@ __device__ __forceinline__ void clip_row(const float e1[3], const float e2[3], f
     kx1 = (int)fminf(floorf(b + kClipEps), 1e6f);
 }
 
+// Per-image constants of a group, kept in LDS in double precision so the
+// pixel loop needs no conversions: the rows of R and the folded CTF term.
+struct ImgSlot {
+    double e1[3];
+    double e2[3];
+    double ctfA;  // (lambda df / 2) / (M pixel)^2: chi / 2pi = k2 (ctfA - ctfB k2)
+    double pad;
+};
+
+constexpr int PIXCAP = 4096;  // pixels per window of the pixel -> segment table
+
 template <int MODE>
 __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool OWNER_ONLY = MODE == kBProject;
+    constexpr int CHUNK = OWNER_ONLY ? CHUNK_FWD : CHUNK_ADJ;
     __shared__ float2 vh[GATHER ? BH * VP : 1];
-    __shared__ float acc_re[SCATTER ? BS * AP : 1];
-    __shared__ float acc_im[SCATTER ? BS * AP : 1];
-    __shared__ int seg_start[kBT + 1];
-    __shared__ int seg_kx0[kBT];
-    __shared__ int seg_ky[kBT];
-    __shared__ float img_e[GIMG][6];
-    __shared__ double img_a[GIMG];
-    __shared__ int img_idx[GIMG];
+    __shared__ double acc_re[SCATTER ? BS * AP : 1];
+    __shared__ double acc_im[SCATTER ? BS * AP : 1];
+    // segment record: x = first flat pixel, y = kx of that pixel,
+    // z = (ky + 512) | image slot << 16, w = pixel index of (kx = 0, ky)
+    __shared__ int4 seg[kBT];
+    __shared__ unsigned short pix2seg[PIXCAP];
+    __shared__ ImgSlot slot[GIMG];
     __shared__ int wave_sums[kBT / 64];
     __shared__ double red[16];
 
     const Geom &g = a.g;
     const int M = g.M;
+    // highest chunk index first: the extra work items of the heavily crossed
+    // central bricks start before the single items of the outer bricks
     const int brick = blockIdx.x % a.nb;
-    const int chunk = blockIdx.x / a.nb;
+    const int chunk = a.nchunks - 1 - (int)(blockIdx.x / a.nb);
     const int count = a.counts[brick];
     const int first = chunk * CHUNK;
     if (first >= count) return;  // uniform: no work item here
@@ -205,8 +226,8 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
     }
     if (SCATTER) {
         for (int t = threadIdx.x; t < BS * AP; t += kBT) {
-            acc_re[t] = 0.f;
-            acc_im[t] = 0.f;
+            acc_re[t] = 0.0;
+            acc_im[t] = 0.0;
         }
     }
     // enumeration box (grid coordinates): owned pixels have floor(g) in the
@@ -218,17 +239,25 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
         hi[d] = (float)(o[d] + BS);
     }
     const float halff = (float)g.half;
+    const double halfd = (double)g.half;
     const int kymax = (int)floorf(sqrtf((float)g.k2max) + 1e-4f);
     const int *list = a.lists + (int64_t)brick * a.stride + first;
+    const double ctfB = g.ctf_b * g.inv_s2 * g.inv_s2;
+    const uint32_t MM = (uint32_t)M * (uint32_t)M;
     double lsum = 0.0;
     __syncthreads();
 
     for (int gi = 0; gi < n_img; gi += GIMG) {
+        // every wave has finished with the previous group's scan, segments
+        // and image slots before they are rewritten
+        __syncthreads();
         // ---- row segments of GIMG images x ROWS rows, one per thread
         const int s = threadIdx.x / ROWS, r = threadIdx.x % ROWS;
         int len = 0, kx0 = 0, ky = 0;
+        uint32_t img_base = 0;
         if (gi + s < n_img) {
             const int ii = list[gi + s];
+            img_base = (uint32_t)ii * MM;
             float e1[3], e2[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -238,11 +267,10 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
             if (r == 0) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    img_e[s][d] = e1[d];
-                    img_e[s][3 + d] = e2[d];
+                    slot[s].e1[d] = (double)e1[d];
+                    slot[s].e2[d] = (double)e2[d];
                 }
-                img_a[s] = g.ctf_a * (double)a.defocus[ii];
-                img_idx[s] = ii;
+                slot[s].ctfA = g.ctf_a * (double)a.defocus[ii] * g.inv_s2;
             }
             // rows: range of e2 . (g - half) over the box
             float ylo = 0.f, yhi = 0.f;
@@ -273,105 +301,110 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
         }
         int T;
         const int pre = block_exclusive_scan(len, wave_sums, &T);
-        seg_start[threadIdx.x] = pre;
-        seg_kx0[threadIdx.x] = kx0;
-        seg_ky[threadIdx.x] = ky;
-        if (threadIdx.x == 0) seg_start[kBT] = T;
-        __syncthreads();
+        seg[threadIdx.x] = make_int4(pre, kx0, (ky + 512) | (s << 16),
+                                     (int)(img_base + (uint32_t)(ky + g.half) * (uint32_t)M + (uint32_t)g.half));
 
-        // ---- walk the flat pixel range
-        for (int f = threadIdx.x; f < T; f += kBT) {
-            // last segment whose start is <= f
-            int lo_s = 0, hi_s = kBT;  // seg_start[lo_s] <= f < seg_start[hi_s]
-            while (hi_s - lo_s > 1) {
-                const int mid = (lo_s + hi_s) >> 1;
-                if (seg_start[mid] <= f) lo_s = mid; else hi_s = mid;
+        for (int wbase = 0; wbase < T; wbase += PIXCAP) {
+            // ---- pixel -> segment table of this window
+            {
+                const int b0 = max(pre, wbase), b1 = min(pre + len, wbase + PIXCAP);
+                for (int q = b0; q < b1; ++q) pix2seg[q - wbase] = (unsigned short)threadIdx.x;
             }
-            const int sl = lo_s;
-            const int is = sl / ROWS;
-            const int pky = seg_ky[sl];
-            const int pkx = seg_kx0[sl] + (f - seg_start[sl]);
-            float e1[3], e2[3];
+            __syncthreads();
+            const int wend = min(T, wbase + PIXCAP);
+            for (int f = wbase + threadIdx.x; f < wend; f += kBT) {
+                const int sl = pix2seg[f - wbase];
+                const int4 rec = seg[sl];
+                const int pkx = rec.y + (f - rec.x);
+                const int pky = (rec.z & 0xFFFF) - 512;
+                const ImgSlot &I = slot[rec.z >> 16];
+                const double dkx = (double)pkx, dky = (double)pky;
+                double rel[3];
+                float t[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                e1[d] = img_e[is][d];
-                e2[d] = img_e[is][3 + d];
-            }
-            const Cell cl = sample_cell(g, e1, e2, pkx, pky);
-            int l[3];
-            bool inside = true, owned = true;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                l[d] = cl.f[d] - o[d];  // base corner relative to the brick
-                inside = inside && l[d] >= -1 && l[d] <= BS - 1;
-                owned = owned && l[d] >= 0 && l[d] <= BS - 1;
-            }
-            if (OWNER_ONLY ? !owned : !inside) continue;
-            const int k2 = pkx * pkx + pky * pky;
-            const float C = ctf_value(g, img_a[is], k2);
-            const int64_t j = ((int64_t)img_idx[is] * M + (pky + g.half)) * (int64_t)M + (pkx + g.half);
-            float wx[2] = {1.0f - cl.t[0], cl.t[0]};
-            float wy[2] = {1.0f - cl.t[1], cl.t[1]};
-            float wz[2] = {1.0f - cl.t[2], cl.t[2]};
-            // corners outside the grid are dropped
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                if (!in_grid(cl.f[0] + e, M)) wx[e] = 0.f;
-                if (!in_grid(cl.f[1] + e, M)) wy[e] = 0.f;
-                if (!in_grid(cl.f[2] + e, M)) wz[e] = 0.f;
-            }
-            float2 acc = make_float2(0.f, 0.f);
-            if (GATHER) {
-                // halo index of the base corner: l + 1 in [0, BS]
-                const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                    const float w = wx[ax] * wy[ay] * wz[az];
-                    const float2 v = vh[hb + az * VP + ay * VR + ax];
-                    acc.x = fmaf(w, v.x, acc.x);
-                    acc.y = fmaf(w, v.y, acc.y);
+                for (int d = 0; d < 3; ++d) {
+                    const double gd = fma(dkx, I.e1[d], fma(dky, I.e2[d], halfd));
+                    const double fl = floor(gd);
+                    rel[d] = fl - (double)o[d];  // base corner relative to the brick
+                    t[d] = (float)(gd - fl);
                 }
-            }
-            float2 val = make_float2(0.f, 0.f);
-            if (MODE == kBProject) {
-                float2 y = make_float2(C * acc.x, C * acc.y);
-                if (a.img) {
-                    const float2 x = a.img[j];
-                    y.x -= x.x;
-                    y.y -= x.y;
+                // range tests in floating point (NaN fails them), so only
+                // in-range values are converted to int
+                const bool owned = rel[0] >= 0.0 && rel[0] <= BS - 1.0 && rel[1] >= 0.0 && rel[1] <= BS - 1.0 &&
+                                   rel[2] >= 0.0 && rel[2] <= BS - 1.0;
+                const bool inside = rel[0] >= -1.0 && rel[0] <= BS - 1.0 && rel[1] >= -1.0 &&
+                                    rel[1] <= BS - 1.0 && rel[2] >= -1.0 && rel[2] <= BS - 1.0;
+                if (OWNER_ONLY ? !owned : !inside) continue;
+                const int l[3] = {(int)rel[0], (int)rel[1], (int)rel[2]};
+                float C = 1.0f;
+                if (g.ctf_on) {
+                    const double k2 = (double)(pkx * pkx + pky * pky);
+                    const double turns = fma(fma(-ctfB, k2, I.ctfA), k2, g.phase0);
+                    C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
                 }
-                if (a.out) a.out[j] = y;
-                lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
-            } else if (MODE == kBBackproject) {
-                const float2 x = a.img[j];
-                const float fct = a.scale * ctf_pow(C, a.ctf_power);
-                val = make_float2(fct * x.x, fct * x.y);
-            } else if (MODE == kBGradient) {
-                const float2 x = a.img[j];
-                const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
-                if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
-                const float fct = a.scale * C;
-                val = make_float2(fct * rr.x, fct * rr.y);
-            } else if (MODE == kBHvp) {
-                const float fct = a.scale * C * C;
-                val = make_float2(fct * acc.x, fct * acc.y);
-            }
-            if (SCATTER) {
+                const uint32_t j = (uint32_t)rec.w + (uint32_t)pkx;
+                const float wx[2] = {1.0f - t[0], t[0]};
+                const float wy[2] = {1.0f - t[1], t[1]};
+                const float wz[2] = {1.0f - t[2], t[2]};
+                float2 acc = make_float2(0.f, 0.f);
+                if (GATHER) {
+                    // halo index of the base corner: l + 1 in [0, BS]; halo
+                    // voxels outside the grid hold zeros, which drops those
+                    // corners
+                    const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                    const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
-                    if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS && (unsigned)lz < (unsigned)BS) {
+                    for (int c = 0; c < 8; ++c) {
+                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                         const float w = wx[ax] * wy[ay] * wz[az];
-                        const int li = lz * AP + ly * AR + lx;
-                        atomicAdd(&acc_re[li], w * val.x);
-                        atomicAdd(&acc_im[li], w * val.y);
+                        const float2 v = vh[hb + az * VP + ay * VR + ax];
+                        acc.x = fmaf(w, v.x, acc.x);
+                        acc.y = fmaf(w, v.y, acc.y);
+                    }
+                }
+                float2 val = make_float2(0.f, 0.f);
+                if (MODE == kBProject) {
+                    float2 y = make_float2(C * acc.x, C * acc.y);
+                    if (a.img) {
+                        const float2 x = a.img[j];
+                        y.x -= x.x;
+                        y.y -= x.y;
+                    }
+                    if (a.out) a.out[j] = y;
+                    lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
+                } else if (MODE == kBBackproject) {
+                    const float2 x = a.img[j];
+                    const float fct = a.scale * ctf_pow(C, a.ctf_power);
+                    val = make_float2(fct * x.x, fct * x.y);
+                } else if (MODE == kBGradient) {
+                    const float2 x = a.img[j];
+                    const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
+                    if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                    const float fct = a.scale * C;
+                    val = make_float2(fct * rr.x, fct * rr.y);
+                } else if (MODE == kBHvp) {
+                    const float fct = a.scale * C * C;
+                    val = make_float2(fct * acc.x, fct * acc.y);
+                }
+                if (SCATTER) {
+                    // corners inside the brick; a corner beyond the grid edge
+                    // lands in an LDS slot that is never written back
+                    const int lb = l[2] * AP + l[1] * AR + l[0];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                        const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
+                        if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS &&
+                            (unsigned)lz < (unsigned)BS) {
+                            const float w = wx[ax] * wy[ay] * wz[az];
+                            const int li = lb + az * AP + ay * AR + ax;
+                            atomicAdd(&acc_re[li], (double)(w * val.x));
+                            atomicAdd(&acc_im[li], (double)(w * val.y));
+                        }
                     }
                 }
             }
+            __syncthreads();  // the table (and, after the last window, the segments) are rebuilt
         }
-        __syncthreads();  // segments are rebuilt for the next group
     }
 
     if (SCATTER) {
@@ -380,7 +413,7 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
             const int qx = o[0] + tx, qy = o[1] + ty, qz = o[2] + tz;
             if (!(qx < M && qy < M && qz < M)) continue;
             const int li = tz * AP + ty * AR + tx;
-            const float re = acc_re[li], im = acc_im[li];
+            const float re = (float)acc_re[li], im = (float)acc_im[li];
             float2 *p = a.accum + ((int64_t)qz * M + qy) * M + qx;
             if (single) {
                 float2 v = *p;
@@ -463,7 +496,9 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.stride = stride;
         a.nbx = nbx;
         a.nb = nb;
-        const int64_t chunks = (ns + CHUNK - 1) / CHUNK;
+        const int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
+        const int64_t chunks = (ns + chunk - 1) / chunk;
+        a.nchunks = (int)chunks;
         hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBT), 0, st, a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
