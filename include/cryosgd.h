@@ -184,6 +184,41 @@ int csg_threshold_alpha(const csg_grid *grid, const csg_optics *optics, const cs
 int csg_features(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
                  float *ctf2_accum, float *cover_accum, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (not part of the paper's method: a regression of
+ * the Hessian diagonal of Sec. 3.2 from per-voxel features, trained on
+ * Hutchinson estimates, with Hutchinson as its judge and fallback).
+ * Network: MLP 3 -> 64 -> 64 -> 1, GELU activations, float32 master
+ * weights used as bfloat16 (round to nearest even), layer inputs rounded to
+ * bfloat16, float32 accumulation (the 64 x 64 products on the matrix cores).
+ * Parameter vector, float32, csg_mlp_param_count() entries:
+ *   W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3.
+ * ------------------------------------------------------------------------ */
+int32_t csg_mlp_param_count(void);
+
+/* y[s] = mlp(X[s]) for n samples; X device float [n][3], y device float [n]. */
+int csg_mlp_forward(const float *params, const float *X, int64_t n, float *y, void *stream);
+
+/* Gradient of the mean squared error L = 1/n sum_s (mlp(X[s]) - T[s])^2 with
+ * respect to the parameter vector (bfloat16 roundings passed straight
+ * through).  grad device float [param_count] and loss_out device double [1]
+ * are overwritten. */
+int csg_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad,
+                 double *loss_out, void *stream);
+
+/* One Adam step (Kingma & Ba) on params with moment buffers m, v (device
+ * float [param_count], zero before step 1); step >= 1 counts the updates. */
+int csg_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream);
+
+/* Predicted Hessian diagonal over the M^3 grid of `grid`:
+ *   diag_out[k] = lambda + N exp(mlp(|k| / (M/2), log(ctf2[k]/N), log(cover[k]/N)))
+ * where cover[k] > 0, and lambda where no image reaches voxel k (there the
+ * data part of the diagonal is exactly zero).  ctf2 and cover are the
+ * outputs of csg_features over the N = n_images images of the data set. */
+int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const float *params,
+                     const float *ctf2, const float *cover, float *diag_out, void *stream);
+
 /* Workspace sizes (bytes) for a batch of n images:
  *   CSG_WS_PROJECT                 csg_project
  *   CSG_WS_BACKPROJECT             csg_backproject (either mode)

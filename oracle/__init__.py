@@ -396,3 +396,93 @@ def fsc(u, v, M: int):
         den = np.sqrt(np.sum(np.abs(u[m]) ** 2) * np.sum(np.abs(v[m]) ** 2))
         out.append((num / den).real if den > 0 else 0.0)
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner network (not part of the paper's method: a
+# per-voxel regression of the Hessian diagonal from cheap features, trained on
+# Hutchinson estimates).  MLP 3 -> 64 -> 64 -> 1 with GELU; weights and the
+# inputs of each weight product are rounded to bfloat16 (round to nearest
+# even), products are accumulated in double here.
+# Parameter vector (float32): W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3.
+# ---------------------------------------------------------------------------
+MLP_H = 64
+MLP_NPARAM = MLP_H * 3 + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+def bf16_round(a) -> np.ndarray:
+    """Round to float32 and then to the nearest bfloat16 (ties to even) -- the
+    path of a float32 activation or weight on the GPU -- returned as
+    float64."""
+    x = np.ascontiguousarray(a, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    rounded = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    out = rounded.astype(np.uint32).view(np.float32)
+    # NaN/Inf pass through unchanged
+    out = np.where(np.isfinite(x), out, x)
+    return out.astype(np.float64)
+
+
+def mlp_unpack(params):
+    p = np.asarray(params, dtype=np.float32)
+    H = MLP_H
+    o = 0
+    W1 = p[o:o + 3 * H].reshape(H, 3); o += 3 * H
+    b1 = p[o:o + H]; o += H
+    W2 = p[o:o + H * H].reshape(H, H); o += H * H
+    b2 = p[o:o + H]; o += H
+    W3 = p[o:o + H]; o += H
+    b3 = p[o:o + 1]
+    return W1, b1, W2, b2, W3, b3
+
+
+def gelu(x):
+    """GELU(x) = x Phi(x) = x/2 (1 + erf(x / sqrt 2))."""
+    from scipy.special import erf
+    return 0.5 * x * (1.0 + erf(x / np.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    from scipy.special import erf
+    return 0.5 * (1.0 + erf(x / np.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+
+
+def mlp_forward(params, X, keep=False):
+    """y = W3 . g(W2 g(W1 x + b1) + b2) + b3 per row of X [n,3]; weights and
+    layer inputs rounded to bfloat16."""
+    W1, b1, W2, b2, W3, b3 = (bf16_round(w) if i % 2 == 0 else np.asarray(w, np.float64)
+                              for i, w in enumerate(mlp_unpack(params)))
+    x0 = bf16_round(np.asarray(X, dtype=np.float64))
+    z1 = x0 @ W1.T + b1
+    h1 = gelu(z1)
+    h1r = bf16_round(h1)
+    z2 = h1r @ W2.T + b2
+    h2 = gelu(z2)
+    h2r = bf16_round(h2)
+    y = h2r @ W3 + b3[0]
+    if keep:
+        return y, dict(x0=x0, z1=z1, h1r=h1r, z2=z2, h2r=h2r, W2=W2, W3=W3)
+    return y
+
+
+def mlp_loss_grad(params, X, t):
+    """Mean squared error L = 1/n sum (y - t)^2 and its gradient with respect
+    to the parameter vector (straight-through: the bfloat16 roundings are
+    treated as identity in the backward pass)."""
+    y, c = mlp_forward(params, X, keep=True)
+    n = len(t)
+    r = y - np.asarray(t, dtype=np.float64)
+    L = float(np.mean(r * r))
+    dy = 2.0 * r / n
+    dW3 = dy @ c["h2r"]
+    db3 = np.array([dy.sum()])
+    dh2 = np.outer(dy, c["W3"])
+    dz2 = dh2 * gelu_grad(c["z2"])
+    dW2 = dz2.T @ c["h1r"]
+    db2 = dz2.sum(axis=0)
+    dh1 = dz2 @ c["W2"]
+    dz1 = dh1 * gelu_grad(c["z1"])
+    dW1 = dz1.T @ c["x0"]
+    db1 = dz1.sum(axis=0)
+    g = np.concatenate([dW1.reshape(-1), db1, dW2.reshape(-1), db2, dW3, db3])
+    return L, g

@@ -62,6 +62,14 @@ EXPORTS = {
                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "csg_threshold_alpha": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_mlp_param_count": [],
+    "csg_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_mlp_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_void_p],
+    "csg_mlp_adam": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_void_p],
+    "csg_learned_diag": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "csg_workspace_bytes": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32],
     "csg_last_error": [],
 }
@@ -319,3 +327,57 @@ def precond_sgd_step(v, g, D, D_avg, zHz, k: int, beta: float, alpha: float, eta
                                       float(beta), float(alpha), float(eta), _ptr(v_out), _ptr(Dhat_out),
                                       _ptr(stats_out), _stream(stream)), "csg_precond_sgd_step")
     return v_out, stats_out
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner network
+# ---------------------------------------------------------------------------
+def mlp_param_count() -> int:
+    return int(lib().csg_mlp_param_count())
+
+
+def _f32(t, name, numel=None):
+    if t.dtype != torch.float32:
+        raise CsgError("%s must be float32" % name)
+    if numel is not None and t.numel() != numel:
+        raise CsgError("%s must have %d elements" % (name, numel))
+    return _ptr(t)
+
+
+def mlp_forward(params, X, y=None, stream=None):
+    """y = mlp(X) for X float32 [n, 3]."""
+    n = X.shape[0]
+    if y is None:
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().csg_mlp_forward(_f32(params, "params", mlp_param_count()), _f32(X, "X", 3 * n), int(n),
+                                 _f32(y, "y", n), _stream(stream)), "csg_mlp_forward")
+    return y
+
+
+def mlp_grad(params, X, T, grad=None, loss=None, stream=None):
+    """Gradient (and value) of the mean squared error of mlp(X) against T."""
+    n = X.shape[0]
+    if grad is None:
+        grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    _check(lib().csg_mlp_grad(_f32(params, "params", mlp_param_count()), _f32(X, "X", 3 * n), _f32(T, "T", n),
+                              int(n), _f32(grad, "grad", mlp_param_count()), _ptr(loss), _stream(stream)),
+           "csg_mlp_grad")
+    return grad, loss
+
+
+def mlp_adam(params, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None):
+    _check(lib().csg_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream(stream)), "csg_mlp_adam")
+
+
+def learned_diag(grid: Grid, n_images: int, lam: float, params, ctf2, cover, out=None, stream=None):
+    M = grid.M
+    if out is None:
+        out = torch.empty((M, M, M), dtype=torch.float32, device=params.device)
+    g = grid.c()
+    _check(lib().csg_learned_diag(ctypes.byref(g), int(n_images), float(lam), _ptr(params), _ptr(ctf2),
+                                  _ptr(cover), _ptr(out), _stream(stream)), "csg_learned_diag")
+    return out

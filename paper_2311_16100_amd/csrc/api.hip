@@ -354,4 +354,46 @@ int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D,
     return CSG_OK;
 }
 
+int32_t csg_mlp_param_count(void) { return (int32_t)csg::mlp_param_count(); }
+
+int csg_mlp_forward(const float *params, const float *X, int64_t n, float *y, void *stream) {
+    if (n < 0) return fail(CSG_EINVAL, "csg_mlp_forward: n must be non-negative");
+    if (n == 0) return CSG_OK;
+    if (!params || !X || !y) return fail(CSG_EINVAL, "csg_mlp_forward: params, X and y must be non-NULL");
+    CSG_TRY(csg::launch_mlp_forward(params, X, y, n, (hipStream_t)stream), "csg_mlp_forward");
+    return CSG_OK;
+}
+
+int csg_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad, double *loss_out,
+                 void *stream) {
+    if (n < 0) return fail(CSG_EINVAL, "csg_mlp_grad: n must be non-negative");
+    if (!params || !grad || !loss_out || (n > 0 && (!X || !T)))
+        return fail(CSG_EINVAL, "csg_mlp_grad: params, X, T, grad and loss_out must be non-NULL");
+    CSG_TRY(csg::launch_mlp_grad(params, X, T, n, grad, loss_out, (hipStream_t)stream), "csg_mlp_grad");
+    return CSG_OK;
+}
+
+int csg_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr, float beta1,
+                 float beta2, float eps, void *stream) {
+    if (!params || !m || !v || !grad) return fail(CSG_EINVAL, "csg_mlp_adam: buffers must be non-NULL");
+    if (step < 1) return fail(CSG_EINVAL, "csg_mlp_adam: step must be >= 1");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(CSG_EINVAL, "csg_mlp_adam: invalid hyper-parameters");
+    CSG_TRY(csg::launch_mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps, (hipStream_t)stream),
+            "csg_mlp_adam");
+    return CSG_OK;
+}
+
+int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const float *params, const float *ctf2,
+                     const float *cover, float *diag_out, void *stream) {
+    if (!grid || grid->M < 4 || grid->M > 1024 || (grid->M & 1))
+        return fail(CSG_EINVAL, "csg_learned_diag: invalid grid");
+    if (n_images < 1) return fail(CSG_EINVAL, "csg_learned_diag: n_images must be >= 1");
+    if (!params || !ctf2 || !cover || !diag_out) return fail(CSG_EINVAL, "csg_learned_diag: NULL buffer");
+    CSG_TRY(csg::launch_learned_diag(params, grid->M, (float)n_images, lambda, ctf2, cover, diag_out,
+                                     (hipStream_t)stream),
+            "csg_learned_diag");
+    return CSG_OK;
+}
+
 }  // extern "C"

@@ -60,4 +60,14 @@ hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, f
                                const float *zHz, int64_t k, float beta, float alpha, float eta, float2 *v_out,
                                float *Dhat_out, double *stats, hipStream_t st);
 
+// preconditioner network (mlp_kernels.hip)
+int mlp_param_count();
+hipError_t launch_mlp_forward(const float *params, const float *X, float *y, int64_t n, hipStream_t st);
+hipError_t launch_learned_diag(const float *params, int M, float N, float lambda, const float *ctf2,
+                               const float *cover, float *D, hipStream_t st);
+hipError_t launch_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad,
+                           double *loss, hipStream_t st);
+hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
+                           float beta2, float eps, hipStream_t st);
+
 }  // namespace csg

@@ -1,0 +1,410 @@
+// mlp_kernels.hip -- the per-voxel preconditioner network: inference and
+// training (forward, backward, Adam).  MLP 3 -> 64 -> 64 -> 1 with GELU;
+// weights are float32 masters rounded to bfloat16 when used, layer inputs
+// are rounded to bfloat16, products accumulate in float32.  The 64 x 64
+// layer and the two GEMMs of its backward pass run on the matrix cores
+// (v_mfma_f32_32x32x8_bf16): one wavefront handles a tile of 32 samples.
+//
+// MFMA 32x32x8 operand layout (wave64), lane l = 32 h + c:
+//   A (32 x 8):  lane l holds A[c][4h + q], q = 0..3
+//   B (8 x 32):  lane l holds B[4h + q][c]
+//   D (32 x 32): lane l holds D[8 (r/4) + 4h + (r%4)][c] in register r = 0..15
+//
+// Parameter vector (float32): W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3.
+#include <math.h>
+
+#include "csg_device.h"
+#include "csg_internal.h"
+
+namespace csg {
+
+constexpr int H = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + 3 * H, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
+              OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + H, NPARAM = OFF_B3 + 1;
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)(u >> 16);  // inf / nan
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// Parameters staged in LDS for a block.
+struct MlpShared {
+    unsigned short w2[H * H];  // bf16 W2[j][k]
+    float w1[H * 3];           // bf16-rounded W1
+    float b1[H];
+    float b2[H];
+    float w3[H];               // bf16-rounded W3
+    float b3;
+};
+
+__device__ void stage_params(const float *p, MlpShared &s) {
+    for (int t = threadIdx.x; t < H * H; t += blockDim.x) s.w2[t] = f2bf(p[OFF_W2 + t]);
+    for (int t = threadIdx.x; t < H * 3; t += blockDim.x) s.w1[t] = bfr(p[OFF_W1 + t]);
+    for (int t = threadIdx.x; t < H; t += blockDim.x) {
+        s.b1[t] = p[OFF_B1 + t];
+        s.b2[t] = p[OFF_B2 + t];
+        s.w3[t] = bfr(p[OFF_W3 + t]);
+    }
+    if (threadIdx.x == 0) s.b3 = p[OFF_B3];
+}
+
+// Layer 1 for the lane's sample and its 32 hidden units k = 8 st + 4 h + q;
+// returns the bf16 A operands of layer 2 and (optionally) the pre-activations.
+__device__ __forceinline__ void layer1(const MlpShared &s, const float x0[3], int hh, s16x4 a[8], float *z1) {
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 8 * st + 4 * hh + q;
+            const float z = fmaf(s.w1[k * 3 + 2], x0[2], fmaf(s.w1[k * 3 + 1], x0[1], fmaf(s.w1[k * 3], x0[0], s.b1[k])));
+            if (z1) z1[st * 4 + q] = z;
+            a[st][q] = (short)f2bf(gelu(z));
+        }
+    }
+}
+
+// Layer 2: D_nb = H1 (32 x 64) . W2^T restricted to output columns 32 nb + c.
+__device__ __forceinline__ void layer2(const MlpShared &s, const s16x4 a[8], int hh, int c, f32x16 &acc0,
+                                       f32x16 &acc1) {
+    acc0 = f32x16{0.f};
+    acc1 = f32x16{0.f};
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        const int k = 8 * st + 4 * hh;
+        s16x4 b0, b1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            b0[q] = (short)s.w2[c * H + k + q];
+            b1[q] = (short)s.w2[(32 + c) * H + k + q];
+        }
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[st], b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[st], b1, acc1, 0, 0, 0);
+    }
+}
+
+// Sum over the 32 lanes of one half-wave (lanes with the same l / 32).
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Inputs of one voxel for the fused (volume) mode: |k| / (M/2),
+// log(ctf2 / N), log(cover / N); returns false for voxels no image reaches.
+__device__ __forceinline__ bool voxel_inputs(int64_t v, int M, float invN, const float *ctf2, const float *cover,
+                                             float x0[3]) {
+    const int half = M / 2;
+    const int kx = (int)(v % M) - half, ky = (int)((v / M) % M) - half, kz = (int)(v / ((int64_t)M * M)) - half;
+    const float cv = cover[v];
+    x0[0] = sqrtf((float)(kx * kx + ky * ky + kz * kz)) / (float)half;
+    x0[1] = logf(fmaxf(ctf2[v] * invN, 1e-30f));
+    x0[2] = logf(fmaxf(cv * invN, 1e-30f));
+    return cv > 0.f;
+}
+
+// Inference.  FUSED = false: y[s] = mlp(X[s]) for n samples.  FUSED = true:
+// over the M^3 voxels, D[v] = lambda + N exp(mlp(inputs(v))) where some image
+// reaches v, else lambda.
+template <bool FUSED>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, const float *X, float *y, int64_t n,
+                                                        int M, float N, float lambda, const float *ctf2,
+                                                        const float *cover) {
+    __shared__ MlpShared s;
+    stage_params(params, s);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int hh = lane >> 5, c = lane & 31;
+    const float invN = 1.0f / N;
+    const int64_t ntiles = (n + 31) / 32;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t smp = tile * 32 + c;
+        float x0[3] = {0.f, 0.f, 0.f};
+        if (smp < n) {
+            if (FUSED) {
+                voxel_inputs(smp, M, invN, ctf2, cover, x0);
+            } else {
+                x0[0] = X[smp * 3];
+                x0[1] = X[smp * 3 + 1];
+                x0[2] = X[smp * 3 + 2];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x0[d] = bfr(x0[d]);
+        s16x4 a[8];
+        layer1(s, x0, hh, a, nullptr);
+        f32x16 acc0, acc1;
+        layer2(s, a, hh, c, acc0, acc1);
+        float out[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float h0 = bfr(gelu(acc0[r] + s.b2[c]));
+            const float h1 = bfr(gelu(acc1[r] + s.b2[32 + c]));
+            out[r] = half_sum(fmaf(s.w3[c], h0, s.w3[32 + c] * h1)) + s.b3;
+        }
+        if (c == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 8 * (r / 4) + 4 * hh + (r % 4);
+                const int64_t t = tile * 32 + i;
+                if (t < n) {
+                    if (FUSED) {
+                        const float cv = cover[t];
+                        y[t] = cv > 0.f ? lambda + N * expf(out[r]) : lambda;
+                    } else {
+                        y[t] = out[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: gradient of L = 1/n sum (y - t)^2 over a batch (straight-through
+// for the bfloat16 roundings), accumulated into grad[NPARAM]; loss += L.
+// ---------------------------------------------------------------------------
+constexpr int TW = 4;  // waves per training block
+
+struct TrainShared {
+    MlpShared p;
+    unsigned short h1t[TW][32][H];  // bf16 H1 of the tile, [sample][k]
+    unsigned short dzt[TW][32][H];  // bf16 dZ2 of the tile, [sample][j]
+    float dh[TW][32][H + 1];        // dH1, then dZ1, [sample][k]
+    float x0[TW][32][3];
+    float g[NPARAM];                // block gradient
+    double red[16];
+};
+
+__global__ __launch_bounds__(TW * 64) void mlp_grad_kernel(const float *params, const float *X, const float *T,
+                                                           int64_t n, float inv_n, float *grad, double *loss) {
+    __shared__ TrainShared s;
+    stage_params(params, s.p);
+    for (int t = threadIdx.x; t < NPARAM; t += blockDim.x) s.g[t] = 0.f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int hh = lane >> 5, c = lane & 31;
+    // per-lane accumulators kept across tiles
+    f32x16 dw2[2][2];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) dw2[jb][kb] = f32x16{0.f};
+    float dw1[3] = {0.f, 0.f, 0.f}, db1 = 0.f;  // hidden unit k = lane
+    float dw3[2] = {0.f, 0.f}, db2[2] = {0.f, 0.f}, db3 = 0.f;
+    double lsum = 0.0;
+
+    // the loop runs the same number of times in every wave of the block (it
+    // contains barriers); tiles past the end hold no valid sample and add zero
+    const int64_t ntiles = (n + 31) / 32;
+    for (int64_t bt = blockIdx.x; bt * TW < ntiles; bt += gridDim.x) {
+        const int64_t tile = bt * TW + wv;
+        const int64_t smp = tile * 32 + c;
+        const bool valid = smp < n;
+        float x0[3] = {0.f, 0.f, 0.f};
+        if (valid) {
+            x0[0] = X[smp * 3];
+            x0[1] = X[smp * 3 + 1];
+            x0[2] = X[smp * 3 + 2];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x0[d] = bfr(x0[d]);
+        if (hh == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s.x0[wv][c][d] = x0[d];
+        }
+        // ---- forward
+        s16x4 a[8];
+        float z1[32];
+        layer1(s.p, x0, hh, a, z1);
+#pragma unroll
+        for (int st = 0; st < 8; ++st)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s.h1t[wv][c][8 * st + 4 * hh + q] = (unsigned short)a[st][q];
+        f32x16 acc0, acc1;
+        layer2(s.p, a, hh, c, acc0, acc1);
+        float h2[2][16], z2[2][16], out[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            z2[0][r] = acc0[r] + s.p.b2[c];
+            z2[1][r] = acc1[r] + s.p.b2[32 + c];
+            h2[0][r] = bfr(gelu(z2[0][r]));
+            h2[1][r] = bfr(gelu(z2[1][r]));
+            out[r] = half_sum(fmaf(s.p.w3[c], h2[0][r], s.p.w3[32 + c] * h2[1][r])) + s.p.b3;
+        }
+        // ---- output layer and its gradient
+        float dy[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r / 4) + 4 * hh + (r % 4);
+            const int64_t t = tile * 32 + i;
+            const float res = t < n ? out[r] - T[t] : 0.f;
+            dy[r] = t < n ? 2.0f * res * inv_n : 0.f;
+            if (c == 0) lsum += (double)res * res * inv_n;
+            dw3[0] = fmaf(dy[r], h2[0][r], dw3[0]);
+            dw3[1] = fmaf(dy[r], h2[1][r], dw3[1]);
+            if (c == 0) db3 += dy[r];
+        }
+        // dZ2 = dy W3 gelu'(z2), D layout; its bf16 copy feeds two GEMMs
+        float dz2[2][16];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                dz2[jb][r] = dy[r] * s.p.w3[32 * jb + c] * gelu_grad(z2[jb][r]);
+                db2[jb] += dz2[jb][r];
+                const int i = 8 * (r / 4) + 4 * hh + (r % 4);
+                s.dzt[wv][i][32 * jb + c] = f2bf(dz2[jb][r]);
+            }
+        __syncthreads();  // h1t / dzt / x0 of every wave written
+        // ---- dW2 += dZ2^T H1: rows j (A from dZ2 in D layout), K = samples
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                s16x4 av;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) av[q] = (short)f2bf(dz2[jb][4 * s4 + q]);
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    s16x4 bv;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bv[q] = (short)s.h1t[wv][8 * s4 + 4 * hh + q][32 * kb + c];
+                    dw2[jb][kb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, dw2[jb][kb], 0, 0, 0);
+                }
+            }
+        }
+        // ---- dH1 = dZ2 W2: rows = samples (A from dzt), K = j
+        f32x16 dh[2];
+        dh[0] = f32x16{0.f};
+        dh[1] = f32x16{0.f};
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            s16x4 av;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[q] = (short)s.dzt[wv][c][8 * st + 4 * hh + q];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                s16x4 bv;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bv[q] = (short)s.p.w2[(8 * st + 4 * hh + q) * H + 32 * kb + c];
+                dh[kb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, dh[kb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) s.dh[wv][8 * (r / 4) + 4 * hh + (r % 4)][32 * kb + c] = dh[kb][r];
+        __syncthreads();
+        // dZ1 = dH1 gelu'(z1) in the layer-1 layout, written back in place
+#pragma unroll
+        for (int st = 0; st < 8; ++st)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 8 * st + 4 * hh + q;
+                s.dh[wv][c][k] *= gelu_grad(z1[st * 4 + q]);
+            }
+        __syncthreads();
+        // dW1[k][.] and db1[k] for k = lane, summed over the tile's samples
+        for (int i = 0; i < 32; ++i) {
+            const float d = s.dh[wv][i][lane];
+            db1 += d;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) dw1[e] = fmaf(d, s.x0[wv][i][e], dw1[e]);
+        }
+        __syncthreads();  // LDS tile buffers are rewritten by the next tile
+    }
+    // ---- fold the per-lane accumulators into the block gradient
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = 32 * jb + 8 * (r / 4) + 4 * hh + (r % 4);
+                atomicAdd(&s.g[OFF_W2 + j * H + 32 * kb + c], dw2[jb][kb][r]);
+            }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) atomicAdd(&s.g[OFF_W1 + lane * 3 + e], dw1[e]);
+    atomicAdd(&s.g[OFF_B1 + lane], db1);
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+        atomicAdd(&s.g[OFF_W3 + 32 * jb + c], dw3[jb]);
+        atomicAdd(&s.g[OFF_B2 + 32 * jb + c], db2[jb]);
+    }
+    if (c == 0) atomicAdd(&s.g[OFF_B3], db3);
+    const double lt = block_sum(lsum, s.red);  // contains a barrier
+    for (int t = threadIdx.x; t < NPARAM; t += blockDim.x) atomicAdd(&grad[t], s.g[t]);
+    if (threadIdx.x == 0) atomicAdd(loss, lt);
+}
+
+// Adam (Kingma & Ba) on the float32 master parameters.
+__global__ void mlp_adam_kernel(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
+                                float beta2, float eps) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NPARAM) return;
+    const float g = grad[t];
+    const float mt = beta1 * m[t] + (1.0f - beta1) * g;
+    const float vt = beta2 * v[t] + (1.0f - beta2) * g * g;
+    m[t] = mt;
+    v[t] = vt;
+    const float mh = mt / (1.0f - powf(beta1, (float)step));
+    const float vh = vt / (1.0f - powf(beta2, (float)step));
+    params[t] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+int mlp_param_count() { return NPARAM; }
+
+hipError_t launch_mlp_forward(const float *params, const float *X, float *y, int64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = ((n + 31) / 32 + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((mlp_infer_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, st, params, X, y, n, 0, 1.0f,
+                       0.0f, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_diag(const float *params, int M, float N, float lambda, const float *ctf2,
+                               const float *cover, float *D, hipStream_t st) {
+    const int64_t n = (int64_t)M * M * M;
+    int64_t blocks = ((n + 31) / 32 + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((mlp_infer_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, st, params, nullptr, D, n, M, N,
+                       lambda, ctf2, cover);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad,
+                           double *loss, hipStream_t st) {
+    hipError_t e = launch_fill_f32(grad, NPARAM, 0.0f, st);
+    if (e != hipSuccess) return e;
+    e = launch_fill_f64(loss, 1, 0.0, st);
+    if (e != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    int64_t blocks = ((n + 31) / 32 + TW * 4 - 1) / (TW * 4);  // about four tiles per wave
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(TW * 64), 0, st, params, X, T, n,
+                       1.0f / (float)n, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
+                           float beta2, float eps, hipStream_t st) {
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, st, params, m, v, grad, step, lr,
+                       beta1, beta2, eps);
+    return hipGetLastError();
+}
+
+}  // namespace csg
