@@ -166,6 +166,16 @@ int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D,
                          const float *zHz, int64_t k, float beta, float alpha, float eta,
                          float *v_out, float *Dhat_out, double *stats_out, void *stream);
 
+/* Fast per-voxel sums for the learned preconditioner, one pass over the
+ * images (trilinear grids only):
+ *   accum[k].re += sum_i sum_j C_ij^2 w_ijk   (as ctf2_accum of csg_features)
+ *   accum[k].im += sum_i sum_j w_ijk          (interpolation weight reaching
+ *                  k: for nearest-neighbour stencils without repeated hits
+ *                  this is the size of the voxel mapping set |Omega_k|)
+ *   accum device complex [M^3]; workspace as for csg_backproject. */
+int csg_feature_sums(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                     float *accum, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Threshold of the preconditioner, eq. (thresh value) (Sec. 3.3): the
  * expected Hessian entry at the maximum radius R = round(r_max),
  *   alpha = (P_x(R) / P_v(R)) * sum_{i=1}^N C_i(R)^2 + lambda,
@@ -214,8 +224,9 @@ int csg_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t s
 /* Predicted Hessian diagonal over the M^3 grid of `grid`:
  *   diag_out[k] = lambda + N exp(mlp(|k| / (M/2), log(ctf2[k]/N), log(cover[k]/N)))
  * where cover[k] > 0, and lambda where no image reaches voxel k (there the
- * data part of the diagonal is exactly zero).  ctf2 and cover are the
- * outputs of csg_features over the N = n_images images of the data set. */
+ * data part of the diagonal is exactly zero).  ctf2 and cover are per-voxel
+ * sums over the N = n_images images of the data set, the same kind the
+ * network was trained on (csg_feature_sums: real and imaginary parts). */
 int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const float *params,
                      const float *ctf2, const float *cover, float *diag_out, void *stream);
 

@@ -62,6 +62,7 @@ EXPORTS = {
                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "csg_threshold_alpha": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_feature_sums": [ctypes.c_void_p] * 4 + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "csg_mlp_param_count": [],
     "csg_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "csg_mlp_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -313,6 +314,21 @@ def threshold_alpha(grid: Grid, optics: Optics, rot, defocus, lam: float, alpha_
     _check(lib().csg_threshold_alpha(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), float(lam), _ptr(alpha_out),
                                      _stream(stream)), "csg_threshold_alpha")
     return alpha_out
+
+
+def feature_sums(grid: Grid, optics: Optics, rot, defocus, accum=None, workspace=None, stream=None):
+    """accum.real += sum C^2 w, accum.imag += sum w (complex64 [M,M,M])."""
+    M = grid.M
+    p = _poses(rot, defocus)
+    if accum is None:
+        accum = torch.zeros((M, M, M), dtype=torch.complex64, device=rot.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_BACKPROJECT, rot.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_feature_sums(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(accum, (M, M, M), "accum"),
+                                  wp, wn, _stream(stream)), "csg_feature_sums")
+    return accum
 
 
 def precond_sgd_step(v, g, D, D_avg, zHz, k: int, beta: float, alpha: float, eta: float, v_out=None,

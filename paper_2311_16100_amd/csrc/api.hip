@@ -337,6 +337,23 @@ int csg_threshold_alpha(const csg_grid *grid, const csg_optics *optics, const cs
     return CSG_OK;
 }
 
+int csg_feature_sums(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, float *accum,
+                     void *workspace, size_t workspace_bytes, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (g.interp != 1) return fail(CSG_EINVAL, "csg_feature_sums: trilinear grids only");
+    if (!accum) return fail(CSG_EINVAL, "csg_feature_sums: accum is NULL");
+    if (poses->n == 0) return CSG_OK;
+    const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_feature_sums"))) return rc;
+    CSG_TRY(csg::launch_brick_feature_sums(g, poses->rot, poses->defocus_A, poses->n, (float2 *)accum, workspace,
+                                           (hipStream_t)stream),
+            "csg_feature_sums");
+    return CSG_OK;
+}
+
 int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D, float *D_avg, const float *zHz,
                          int64_t k, float beta, float alpha, float eta, float *v_out, float *Dhat_out,
                          double *stats_out, void *stream) {

@@ -31,6 +31,8 @@
 //   kBBackproject  accum += scale C^p img
 //   kBGradient     r = C P v - x; loss (owner); accum += scale C r
 //   kBHvp          accum += scale C^2 P z
+//   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
+//                  sum of every voxel (no image is read)
 #include "csg_device.h"
 #include "csg_internal.h"
 
@@ -54,7 +56,7 @@ constexpr int CHUNK_ADJ = 256;   // images per work item of the adjoint modes
 constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
-enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3 };
+enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4 };
 
 struct BrickArgs {
     Geom g;
@@ -384,6 +386,8 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
                 } else if (MODE == kBHvp) {
                     const float fct = a.scale * C * C;
                     val = make_float2(fct * acc.x, fct * acc.y);
+                } else if (MODE == kBFeatures) {
+                    val = make_float2(C * C, 1.0f);
                 }
                 if (SCATTER) {
                     // corners inside the brick; a corner beyond the grid edge
@@ -535,6 +539,13 @@ hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *d
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_gradient_atomic(g, rot, defocus, n, vol, x, scale, accum, loss, st);
     return run_brick_mode<kBGradient>(g, rot, defocus, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
+}
+
+hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                     float2 *accum, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
+    return run_brick_mode<kBFeatures>(g, rot, defocus, n, nullptr, nullptr, nullptr, accum, nullptr, 1.0f, 0, ws, st);
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,

@@ -1,0 +1,274 @@
+"""Synthetic data sets, the ground truth v* and the time-to-accuracy runs of
+the preconditioned SGD arms (Sec. 4 of the paper, with synthetic data in
+place of its EMPIAR set).
+
+Data: x_i = C_i P_i v_true + eta_i (eq. (fwd model)), v_true the Fourier
+transform of a sum of Gaussian blobs, eta complex Gaussian of variance sigma^2
+on the disk, sigma^2 = signal power / SNR.  The regularisation follows the
+MAP reading lambda = sigma^2 / tau^2 (Sec. 3), tau^2 the mean power of v_true
+on the ball; noise-free sets use a small lambda relative to the threshold.
+
+Ground truth: v* solves H v = b (eq. (lin sys)) with all N images; it is
+found with conjugate gradients (the paper uses L-BFGS on the same quadratic,
+Sec. 4.1).  The CG vector algebra is ordinary torch arithmetic (evaluation,
+not the method); every H v product is the library's HVP.
+
+Arms (all share Algorithm 1's loop, the Armijo rule and the step schedule):
+  plain        D_hat = 1
+  hutchinson   D estimated on the fly (Algorithm 1)
+  learned      D_hat = max(D_pred, alpha) from the preconditioner network
+  exact        D_hat = max(diag H, alpha), diag H from one squared-weight
+               backprojection (the "precomputed" arm of Sec. 4)
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+import synth
+
+from . import binding as B
+from .sgd import Alg1Config, Alg1Runner
+
+CHUNK = 2048  # images per library call when sweeping a whole data set
+
+
+@dataclass
+class Dataset:
+    grid: B.Grid
+    optics: B.Optics
+    rot: torch.Tensor
+    defocus: torch.Tensor
+    x: torch.Tensor
+    v_true: torch.Tensor
+    sigma2: float
+    lam: float
+    seed: int
+
+    @property
+    def N(self) -> int:
+        return self.rot.shape[0]
+
+    @property
+    def M(self) -> int:
+        return self.grid.M
+
+
+def disk_mask(M: int, r: float, device) -> torch.Tensor:
+    ax = torch.arange(M, device=device) - M // 2
+    return (ax[:, None] ** 2 + ax[None, :] ** 2) <= r * r
+
+
+def ball_mask(M: int, r: float, device) -> torch.Tensor:
+    ax = torch.arange(M, device=device) - M // 2
+    return (ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2) <= r * r
+
+
+def make_dataset(M: int, N: int, n_blobs: int, seed: int, snr: float, defocus_um=(1.0, 3.0), poses="uniform",
+                 kappa: float = 10.0, device="cuda", lam: float | None = None) -> Dataset:
+    grid, optics = B.Grid(M), B.Optics()
+    v_true = torch.from_numpy(synth.blob_volume(M, n_blobs, seed)).to(device)
+    rot = synth.vmf_rotations(N, kappa, seed) if poses == "vmf" else synth.uniform_rotations(N, seed)
+    rot = torch.from_numpy(rot).to(device)
+    df = torch.from_numpy(synth.defocus_values(N, defocus_um[0], defocus_um[1], seed)).to(device)
+    x = torch.empty((N, M, M), dtype=torch.complex64, device=device)
+    for s in range(0, N, CHUNK):
+        e = min(N, s + CHUNK)
+        B.project(grid, optics, rot[s:e].contiguous(), df[s:e].contiguous(), v_true, out=x[s:e])
+    disk = disk_mask(M, grid.rmax, device)
+    pilot = x[: min(N, 1024)]
+    power = float((torch.abs(pilot) ** 2)[:, disk].mean().item())
+    ball = ball_mask(M, grid.rmax, device)
+    tau2 = float((torch.abs(v_true) ** 2)[ball].mean().item())
+    if math.isfinite(snr) and snr > 0:
+        sigma2 = power / snr
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed) * 1000 + synth.STREAM_NOISE)
+        for s in range(0, N, CHUNK):
+            e = min(N, s + CHUNK)
+            noise = torch.randn((e - s, M, M, 2), generator=gen, device=device) * math.sqrt(sigma2 / 2)
+            x[s:e] += torch.view_as_complex(noise) * disk
+        lam_ = sigma2 / tau2 if lam is None else lam
+    else:
+        sigma2 = 0.0
+        lam_ = 1e-3 if lam is None else lam
+    return Dataset(grid, optics, rot, df, x, v_true, sigma2, float(lam_), seed)
+
+
+def full_hvp(ds: Dataset, z: torch.Tensor, ws=None) -> torch.Tensor:
+    """H z over all N images (scale 1)."""
+    out = ds.lam * z
+    for s in range(0, ds.N, CHUNK):
+        e = min(ds.N, s + CHUNK)
+        h = B.hvp(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), z, 1.0, 0.0,
+                  workspace=ws)
+        out = out + h
+    return out
+
+
+def rhs(ds: Dataset) -> torch.Tensor:
+    """b = sum_i P_i^T C_i x_i (eq. (lin sys) with the CTF)."""
+    b = torch.zeros_like(ds.v_true)
+    for s in range(0, ds.N, CHUNK):
+        e = min(ds.N, s + CHUNK)
+        B.backproject(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(),
+                      ds.x[s:e].contiguous(), ctf_power=1, accum=b)
+    return b
+
+
+def exact_diagonal(ds: Dataset, scale: float = 1.0) -> torch.Tensor:
+    """diag H = lambda + sum_ij C_ij^2 w_ijk^2 over all N images."""
+    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.x.device)
+    for s in range(0, ds.N, CHUNK):
+        e = min(ds.N, s + CHUNK)
+        d += B.exact_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), scale, 0.0)
+    return d + ds.lam
+
+
+def ground_truth(ds: Dataset, tol: float = 1e-6, max_iter: int = 500):
+    """v* = H^{-1} b by Jacobi-preconditioned CG (double-precision dots)."""
+    b = rhs(ds)
+    dinv = 1.0 / exact_diagonal(ds)
+    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_GRADIENT, ds.x.device)
+    x = torch.zeros_like(b)
+    r = b.clone()
+    z = dinv * r
+    p = z.clone()
+    rz = torch.vdot(r.reshape(-1).to(torch.complex128), z.reshape(-1).to(torch.complex128)).real
+    bn = torch.linalg.vector_norm(b.to(torch.complex128))
+    it = 0
+    for it in range(max_iter):
+        if torch.linalg.vector_norm(r.to(torch.complex128)) <= tol * bn:
+            break
+        Ap = full_hvp(ds, p, ws)
+        alpha = rz / torch.vdot(p.reshape(-1).to(torch.complex128), Ap.reshape(-1).to(torch.complex128)).real
+        x = x + (alpha * p.to(torch.complex128)).to(torch.complex64)
+        r = r - (alpha * Ap.to(torch.complex128)).to(torch.complex64)
+        z = dinv * r
+        rz_new = torch.vdot(r.reshape(-1).to(torch.complex128), z.reshape(-1).to(torch.complex128)).real
+        p = z + (rz_new / rz).to(torch.float32) * p
+        rz = rz_new
+    res = float((torch.linalg.vector_norm(r.to(torch.complex128)) / bn).item())
+    return x, it, res
+
+
+def rel_error(v, v_star, ball) -> float:
+    d = (v - v_star)[ball]
+    return float((torch.linalg.vector_norm(d) / torch.linalg.vector_norm(v_star[ball])).item())
+
+
+@dataclass
+class RunResult:
+    arm: str
+    reached: bool
+    iterations: int
+    seconds: float
+    setup_seconds: float
+    errors: list = field(default_factory=list)  # (iteration, seconds, ball error, high-band error)
+    halvings: int = 0
+    capped: int = 0
+    note: str = ""
+
+    @property
+    def total_seconds(self) -> float:
+        return self.setup_seconds + self.seconds
+
+
+def high_band_mask(M: int, r_max: float, device) -> torch.Tensor:
+    """Voxels with M/4 <= |k| <= r_max: the high-resolution half of the ball."""
+    ax = torch.arange(M, device=device) - M // 2
+    k2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    return (k2 >= (M / 4) ** 2) & (k2 <= r_max * r_max)
+
+
+def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
+            eval_every: int = 5, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
+            seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball") -> RunResult:
+    """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
+    the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target.
+    `decay_epochs` > 0 halves the step-size cap every that many epochs
+    (identically in every arm).  Wall time counts iterations and error
+    evaluations."""
+    dev = ds.x.device
+    scale = ds.N / batch
+    alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
+    cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17)
+    kind = {"plain": "plain", "hutchinson": "hutchinson", "learned": "fixed", "exact": "fixed"}[arm]
+    v0 = torch.zeros_like(v_star)
+    run = Alg1Runner(ds.grid, ds.optics, kind, scale, ds.lam, alpha, cfg, v0, D_fixed=D_fixed, batch=batch)
+    ball = ball_mask(ds.M, ds.grid.rmax, dev)
+    high = high_band_mask(ds.M, ds.grid.rmax, dev)
+    res = RunResult(arm, False, 0, 0.0, setup_seconds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    eta_cap = eta0
+    for epoch in range(max_epochs):
+        if decay_epochs and epoch > 0 and epoch % decay_epochs == 0:
+            eta_cap *= 0.5
+            run.state.eta = min(run.state.eta, eta_cap)
+        perm = torch.from_numpy(synth.epoch_permutation(ds.N, seed, epoch)).to(dev)
+        for s in range(0, ds.N - batch + 1, batch):
+            idx = perm[s:s + batch]
+            res.halvings += run.iteration(ds.rot[idx].contiguous(), ds.defocus[idx].contiguous(),
+                                          ds.x[idx].contiguous())
+            it += 1
+            if it % eval_every == 0:
+                eb = rel_error(run.state.v, v_star, ball)
+                eh = rel_error(run.state.v, v_star, high)
+                el = time.perf_counter() - t0
+                res.errors.append((it, el, eb, eh))
+                if (eb if stop_on == "ball" else eh) <= target:
+                    res.reached, res.iterations, res.seconds = True, it, el
+                    res.capped = run.state.capped
+                    return res
+                if el > time_limit:
+                    res.iterations, res.seconds, res.note = it, el, "time limit"
+                    res.capped = run.state.capped
+                    return res
+    res.iterations, res.seconds, res.note = it, time.perf_counter() - t0, "epoch limit"
+    res.capped = run.state.capped
+    return res
+
+
+def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinson", "learned", "exact"),
+                 target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print, **kw):
+    """Time to `target` for each arm on the same data set and ground truth.
+    Setup time is charged to the arm that needs it: the exact arm one
+    squared-weight pass over the data; the learned arm the feature pass, the
+    network and the judge (and, if the judge rejects the prediction, it
+    continues as the Hutchinson arm)."""
+    from . import learned as L
+    v_star, cg_it, cg_res = ground_truth(ds)
+    out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
+    for arm in arms:
+        D = None
+        setup = 0.0
+        note = ""
+        run_as = arm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if arm == "exact":
+            D = exact_diagonal(ds)
+        elif arm == "learned":
+            if params is None:
+                continue
+            ctf2, cover = L.features(ds)
+            D = L.predict(ds, params, ctf2, cover)
+            err = L.judge(ds, D)
+            note = "judge %.3f" % err
+            if not math.isfinite(err) or err > judge_threshold:
+                run_as, D, note = "hutchinson", None, note + " -> fallback to hutchinson"
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        r = run_arm(ds, v_star, run_as, batch, target=target, D_fixed=D, setup_seconds=setup, stop_on=stop_on, **kw)
+        r.arm, r.note = arm, (r.note + " " + note).strip()
+        out["arms"][arm] = r
+        if log:
+            log("  %-10s reached=%s it=%d run=%.3fs setup=%.3fs total=%.3fs %s" % (
+                arm, r.reached, r.iterations, r.seconds, r.setup_seconds, r.total_seconds, r.note))
+    return out

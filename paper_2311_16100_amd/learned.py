@@ -1,0 +1,151 @@
+"""Learned preconditioner: a per-voxel regression of the Hessian diagonal
+(the quantity Hutchinson's estimator targets, Sec. 3.2) from cheap features,
+used in place of the on-the-fly estimate of Algorithm 1, with a short
+Hutchinson estimate as judge and the Hutchinson arm as fallback.
+
+Features of voxel k over the N images of a data set (csg_feature_sums):
+  |k| / (M/2),  log(F2_k / N),  log(F3_k / N)
+F2_k = sum_ij C_ij^2 w_ijk (CTF^2 weight), F3_k = sum_ij w_ijk, the
+interpolation weight that reaches k (the pose coverage: for nearest-neighbour
+stencils it counts the voxel mapping set of Sec. 3.1).
+Target: log((D_k - lambda) / N), D the Hutchinson estimate with many probes.
+Prediction: D_k = lambda + N exp(net(features)) (csg_learned_diag).
+
+Training runs on the GPU through csg_mlp_grad / csg_mlp_adam.  Assembling
+the training set (selecting voxels, taking logs) is host-side torch
+arithmetic on the library's outputs.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+import synth
+
+from . import binding as B
+from .experiment import CHUNK, Dataset, ball_mask
+
+
+def features(ds: Dataset):
+    """(F2, F3) over all images of the data set in one scatter pass
+    (csg_feature_sums): F2 = sum C^2 w, F3 = sum w."""
+    acc = torch.zeros((ds.M,) * 3, dtype=torch.complex64, device=ds.x.device)
+    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
+    for s in range(0, ds.N, CHUNK):
+        e = min(ds.N, s + CHUNK)
+        B.feature_sums(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), acc, workspace=ws)
+    return acc.real.contiguous(), acc.imag.contiguous()
+
+
+def hutchinson_full(ds: Dataset, n_probe: int, seed: int, n_images: int | None = None, probe0: int = 0):
+    """Hutchinson estimate of diag H over the data set (or an unbiased
+    estimate from its first n_images images, rescaled by N / n_images)."""
+    n = ds.N if n_images is None else min(ds.N, n_images)
+    scale = ds.N / n
+    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.x.device)
+    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_HUTCHINSON, ds.x.device)
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        d += B.hutchinson_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(),
+                               n_probe, seed, scale, 0.0, probe0=probe0, workspace=ws)
+    return d + ds.lam
+
+
+def inputs(M: int, N: int, ctf2: torch.Tensor, cover: torch.Tensor) -> torch.Tensor:
+    dev = ctf2.device
+    ax = (torch.arange(M, device=dev) - M // 2).float()
+    k = torch.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2) / (M // 2)
+    x1 = torch.log(torch.clamp(ctf2 / N, min=1e-30))
+    x2 = torch.log(torch.clamp(cover / N, min=1e-30))
+    return torch.stack([k, x1, x2], dim=-1).reshape(-1, 3).contiguous()
+
+
+@dataclass
+class TrainingSet:
+    X: torch.Tensor  # float32 [n, 3]
+    T: torch.Tensor  # float32 [n]
+
+
+def training_set(ds: Dataset, n_probe: int = 200, seed: int = 0, max_samples: int = 200_000) -> TrainingSet:
+    ctf2, cover = features(ds)
+    D = hutchinson_full(ds, n_probe, seed)
+    X = inputs(ds.M, ds.N, ctf2, cover)
+    data = (D - ds.lam).reshape(-1)
+    ok = (cover.reshape(-1) > 0) & (data > 0)
+    idx = torch.nonzero(ok).reshape(-1)
+    if idx.numel() > max_samples:
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        idx = idx[torch.randperm(idx.numel(), generator=g)[:max_samples].to(idx.device)]
+    T = torch.log(data[idx] / ds.N).float().contiguous()
+    return TrainingSet(X[idx].contiguous(), T)
+
+
+def train(sets, steps: int = 2000, batch: int = 8192, lr: float = 3e-3, seed: int = 0, device="cuda", log=None):
+    """Adam on the mean squared error over the union of training sets."""
+    X = torch.cat([s.X for s in sets]).contiguous()
+    T = torch.cat([s.T for s in sets]).contiguous()
+    n = X.shape[0]
+    g = np.random.default_rng([seed, synth.STREAM_MLP])
+    # He-style initialisation of the float32 master weights
+    H = 64
+    p = np.zeros(B.mlp_param_count(), np.float32)
+    o = 0
+    p[o:o + 3 * H] = g.standard_normal(3 * H) * math.sqrt(2.0 / 3); o += 3 * H
+    o += H
+    p[o:o + H * H] = g.standard_normal(H * H) * math.sqrt(2.0 / H); o += H * H
+    o += H
+    p[o:o + H] = g.standard_normal(H) * math.sqrt(1.0 / H); o += H
+    p[o] = float(T.mean().item())
+    params = torch.from_numpy(p).to(device)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (min(batch, n),), generator=gen, device=device)
+        grad, loss = B.mlp_grad(params, X[idx].contiguous(), T[idx].contiguous())
+        lr_t = lr * (0.5 * (1 + math.cos(math.pi * step / steps)))  # cosine schedule
+        B.mlp_adam(params, m, v, grad, step, lr_t)
+        if step % 200 == 0 or step == steps:
+            hist.append((step, loss.item()))
+            if log:
+                log("  mlp step %d loss %.4e" % (step, hist[-1][1]))
+    return params, hist
+
+
+def predict(ds: Dataset, params: torch.Tensor, ctf2=None, cover=None):
+    if ctf2 is None:
+        ctf2, cover = features(ds)
+    return B.learned_diag(ds.grid, ds.N, ds.lam, params, ctf2, cover)
+
+
+def shell_means(d: torch.Tensor, M: int) -> torch.Tensor:
+    dev = d.device
+    ax = torch.arange(M, device=dev) - M // 2
+    r = torch.round(torch.sqrt((ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2).float()))
+    r = r.long().reshape(-1)
+    nsh = M // 2
+    m = r < nsh
+    sums = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m], d.reshape(-1)[m].double())
+    cnt = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m], torch.ones_like(r[m], dtype=torch.float64))
+    return sums / cnt
+
+
+def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 8, n_images: int = 4096, seed: int = 99):
+    """Relative L2 error between the Fourier-shell means of the prediction and
+    of a short Hutchinson estimate (n_probe probes over n_images images,
+    rescaled to the full data set).  Shell means average out the probe noise
+    of a short estimate."""
+    Dh = hutchinson_full(ds, n_probe, seed, n_images=n_images, probe0=1_000_000)
+    a, b = shell_means(D_pred, ds.M), shell_means(Dh, ds.M)
+    return float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item())
+
+
+def diag_rel_error(D_a: torch.Tensor, D_b: torch.Tensor, ds: Dataset) -> float:
+    ball = ball_mask(ds.M, ds.grid.rmax, D_a.device)
+    return float((torch.linalg.vector_norm((D_a - D_b)[ball]) / torch.linalg.vector_norm(D_b[ball])).item())

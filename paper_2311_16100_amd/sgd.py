@@ -41,6 +41,7 @@ class Alg1State:
     eta: float
     k: int = 0
     halvings: list = field(default_factory=list)
+    capped: int = 0  # iterations whose line search hit max_halvings
 
 
 class Alg1Runner:
@@ -95,10 +96,13 @@ class Alg1Runner:
             f1 = self.scale * l1 + 0.5 * self.lam * vn2
             if f1 <= f0 - cfg.c * eta * gn:
                 break
+            if halvings >= cfg.max_halvings:
+                # the decrease is below the resolution of the minibatch loss:
+                # keep the (tiny) step rather than loop on rounding noise
+                st.capped += 1
+                break
             eta *= 0.5
             halvings += 1
-            if halvings > cfg.max_halvings:
-                raise RuntimeError("Armijo line search did not terminate after %d halvings" % halvings)
         st.v, self.v_new = self.v_new, st.v
         st.eta = eta
         st.halvings.append(halvings)

@@ -180,6 +180,20 @@ def test_exact_diag_and_features_parity(b, interp):
     assert np.array_equal(f3.cpu().numpy(), w3.astype(np.float32))
 
 
+def test_feature_sums_parity(b):
+    # sum C^2 w and sum w are backprojections of an all-ones image stack with
+    # the CTF squared and with no CTF
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=300, seed=33)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df = to_dev(P.rot, P.defocus)
+    acc = b.feature_sums(g, o, rot, df).cpu().numpy()
+    ones = np.ones((P.n, 36, 36), np.complex128)
+    assert rel(acc.real, oracle.backproject(grid_o, opt_o, P, ones, ctf_power=2).real) <= 1e-5
+    assert rel(acc.imag, oracle.backproject(grid_o, opt_o, P, ones, ctf_power=0).real) <= 1e-5
+    f2, _ = oracle.features(grid_o, opt_o, P)
+    assert rel(acc.real, f2) <= 1e-5
+
+
 def test_precond_step_parity(b):
     n = 36 ** 3 + 5
     g0 = np.random.default_rng(3)
