@@ -146,9 +146,11 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
 
 /* Exact diagonal of the minibatch Hessian: diag_out = scale * sum_ij C_ij^2
  * w_ijk^2 + lambda (squared interpolation weights; eq. (hessian) with eq.
- * (def tri interp)).  diag_out device float [M^3], overwritten. */
+ * (def tri interp)).  diag_out device float [M^3], overwritten; workspace as for
+ * csg_backproject. */
 int csg_exact_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
-                   float scale, float lambda, float *diag_out, void *stream);
+                   float scale, float lambda, float *diag_out, void *workspace,
+                   size_t workspace_bytes, void *stream);
 
 /* One preconditioned SGD step of Algorithm 1 (Sec. 3.4), elementwise over
  * nvox voxels:

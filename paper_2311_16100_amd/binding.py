@@ -56,7 +56,8 @@ EXPORTS = {
     "csg_hutchinson_diag": [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_float,
                                                     ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_size_t, ctypes.c_void_p],
-    "csg_exact_diag": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
+    "csg_exact_diag": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_size_t, ctypes.c_void_p],
     "csg_features": [ctypes.c_void_p] * 5 + [ctypes.c_void_p],
     "csg_precond_sgd_step": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -281,14 +282,18 @@ def hutchinson_diag(grid: Grid, optics: Optics, rot, defocus, n_probe: int, seed
     return diag_out
 
 
-def exact_diag(grid: Grid, optics: Optics, rot, defocus, scale: float, lam: float, diag_out=None, stream=None):
+def exact_diag(grid: Grid, optics: Optics, rot, defocus, scale: float, lam: float, diag_out=None, workspace=None,
+               stream=None):
     M = grid.M
     p = _poses(rot, defocus)
     if diag_out is None:
         diag_out = torch.empty((M, M, M), dtype=torch.float32, device=rot.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_BACKPROJECT, rot.device)
     g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
     _check(lib().csg_exact_diag(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), float(scale), float(lam),
-                                _ptr(diag_out), _stream(stream)), "csg_exact_diag")
+                                _ptr(diag_out), wp, wn, _stream(stream)), "csg_exact_diag")
     return diag_out
 
 

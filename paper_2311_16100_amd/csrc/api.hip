@@ -272,16 +272,19 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
 }
 
 int csg_exact_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, float scale, float lambda,
-                   float *diag_out, void *stream) {
+                   float *diag_out, void *workspace, size_t workspace_bytes, void *stream) {
     csg::Geom g;
     int rc = make_geom(grid, optics, &g);
     if (rc) return rc;
     if ((rc = check_poses(poses))) return rc;
     if (!diag_out) return fail(CSG_EINVAL, "csg_exact_diag: diag_out is NULL");
+    const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_exact_diag"))) return rc;
     hipStream_t st = (hipStream_t)stream;
     CSG_TRY(csg::launch_fill_f32(diag_out, nvox_of(g), lambda, st), "csg_exact_diag");
     if (poses->n > 0)
-        CSG_TRY(csg::launch_sq_diag(g, poses->rot, poses->defocus_A, poses->n, scale, diag_out, st), "csg_exact_diag");
+        CSG_TRY(csg::launch_brick_sq_diag(g, poses->rot, poses->defocus_A, poses->n, scale, diag_out, workspace, st),
+                "csg_exact_diag");
     return CSG_OK;
 }
 

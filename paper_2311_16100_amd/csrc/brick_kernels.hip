@@ -33,6 +33,8 @@
 //   kBHvp          accum += scale C^2 P z
 //   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
 //                  sum of every voxel (no image is read)
+//   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
+//                  Hessian (real accumulator; no image is read)
 #include "csg_device.h"
 #include "csg_internal.h"
 
@@ -56,7 +58,7 @@ constexpr int CHUNK_ADJ = 256;   // images per work item of the adjoint modes
 constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
-enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4 };
+enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5 };
 
 struct BrickArgs {
     Geom g;
@@ -67,6 +69,7 @@ struct BrickArgs {
     const float2 *img;  // x (project subtract / gradient) or adjoint input
     float2 *out;        // projected images
     float2 *accum;      // adjoint target
+    float *accum_real;  // real target (squared-weight diagonal)
     double *loss;
     float scale;
     int ctf_power;
@@ -388,6 +391,8 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
                     val = make_float2(fct * acc.x, fct * acc.y);
                 } else if (MODE == kBFeatures) {
                     val = make_float2(C * C, 1.0f);
+                } else if (MODE == kBSqDiag) {
+                    val = make_float2(a.scale * C * C, 0.0f);
                 }
                 if (SCATTER) {
                     // corners inside the brick; a corner beyond the grid edge
@@ -401,8 +406,12 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
                             (unsigned)lz < (unsigned)BS) {
                             const float w = wx[ax] * wy[ay] * wz[az];
                             const int li = lb + az * AP + ay * AR + ax;
-                            atomicAdd(&acc_re[li], (double)(w * val.x));
-                            atomicAdd(&acc_im[li], (double)(w * val.y));
+                            if (MODE == kBSqDiag) {
+                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                            } else {
+                                atomicAdd(&acc_re[li], (double)(w * val.x));
+                                atomicAdd(&acc_im[li], (double)(w * val.y));
+                            }
                         }
                     }
                 }
@@ -418,6 +427,12 @@ __global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
             if (!(qx < M && qy < M && qz < M)) continue;
             const int li = tz * AP + ty * AR + tx;
             const float re = (float)acc_re[li], im = (float)acc_im[li];
+            if (MODE == kBSqDiag) {
+                float *pr = a.accum_real + ((int64_t)qz * M + qy) * M + qx;
+                if (single) *pr += re;
+                else if (re != 0.f) atomicAdd(pr, re);
+                continue;
+            }
             float2 *p = a.accum + ((int64_t)qz * M + qy) * M + qx;
             if (single) {
                 float2 v = *p;
@@ -469,7 +484,7 @@ size_t brick_workspace_bytes(int M, int64_t n) {
 template <int MODE>
 static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *src,
                                  const float2 *img, float2 *out, float2 *accum, double *loss, float scale,
-                                 int ctf_power, void *ws, hipStream_t st) {
+                                 int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr) {
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
@@ -492,6 +507,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.img = img ? img + s0 * img_stride : nullptr;
         a.out = out ? out + s0 * img_stride : nullptr;
         a.accum = accum;
+        a.accum_real = accum_real;
         a.loss = loss;
         a.scale = scale;
         a.ctf_power = ctf_power;
@@ -546,6 +562,14 @@ hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const floa
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
     return run_brick_mode<kBFeatures>(g, rot, defocus, n, nullptr, nullptr, nullptr, accum, nullptr, 1.0f, 0, ws, st);
+}
+
+hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
+                                float *diag, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return launch_sq_diag(g, rot, defocus, n, scale, diag, st);
+    return run_brick_mode<kBSqDiag>(g, rot, defocus, n, nullptr, nullptr, nullptr, nullptr, nullptr, scale, 2, ws, st,
+                                    diag);
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,

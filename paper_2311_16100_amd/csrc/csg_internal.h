@@ -25,6 +25,8 @@ hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *d
                                  const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st);
 hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,
                                      float2 *accum, void *ws, hipStream_t st);
+hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
+                                float *diag, void *ws, hipStream_t st);
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
                             float scale, float2 *accum, void *ws, hipStream_t st);
 

@@ -123,9 +123,12 @@ def rhs(ds: Dataset) -> torch.Tensor:
 def exact_diagonal(ds: Dataset, scale: float = 1.0) -> torch.Tensor:
     """diag H = lambda + sum_ij C_ij^2 w_ijk^2 over all N images."""
     d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.x.device)
+    tmp = torch.empty_like(d)
+    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
     for s in range(0, ds.N, CHUNK):
         e = min(ds.N, s + CHUNK)
-        d += B.exact_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), scale, 0.0)
+        d += B.exact_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), scale, 0.0,
+                          diag_out=tmp, workspace=ws)
     return d + ds.lam
 
 

@@ -124,7 +124,8 @@ def predict(ds: Dataset, params: torch.Tensor, ctf2=None, cover=None):
     return B.learned_diag(ds.grid, ds.N, ds.lam, params, ctf2, cover)
 
 
-def shell_means(d: torch.Tensor, M: int) -> torch.Tensor:
+def shell_stats(d: torch.Tensor, M: int):
+    """(shell means, voxel counts) over integer shells round(|k|) < M/2."""
     dev = d.device
     ax = torch.arange(M, device=dev) - M // 2
     r = torch.round(torch.sqrt((ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2).float()))
@@ -132,18 +133,21 @@ def shell_means(d: torch.Tensor, M: int) -> torch.Tensor:
     nsh = M // 2
     m = r < nsh
     sums = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m], d.reshape(-1)[m].double())
-    cnt = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m], torch.ones_like(r[m], dtype=torch.float64))
-    return sums / cnt
+    cnt = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m],
+                                                                       torch.ones_like(r[m], dtype=torch.float64))
+    return sums / cnt, cnt
 
 
-def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 8, n_images: int = 4096, seed: int = 99):
-    """Relative L2 error between the Fourier-shell means of the prediction and
+def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 2, n_images: int = 8192, seed: int = 99):
+    """Relative error between the Fourier-shell means of the prediction and
     of a short Hutchinson estimate (n_probe probes over n_images images,
-    rescaled to the full data set).  Shell means average out the probe noise
-    of a short estimate."""
+    rescaled to the data set), each shell weighted by its voxel count.  Shell
+    means average out the probe noise of a short estimate; the count weights
+    keep the few-voxel central shells from dominating."""
     Dh = hutchinson_full(ds, n_probe, seed, n_images=n_images, probe0=1_000_000)
-    a, b = shell_means(D_pred, ds.M), shell_means(Dh, ds.M)
-    return float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item())
+    a, n = shell_stats(D_pred, ds.M)
+    b, _ = shell_stats(Dh, ds.M)
+    return float((torch.sqrt(torch.sum(n * (a - b) ** 2)) / torch.sqrt(torch.sum(n * b * b))).item())
 
 
 def diag_rel_error(D_a: torch.Tensor, D_b: torch.Tensor, ds: Dataset) -> float:
