@@ -239,12 +239,14 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
 
 
 def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinson", "learned", "exact"),
-                 target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print, **kw):
+                 target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print,
+                 feature_images: int = 8192, judge_images: int = 4096, **kw):
     """Time to `target` for each arm on the same data set and ground truth.
     Setup time is charged to the arm that needs it: the exact arm one
-    squared-weight pass over the data; the learned arm the feature pass, the
-    network and the judge (and, if the judge rejects the prediction, it
-    continues as the Hutchinson arm)."""
+    squared-weight pass over the data; the learned arm the feature pass (over
+    `feature_images` random images), the network and the judge (one complex
+    probe over `judge_images` images); if the judge rejects the prediction the
+    arm continues as the Hutchinson arm."""
     from . import learned as L
     v_star, cg_it, cg_res = ground_truth(ds)
     out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
@@ -260,9 +262,9 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
         elif arm == "learned":
             if params is None:
                 continue
-            ctf2, cover = L.features(ds)
+            ctf2, cover = L.features(ds, n_images=feature_images)
             D = L.predict(ds, params, ctf2, cover)
-            err = L.judge(ds, D)
+            err = L.judge(ds, D, n_images=judge_images)
             note = "judge %.3f" % err
             if not math.isfinite(err) or err > judge_threshold:
                 run_as, D, note = "hutchinson", None, note + " -> fallback to hutchinson"

@@ -29,15 +29,26 @@ from . import binding as B
 from .experiment import CHUNK, Dataset, ball_mask
 
 
-def features(ds: Dataset):
-    """(F2, F3) over all images of the data set in one scatter pass
-    (csg_feature_sums): F2 = sum C^2 w, F3 = sum w."""
+def features(ds: Dataset, n_images: int | None = None, seed: int = 0):
+    """(F2, F3) per image of the data set, i.e. the sums over the N images
+    divided by N, in one scatter pass (csg_feature_sums): F2 = sum C^2 w,
+    F3 = sum w.  With n_images < N the sums run over a uniform random subset
+    of that many images (an unbiased estimate of the per-image means).
+    Returned already multiplied back by N, so both cases have the same scale."""
     acc = torch.zeros((ds.M,) * 3, dtype=torch.complex64, device=ds.x.device)
-    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
-    for s in range(0, ds.N, CHUNK):
-        e = min(ds.N, s + CHUNK)
-        B.feature_sums(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), acc, workspace=ws)
-    return acc.real.contiguous(), acc.imag.contiguous()
+    n = ds.N if n_images is None else min(ds.N, n_images)
+    if n < ds.N:
+        idx = torch.from_numpy(np.random.default_rng([seed, synth.STREAM_MISC]).choice(ds.N, n, replace=False)).to(
+            ds.x.device)
+        rot, df = ds.rot[idx].contiguous(), ds.defocus[idx].contiguous()
+    else:
+        rot, df = ds.rot, ds.defocus
+    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        B.feature_sums(ds.grid, ds.optics, rot[s:e].contiguous(), df[s:e].contiguous(), acc, workspace=ws)
+    f = ds.N / n
+    return (acc.real * f).contiguous(), (acc.imag * f).contiguous()
 
 
 def hutchinson_full(ds: Dataset, n_probe: int, seed: int, n_images: int | None = None, probe0: int = 0):
@@ -124,21 +135,36 @@ def predict(ds: Dataset, params: torch.Tensor, ctf2=None, cover=None):
     return B.learned_diag(ds.grid, ds.N, ds.lam, params, ctf2, cover)
 
 
+_SHELLS = {}
+
+
+def _shell_order(M: int, device):
+    """Voxels sorted by integer shell round(|k|) < M/2, with shell bounds."""
+    key = (M, str(device))
+    if key not in _SHELLS:
+        ax = torch.arange(M, device=device) - M // 2
+        r = torch.round(torch.sqrt((ax[:, None, None] ** 2 + ax[None, :, None] ** 2
+                                    + ax[None, None, :] ** 2).float())).long().reshape(-1)
+        order = torch.argsort(r, stable=True)
+        rs = r[order]
+        nsh = M // 2
+        bounds = torch.searchsorted(rs, torch.arange(nsh + 1, device=device))
+        _SHELLS[key] = (order, bounds)
+    return _SHELLS[key]
+
+
 def shell_stats(d: torch.Tensor, M: int):
-    """(shell means, voxel counts) over integer shells round(|k|) < M/2."""
-    dev = d.device
-    ax = torch.arange(M, device=dev) - M // 2
-    r = torch.round(torch.sqrt((ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2).float()))
-    r = r.long().reshape(-1)
-    nsh = M // 2
-    m = r < nsh
-    sums = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m], d.reshape(-1)[m].double())
-    cnt = torch.zeros(nsh, dtype=torch.float64, device=dev).index_add_(0, r[m],
-                                                                       torch.ones_like(r[m], dtype=torch.float64))
+    """(shell means, voxel counts) over integer shells round(|k|) < M/2,
+    from prefix sums of the voxels sorted by shell."""
+    order, bounds = _shell_order(M, d.device)
+    vals = d.reshape(-1)[order].double()
+    csum = torch.cat([torch.zeros(1, dtype=torch.float64, device=d.device), torch.cumsum(vals, 0)])
+    sums = csum[bounds[1:]] - csum[bounds[:-1]]
+    cnt = (bounds[1:] - bounds[:-1]).double()
     return sums / cnt, cnt
 
 
-def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 2, n_images: int = 8192, seed: int = 99):
+def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 2, n_images: int = 4096, seed: int = 99):
     """Relative error between the Fourier-shell means of the prediction and
     of a short Hutchinson estimate (n_probe probes over n_images images,
     rescaled to the data set), each shell weighted by its voxel count.  Shell
