@@ -224,7 +224,7 @@ int csg_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t s
                  float beta1, float beta2, float eps, void *stream);
 
 /* Predicted Hessian diagonal over the M^3 grid of `grid`:
- *   diag_out[k] = lambda + N exp(mlp(|k| / (M/2), log(ctf2[k]/N), log(cover[k]/N)))
+ *   diag_out[k] = lambda + (N/M) exp(mlp(|k| / (M/2), log(ctf2[k] M/N), log(cover[k] M/N)))
  * where cover[k] > 0, and lambda where no image reaches voxel k (there the
  * data part of the diagonal is exactly zero).  ctf2 and cover are per-voxel
  * sums over the N = n_images images of the data set, the same kind the

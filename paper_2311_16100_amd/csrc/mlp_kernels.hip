@@ -102,21 +102,24 @@ __device__ __forceinline__ float half_sum(float v) {
 }
 
 // Inputs of one voxel for the fused (volume) mode: |k| / (M/2),
-// log(ctf2 / N), log(cover / N); returns false for voxels no image reaches.
-__device__ __forceinline__ bool voxel_inputs(int64_t v, int M, float invN, const float *ctf2, const float *cover,
+// log(ctf2 M / N), log(cover M / N) (the chance that an image reaches a voxel
+// at a given fraction of the maximum radius falls like 1/M, so the M / N
+// scaling makes the inputs comparable across grid sizes); returns false for
+// voxels no image reaches.
+__device__ __forceinline__ bool voxel_inputs(int64_t v, int M, float scale, const float *ctf2, const float *cover,
                                              float x0[3]) {
     const int half = M / 2;
     const int kx = (int)(v % M) - half, ky = (int)((v / M) % M) - half, kz = (int)(v / ((int64_t)M * M)) - half;
     const float cv = cover[v];
     x0[0] = sqrtf((float)(kx * kx + ky * ky + kz * kz)) / (float)half;
-    x0[1] = logf(fmaxf(ctf2[v] * invN, 1e-30f));
-    x0[2] = logf(fmaxf(cv * invN, 1e-30f));
+    x0[1] = logf(fmaxf(ctf2[v] * scale, 1e-30f));
+    x0[2] = logf(fmaxf(cv * scale, 1e-30f));
     return cv > 0.f;
 }
 
 // Inference.  FUSED = false: y[s] = mlp(X[s]) for n samples.  FUSED = true:
-// over the M^3 voxels, D[v] = lambda + N exp(mlp(inputs(v))) where some image
-// reaches v, else lambda.
+// over the M^3 voxels, D[v] = lambda + (N / M) exp(mlp(inputs(v))) where some
+// image reaches v, else lambda.
 template <bool FUSED>
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, const float *X, float *y, int64_t n,
                                                         int M, float N, float lambda, const float *ctf2,
@@ -126,14 +129,14 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, con
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int hh = lane >> 5, c = lane & 31;
-    const float invN = 1.0f / N;
+    const float scale = (float)M / N;
     const int64_t ntiles = (n + 31) / 32;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
         const int64_t smp = tile * 32 + c;
         float x0[3] = {0.f, 0.f, 0.f};
         if (smp < n) {
             if (FUSED) {
-                voxel_inputs(smp, M, invN, ctf2, cover, x0);
+                voxel_inputs(smp, M, scale, ctf2, cover, x0);
             } else {
                 x0[0] = X[smp * 3];
                 x0[1] = X[smp * 3 + 1];
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, con
                 if (t < n) {
                     if (FUSED) {
                         const float cv = cover[t];
-                        y[t] = cv > 0.f ? lambda + N * expf(out[r]) : lambda;
+                        y[t] = cv > 0.f ? lambda + expf(out[r]) / scale : lambda;
                     } else {
                         y[t] = out[r];
                     }

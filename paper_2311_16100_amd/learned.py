@@ -4,12 +4,16 @@ used in place of the on-the-fly estimate of Algorithm 1, with a short
 Hutchinson estimate as judge and the Hutchinson arm as fallback.
 
 Features of voxel k over the N images of a data set (csg_feature_sums):
-  |k| / (M/2),  log(F2_k / N),  log(F3_k / N)
+  |k| / (M/2),  log(F2_k M / N),  log(F3_k M / N)
 F2_k = sum_ij C_ij^2 w_ijk (CTF^2 weight), F3_k = sum_ij w_ijk, the
 interpolation weight that reaches k (the pose coverage: for nearest-neighbour
 stencils it counts the voxel mapping set of Sec. 3.1).
-Target: log((D_k - lambda) / N), D the Hutchinson estimate with many probes.
-Prediction: D_k = lambda + N exp(net(features)) (csg_learned_diag).
+Target: log((D_k - lambda) M / N), D the Hutchinson estimate with many probes.
+Prediction: D_k = lambda + (N / M) exp(net(features)) (csg_learned_diag).
+The M / N scaling: the chance that an image reaches a voxel at a given
+fraction of the maximum radius falls like 1/M, so the scaled quantities are
+comparable across grid sizes and a network trained at 64^3 and 128^3 applies
+at 256^3.
 
 Training runs on the GPU through csg_mlp_grad / csg_mlp_adam.  Assembling
 the training set (selecting voxels, taking logs) is host-side torch
@@ -69,8 +73,8 @@ def inputs(M: int, N: int, ctf2: torch.Tensor, cover: torch.Tensor) -> torch.Ten
     dev = ctf2.device
     ax = (torch.arange(M, device=dev) - M // 2).float()
     k = torch.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2) / (M // 2)
-    x1 = torch.log(torch.clamp(ctf2 / N, min=1e-30))
-    x2 = torch.log(torch.clamp(cover / N, min=1e-30))
+    x1 = torch.log(torch.clamp(ctf2 * (M / N), min=1e-30))
+    x2 = torch.log(torch.clamp(cover * (M / N), min=1e-30))
     return torch.stack([k, x1, x2], dim=-1).reshape(-1, 3).contiguous()
 
 
@@ -91,7 +95,7 @@ def training_set(ds: Dataset, n_probe: int = 200, seed: int = 0, max_samples: in
         g = torch.Generator(device="cpu")
         g.manual_seed(seed)
         idx = idx[torch.randperm(idx.numel(), generator=g)[:max_samples].to(idx.device)]
-    T = torch.log(data[idx] / ds.N).float().contiguous()
+    T = torch.log(data[idx] * (ds.M / ds.N)).float().contiguous()
     return TrainingSet(X[idx].contiguous(), T)
 
 

@@ -103,9 +103,9 @@ def test_learned_diag_fused(B):
                        torch.from_numpy(cover).cuda()).cpu().numpy()
     ax = np.arange(M) - M // 2
     k = np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2) / (M // 2)
-    X = np.stack([k.ravel(), np.log(np.maximum(ctf2.ravel() / N, 1e-30)),
-                  np.log(np.maximum(cover.ravel() / N, 1e-30))], axis=1).astype(np.float32)
+    X = np.stack([k.ravel(), np.log(np.maximum(ctf2.ravel() * M / N, 1e-30)),
+                  np.log(np.maximum(cover.ravel() * M / N, 1e-30))], axis=1).astype(np.float32)
     y = oracle.mlp_forward(p, X)
-    want = np.where(cover.ravel() > 0, lam + N * np.exp(y), lam)
+    want = np.where(cover.ravel() > 0, lam + N / M * np.exp(y), lam)
     assert rel(D.ravel(), want) <= 1e-2
     assert np.all(D.ravel()[cover.ravel() == 0] == np.float32(lam))
