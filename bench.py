@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=48, help="images in the oracle's timed sample")
     ap.add_argument("--deterministic", action="store_true")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-2 comparison of the SGD arms")
     return ap.parse_args()
 
 
@@ -159,6 +160,15 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(vol_true, rot_all, df_all, M, args.cpu_images, scale, lam, alpha)
 
+    tta = None
+    if not args.no_tta:
+        del run, x_b, y, acc, ws_bp
+        torch.cuda.empty_cache()
+        from paper_2311_16100_amd import tta as TTA
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        params, _ = TTA.train_network(log=log)
+        tta = TTA.evaluate(params, log=log)
+
     out = {
         "metric": METRIC,
         "value": round(Bsz / (ms_per_step * 1e-3), 1),
@@ -180,6 +190,7 @@ def main():
         "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "time_to_1e-2": tta,
     }
     print(json.dumps(out), flush=True)
 

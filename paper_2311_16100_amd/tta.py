@@ -1,0 +1,68 @@
+"""Time to 1e-2 relative error of v* for the SGD arms (plain, Hutchinson =
+Algorithm 1, learned preconditioner, exact diagonal), on synthetic data.
+
+Training recipe of the network: data sets at 64^3 and 128^3 with varied
+defocus ranges, Hutchinson diagonals with 200 probes as targets, Adam on the
+GPU kernels.  Evaluation: the mid (128^3, 50,000 images, batch 256) and
+high-resolution (256^3, 200,000 images, batch 1024) workloads, noise-free
+(see `experiment`), every arm from v = 0 with the same Armijo rule; the run
+stops when the relative error over the ball (or over the high-frequency
+half of it) reaches 1e-2.  Wall time = setup (the arm's own preparation)
++ iterations + error evaluations.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import experiment as E
+from . import learned as L
+
+# (grid side, images, blobs, defocus range in micrometres) of the training sets
+TRAIN_SPECS = [(64, 10_000, 100, (0.5 + 0.25 * i, 2.0 + 0.25 * i)) for i in range(10)] + \
+              [(128, 20_000, 200, (0.5 + 0.3 * i, 2.0 + 0.3 * i)) for i in range(10)]
+
+EVAL_SPECS = {
+    "mid_128": dict(M=128, N=50_000, n_blobs=200, batch=256, defocus_um=(0.8, 3.0), seed=2128),
+    "hires_256": dict(M=256, N=200_000, n_blobs=1000, batch=1024, defocus_um=(1.0, 3.0), seed=3256),
+}
+
+
+def train_network(specs=TRAIN_SPECS, steps: int = 2000, n_probe: int = 200, log=print):
+    t0 = time.perf_counter()
+    sets = []
+    for i, (M, N, nb, dfr) in enumerate(specs):
+        ds = E.make_dataset(M, N, nb, 7000 + i, float("inf"), defocus_um=dfr)
+        sets.append(L.training_set(ds, n_probe=n_probe, seed=i))
+        del ds
+    torch.cuda.empty_cache()
+    params, hist = L.train(sets, steps=steps)
+    if log:
+        log("[tta] network trained on %d sets (%d samples) in %.1fs, final loss %.3e" % (
+            len(sets), sum(s.X.shape[0] for s in sets), time.perf_counter() - t0, hist[-1][1]))
+    return params, hist
+
+
+def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: int = 6, time_limit: float = 60.0):
+    out = {}
+    for name in configs:
+        spec = dict(EVAL_SPECS[name])
+        batch = spec.pop("batch")
+        seed = spec.pop("seed")
+        ds = E.make_dataset(spec["M"], spec["N"], spec["n_blobs"], seed, float("inf"), defocus_um=spec["defocus_um"])
+        res = {}
+        for stop in ("ball", "high"):
+            if log:
+                log("[tta] %s stop_on=%s" % (name, stop))
+            r = E.compare_arms(ds, batch, params=params, stop_on=stop, max_epochs=max_epochs, time_limit=time_limit,
+                               eval_every=10 if ds.M <= 128 else 5, log=log)
+            res[stop] = {arm: {"reached": a.reached, "iterations": a.iterations, "run_s": round(a.seconds, 4),
+                               "setup_s": round(a.setup_seconds, 4), "total_s": round(a.total_seconds, 4),
+                               "note": a.note}
+                         for arm, a in r["arms"].items()}
+            res["cg_iterations"] = r["cg_iterations"]
+        out[name] = dict(M=ds.M, N=ds.N, batch=batch, **res)
+        del ds
+        torch.cuda.empty_cache()
+    return out
