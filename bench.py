@@ -7,8 +7,13 @@ diagonal, the preconditioned step and the Armijo line-search forward pass.
 
 Prints one JSON line.  `value` = images per second through full iterations;
 `fwd_adj_images_per_s` = images per second of one plain forward projection
-plus one adjoint of the same batch.  `roofline` is for the dominant call of
-the step, with bytes from the per-image footprint model.
+plus one adjoint of the same batch.  `roofline` is for the dominant kernel
+of the timed steps: its algorithmic bytes per launch (per-image footprint:
+image read 8P, gather 8U, scatter read-modify-write 16U; P disk pixels, U
+distinct voxels an image's stencils touch) over its average launch duration
+from HIP events recorded around each launch on its stream; `traffic` is the
+measured HBM rate of the same launches from the committed counter summary,
+when it was taken on the current kernel sources.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload.
 """
@@ -105,11 +110,18 @@ def main():
         run.iteration(rot_b, df_b, x_b)
     torch.cuda.synchronize()
     calls.clear()
+    # HIP events around every brick-kernel launch of the timed steps, on the
+    # stream the kernels run on
+    B.timing_enable(True)
+    for k in B.KERNELS:
+        B.timing_read(k)
     t_start = time.perf_counter()
     for _ in range(args.steps):
         run.iteration(rot_b, df_b, x_b)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
+    B.timing_enable(False)
+    kern = {k: B.timing_read(k) for k in ("gradient", "hvp", "project")}
     ms_per_step = 1e3 * t_steps / args.steps
     print("[bench] %d Alg.1 steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
 
@@ -149,12 +161,28 @@ def main():
         "project": 8 * M * M + 8 * U,
         "backproject": 8 * P + 16 * U,
     }
-    dominant = max((k for k in ("gradient", "hutchinson_probe", "armijo_project")), key=lambda k: ms[k])
-    achieved = model[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9
+    # dominant kernel of the timed steps: algorithmic bytes per launch (the
+    # per-image footprint times the images of one launch) over its average
+    # event-timed launch duration
+    per_image = {
+        "gradient": 8 * P + 24 * U,  # image read, gather, read-modify-write
+        "hvp": 24 * U,  # gather of the packed probe pair, read-modify-write
+        "project": 8 * P + 8 * U,  # Armijo forward: image read, gather (loss only)
+    }
+    dominant = max(kern, key=lambda k: kern[k][0])
+    tot_ms, launches = kern[dominant]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = per_image[dominant] * Bsz / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
-                "kernel_ms": round(ms[dominant], 4), "bytes_model": "per image: gather 8U + RMW 16U + image 8P",
-                "P": P, "U": round(U)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "brick_kernel<%s>" % dominant, "kernel_avg_ms": round(avg_ms, 4), "launches": launches,
+                "bytes_per_image": round(per_image[dominant]), "P": P, "U": round(U),
+                "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items()}}
+    tr = traffic_record(dominant, Bsz, M)
+    if tr:
+        # measured HBM bytes of one launch over the same average duration (GB/s)
+        roofline["traffic"] = round(tr["hbm_bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_detail"] = tr
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -193,6 +221,39 @@ def main():
         "time_to_1e-2": tta,
     }
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_hires256.md")
+KERNEL_SOURCES = ["brick_kernels.hip", "csg_device.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2311_16100_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel, images, M):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel), or None when
+    there is none for this kernel and workload or the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            line = next(l for l in fh if l.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    if rec.get("kernel") != kernel or rec.get("images") != images or rec.get("M") != M:
+        return None
+    if rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return {"hbm_bytes_per_launch": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
+            "write_bytes": rec["write_bytes"], "calibration": rec.get("calibration")}
 
 
 def cpu_baseline(vol, rot_all, df_all, M, n_img, scale_full, lam, alpha):

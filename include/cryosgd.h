@@ -247,6 +247,33 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
 #define CSG_WS_PROJECT 4
 size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support, not part of the method).  While
+ * enabled, every launch of a brick-binned operator kernel is bracketed by two
+ * HIP events recorded on the stream the kernel is launched on.
+ * csg_timing_read waits for the recorded events of one kernel, returns the
+ * summed duration (ms) and the number of launches recorded since the last
+ * read of that kernel, and forgets them.  At most 8192 launches per kernel
+ * are kept between reads; later ones are not recorded.  Launches of the
+ * nearest-neighbour and deterministic paths (other kernels) are not timed.
+ * Results of the operators do not depend on the setting.
+ *   kernel: CSG_KERNEL_PROJECT     forward projection (csg_project)
+ *           CSG_KERNEL_BACKPROJECT adjoint (csg_backproject, fast mode)
+ *           CSG_KERNEL_GRADIENT    fused residual + adjoint (csg_gradient)
+ *           CSG_KERNEL_HVP         gather + scatter of H z (csg_hvp,
+ *                                  csg_hutchinson_diag)
+ *           CSG_KERNEL_FEATURES    csg_feature_sums
+ *           CSG_KERNEL_SQ_DIAG     csg_exact_diag
+ * ------------------------------------------------------------------------ */
+#define CSG_KERNEL_PROJECT 0
+#define CSG_KERNEL_BACKPROJECT 1
+#define CSG_KERNEL_GRADIENT 2
+#define CSG_KERNEL_HVP 3
+#define CSG_KERNEL_FEATURES 4
+#define CSG_KERNEL_SQ_DIAG 5
+int csg_timing_enable(int32_t on);
+int csg_timing_read(int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Message for the last nonzero return on the calling thread. */
 const char *csg_last_error(void);
 

@@ -73,6 +73,8 @@ EXPORTS = {
     "csg_learned_diag": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "csg_workspace_bytes": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32],
+    "csg_timing_enable": [ctypes.c_int32],
+    "csg_timing_read": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
     "csg_last_error": [],
 }
 
@@ -402,3 +404,20 @@ def learned_diag(grid: Grid, n_images: int, lam: float, params, ctf2, cover, out
     _check(lib().csg_learned_diag(ctypes.byref(g), int(n_images), float(lam), _ptr(params), _ptr(ctf2),
                                   _ptr(cover), _ptr(out), _stream(stream)), "csg_learned_diag")
     return out
+
+
+KERNELS = {"project": 0, "backproject": 1, "gradient": 2, "hvp": 3, "features": 4, "sq_diag": 5}
+
+
+def timing_enable(on: bool = True):
+    """Bracket every brick-kernel launch with HIP events on its stream."""
+    _check(lib().csg_timing_enable(1 if on else 0), "csg_timing_enable")
+
+
+def timing_read(kernel: str):
+    """(summed milliseconds, launches) of one kernel since its last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().csg_timing_read(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)), "csg_timing_read")
+    return ms.value, n.value
+

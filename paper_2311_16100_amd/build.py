@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libcryosgd.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "pixel_kernels.hip", "brick_kernels.hip", "voxel_kernels.hip", "volume_kernels.hip",
-           "mlp_kernels.hip"]
+           "mlp_kernels.hip", "timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

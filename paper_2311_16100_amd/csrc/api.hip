@@ -417,3 +417,15 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
 }
 
 }  // extern "C"
+
+extern "C" int csg_timing_enable(int32_t on) {
+    csg::timing_set(on);
+    return CSG_OK;
+}
+
+extern "C" int csg_timing_read(int32_t kernel, double *total_ms, int64_t *launches) {
+    if (kernel < 0 || kernel >= csg::kTimedKernels) return fail(CSG_EINVAL, "timing: kernel %d out of range", kernel);
+    if (!total_ms || !launches) return fail(CSG_EINVAL, "timing: NULL output pointer");
+    CSG_TRY(csg::timing_read(kernel, total_ms, launches), "csg_timing_read");
+    return CSG_OK;
+}

@@ -519,8 +519,10 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         const int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
         const int64_t chunks = (ns + chunk - 1) / chunk;
         a.nchunks = (int)chunks;
+        hipEvent_t t0 = timing_begin(MODE, st);
         hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBT), 0, st, a);
         e = hipGetLastError();
+        timing_end(MODE, t0, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

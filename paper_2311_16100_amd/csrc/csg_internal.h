@@ -13,6 +13,13 @@ namespace csg {
 // sub-batches of this size (it bounds the per-brick image lists).
 constexpr int64_t kBrickSubBatch = 2048;
 
+// optional kernel timing (timing.hip): brick kernel modes 0..kTimedKernels-1
+constexpr int kTimedKernels = 6;
+void timing_set(int on);
+hipEvent_t timing_begin(int kernel, hipStream_t st);  // nullptr when not timing
+void timing_end(int kernel, hipEvent_t start, hipStream_t st);
+hipError_t timing_read(int kernel, double *total_ms, int64_t *launches);
+
 // brick-binned kernels (brick_kernels.hip)
 int brick_count(int M);
 size_t brick_workspace_bytes(int M, int64_t n);

@@ -92,3 +92,14 @@ def test_bad_ctf_power_rejected(b):
     p = b._Poses(0, None, None)
     assert L.csg_backproject(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, 3, 1.0, None, 0, None, 0,
                              None) == -1
+
+
+def test_timing_arguments_checked(b):
+    L = b.lib()
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    assert L.csg_timing_read(6, ctypes.byref(ms), ctypes.byref(n)) == -1
+    assert L.csg_timing_read(-1, ctypes.byref(ms), ctypes.byref(n)) == -1
+    assert L.csg_timing_read(0, None, ctypes.byref(n)) == -1
+    # nothing recorded: zero launches, and reading needs no device
+    assert b.timing_read("gradient") == (0.0, 0)
+    b.timing_enable(False)
