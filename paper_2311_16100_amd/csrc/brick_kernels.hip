@@ -1,24 +1,29 @@
 // brick_kernels.hip -- brick-binned forward projection and adjoint.
 //
 // The volume is cut into 12^3 bricks.  A cull kernel lists, per brick and in
-// image order, the images whose slice plane reaches the brick.  A work item is
-// one brick and up to 256 of its images; its block
+// image order, the images whose slice plane reaches the brick; a plan kernel
+// turns the lists into work items (one brick and up to 64 of its images for
+// the forward mode, 128 for the adjoint modes), ordered by size, largest
+// first.  One wave of resident blocks takes the items from that list with an
+// atomic counter.  For each item the block
 //   - stages the brick plus a one-voxel halo of the gathered volume in LDS
 //     (14^3 complex values), so every trilinear gather is 8 LDS reads;
 //   - accumulates the adjoint into an LDS copy of the brick with double-
 //     precision LDS atomics, and writes it to HBM once per voxel at the end (a
 //     plain read-modify-write when the brick has a single work item, global
-//     atomics only for the few central bricks that more than 256 images
-//     cross).  On gfx950 the LDS double atomic add sustains about 20x the lane
-//     rate of the single-precision one, so the wider accumulator is also the
-//     faster one.
+//     atomics only for the central bricks that more than 128 images cross).
+//     On gfx950 the LDS double atomic add sustains about 20x the lane rate of
+//     the single-precision one, so the wider accumulator is also the faster
+//     one.
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
-// line against the box.  Eight images x 32 rows fill the 256 lanes; a block
-// scan turns the row intervals into one flat pixel range that the lanes walk
-// together, so neighbouring lanes take neighbouring pixels of a row (coalesced
-// image reads and writes).
+// line against the box.  The rows of a window of images are numbered densely,
+// a block scan turns their intervals into one flat range of runs (one or two
+// consecutive pixels of a row), and the lanes walk that range together, so
+// neighbouring lanes take neighbouring pixels of a row (coalesced image reads
+// and writes).  Within a run the sample point advances in exact fixed-point
+// arithmetic (see ImgSlot), so every brick sees identical cells.
 //
 // A pixel is "touching" a brick when one of its eight cell corners lies in
 // the brick, and "owned" by the brick that contains its base corner
@@ -52,9 +57,7 @@ constexpr int AP = AR * AR;      // accumulator plane stride (289)
 constexpr int VR = BH + 1;       // staged-volume row stride (19)
 constexpr int VP = VR * VR;      // staged-volume plane stride (361)
 constexpr int kBT = 512;         // threads per brick block (8 waves)
-constexpr int ROWS = 32;         // row slots per image (a brick spans <= 24 rows)
-constexpr int GIMG = kBT / ROWS; // images per group
-constexpr int CHUNK_ADJ = 256;   // images per work item of the adjoint modes
+constexpr int CHUNK_ADJ = 128;   // images per work item of the adjoint modes
 constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
@@ -77,7 +80,9 @@ struct BrickArgs {
     const int *lists;   // [nb][stride]
     int stride;
     int nbx, nb;
-    int nchunks;        // work items per brick at most
+    const int *items;   // work items, heaviest first: brick | chunk << 20
+    const int *n_items; // number of work items
+    int *next_item;     // work counter (zero at launch)
 };
 
 __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
@@ -132,6 +137,47 @@ __global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float 
     if (threadIdx.x == 0) counts[b] = total;
 }
 
+// ---------------------------------------------------------------------------
+// Plan: one work item per brick and chunk of `chunk` images of its list,
+// ordered by the number of images, largest first (the full chunks of the
+// heavily crossed central bricks, then the partial chunks by size), so that
+// the long items start first.  Resets the work counter.  One block.
+// ---------------------------------------------------------------------------
+constexpr int kPlanThreads = 1024;
+constexpr int kMaxChunk = 256;
+
+__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int *items,
+                                                                   int *n_items, int *next_item) {
+    __shared__ int hist[kMaxChunk + 1];
+    __shared__ int cursor[kMaxChunk + 1];
+    for (int k = threadIdx.x; k <= chunk; k += kPlanThreads) hist[k] = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
+        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        if (full) atomicAdd(&hist[chunk], full);
+        if (rem) atomicAdd(&hist[rem], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = chunk; k >= 1; --k) {
+            cursor[k] = run;
+            run += hist[k];
+        }
+        *n_items = run;
+        *next_item = 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
+        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        if (full) {
+            const int p = atomicAdd(&cursor[chunk], full);
+            for (int k = 0; k < full; ++k) items[p + k] = b | (k << 20);
+        }
+        if (rem) items[atomicAdd(&cursor[rem], 1)] = b | (full << 20);
+    }
+}
+
 // Exclusive scan of one int per thread over the block; returns the prefix and
 // writes the total to *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *total) {
@@ -178,273 +224,465 @@ __device__ __forceinline__ void clip_row(const float e1[3], const float e2[3], f
     kx1 = (int)fminf(floorf(b + kClipEps), 1e6f);
 }
 
-// Per-image constants of a group, kept in LDS in double precision so the
-// pixel loop needs no conversions: the rows of R and the folded CTF term.
+// Per-image constants of a window, in LDS.  The sample point of pixel
+// (kx, ky) is kept in fixed point with 32 fractional bits:
+//   G = kx E1 + ky E2 + (M/2) 2^32,  E = rint(e 2^32)  (e a row of R),
+// an exact integer (|G| < 2^53), formed in double precision at the first
+// pixel of a run and advanced by the integer E1 from pixel to pixel.  Every
+// brick therefore obtains bit-identical cells and offsets for a pixel, so
+// ownership is decided consistently, and the point differs from
+// kx e1 + ky e2 + M/2 by at most (|kx| + |ky|) 2^-33 grid units.
 struct ImgSlot {
-    double e1[3];
-    double e2[3];
-    double ctfA;  // (lambda df / 2) / (M pixel)^2: chi / 2pi = k2 (ctfA - ctfB k2)
-    double pad;
+    double E1[3];      // rint(e1 2^32), exact integers
+    double E2[3];
+    int64_t E1i[3];    // the same as integers (the per-pixel step)
+    double ctfA;       // (lambda df / 2) / (M pixel)^2: chi / 2pi = k2 (ctfA - ctfB k2)
+    int ky_lo;         // first row that can reach the box
+    int row0;          // index of that row's record in the window
+    uint32_t img_base; // index of pixel (0, 0) of the image: i M^2
+    int pad;
 };
 
-constexpr int PIXCAP = 4096;  // pixels per window of the pixel -> segment table
+// rows of one image that reach a brick's enumeration box (side BS + 1):
+// at most the box diagonal plus the clipping margins
+constexpr int MAXROWS = (int)((BS + 1) * 1.7321f) + 2;
+constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument)
 
+// Window sizes per mode: images per window (a whole forward chunk, whose
+// LDS footprint leaves room; 32 images for the adjoint modes) and runs per
+// pass of the run -> row table.
 template <int MODE>
-__global__ __launch_bounds__(kBT) void brick_kernel(BrickArgs a) {
+struct Win {
+    // consecutive pixels of a row per lane: one for the forward mode, two
+    // for the adjoint modes (measured fastest)
+    static constexpr int RUN = MODE == kBProject ? 1 : 2;
+    static constexpr int WI = MODE == kBProject ? 64 : 32;
+    static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
+    static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
+    static constexpr int RUNCAP = MODE == kBProject ? 3072 : 2048;
+};
+
+__device__ __forceinline__ double rint_scaled(float e) {
+    return rint((double)fminf(fmaxf(e, -2.0f), 2.0f) * 0x1p32);
+}
+
+#ifndef CSG_BRICK_WAVES
+#define CSG_BRICK_WAVES 6
+#endif
+// waves per SIMD the register allocation must allow: three blocks per CU
+// where the LDS footprint permits it (project, backproject, features,
+// squared weights), two for gradient and HVP
+template <int MODE>
+__global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool OWNER_ONLY = MODE == kBProject;
+    constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
     constexpr int CHUNK = OWNER_ONLY ? CHUNK_FWD : CHUNK_ADJ;
     __shared__ float2 vh[GATHER ? BH * VP : 1];
     __shared__ double acc_re[SCATTER ? BS * AP : 1];
     __shared__ double acc_im[SCATTER ? BS * AP : 1];
-    // segment record: x = first flat pixel, y = kx of that pixel,
-    // z = (ky + 512) | image slot << 16, w = pixel index of (kx = 0, ky)
-    __shared__ int4 seg[kBT];
-    __shared__ unsigned short pix2seg[PIXCAP];
-    __shared__ ImgSlot slot[GIMG];
+    constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
+    constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
+    __shared__ ImgSlot slot[WI];
+    // the item's images: index (as int bits), rows 0 and 1 of R, defocus
+    __shared__ float imgdat[CHUNK][8];
+    // row record: x = first run | len << 16 | image slot << 24,
+    //             y = (kx0 + 32768) | (ky + 32768) << 16
+    __shared__ int2 seg[ROWCAP];
+    __shared__ unsigned char row2img[ROWCAP];
+    __shared__ unsigned short run2row[RUNCAP];
     __shared__ int wave_sums[kBT / 64];
+    __shared__ int rows_total;
+    __shared__ int s_item;
     __shared__ double red[16];
 
     const Geom &g = a.g;
     const int M = g.M;
-    // highest chunk index first: the extra work items of the heavily crossed
-    // central bricks start before the single items of the outer bricks
-    const int brick = blockIdx.x % a.nb;
-    const int chunk = a.nchunks - 1 - (int)(blockIdx.x / a.nb);
-    const int count = a.counts[brick];
-    const int first = chunk * CHUNK;
-    if (first >= count) return;  // uniform: no work item here
-    const int n_img = min(CHUNK, count - first);
-    const bool single = count <= CHUNK;
-    int o[3];
-    brick_origin(brick, a.nbx, o);
-
-    if (GATHER) {
-        for (int t = threadIdx.x; t < BH * BH * BH; t += kBT) {
-            const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
-            const int qx = o[0] - 1 + hx, qy = o[1] - 1 + hy, qz = o[2] - 1 + hz;
-            float2 v = make_float2(0.f, 0.f);
-            if (in_grid(qx, M) && in_grid(qy, M) && in_grid(qz, M)) v = a.src[((int64_t)qz * M + qy) * M + qx];
-            vh[(hz * VR + hy) * VR + hx] = v;
-        }
-    }
-    if (SCATTER) {
-        for (int t = threadIdx.x; t < BS * AP; t += kBT) {
-            acc_re[t] = 0.0;
-            acc_im[t] = 0.0;
-        }
-    }
-    // enumeration box (grid coordinates): owned pixels have floor(g) in the
-    // brick, touching pixels have floor(g) in [b0 - 1, b0 + BS - 1]
-    float lo[3], hi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = (float)(OWNER_ONLY ? o[d] : o[d] - 1);
-        hi[d] = (float)(o[d] + BS);
-    }
-    const float halff = (float)g.half;
-    const double halfd = (double)g.half;
-    const int kymax = (int)floorf(sqrtf((float)g.k2max) + 1e-4f);
-    const int *list = a.lists + (int64_t)brick * a.stride + first;
-    const double ctfB = g.ctf_b * g.inv_s2 * g.inv_s2;
-    const uint32_t MM = (uint32_t)M * (uint32_t)M;
+    const int total = *a.n_items;
     double lsum = 0.0;
-    __syncthreads();
 
-    for (int gi = 0; gi < n_img; gi += GIMG) {
-        // every wave has finished with the previous group's scan, segments
-        // and image slots before they are rewritten
+    // work items are taken from the planned list (heaviest first) until it
+    // is exhausted
+    for (;;) {
+        // the previous item is done with every LDS table and accumulator
         __syncthreads();
-        // ---- row segments of GIMG images x ROWS rows, one per thread
-        const int s = threadIdx.x / ROWS, r = threadIdx.x % ROWS;
-        int len = 0, kx0 = 0, ky = 0;
-        uint32_t img_base = 0;
-        if (gi + s < n_img) {
-            const int ii = list[gi + s];
-            img_base = (uint32_t)ii * MM;
-            float e1[3], e2[3];
+        if (threadIdx.x == 0) s_item = atomicAdd(a.next_item, 1);
+        __syncthreads();
+        // uniform values read from LDS are moved to scalar registers
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= total) break;
+        const int code = a.items[item];
+        const int brick = code & 0xFFFFF;
+        const int first = (code >> 20) * CHUNK;
+        const int count = a.counts[brick];
+        const int n_img = min(CHUNK, count - first);
+        const bool single = count <= CHUNK;
+        int o[3];
+        brick_origin(brick, a.nbx, o);
+
+        const int *list = a.lists + (int64_t)brick * a.stride + first;
+        // the item's images are staged in LDS by threads t < n_img; their
+        // loads are issued together with the halo loads so that the
+        // latencies overlap
+        const bool holds_img = (int)threadIdx.x < n_img;
+        int my_ii = 0;
+        if (holds_img) my_ii = list[threadIdx.x];
+        if (GATHER) {
+            // every load of the halo is issued before the first LDS store
+            constexpr int HALO = BH * BH * BH;
+            constexpr int HPT = (HALO + kBT - 1) / kBT;
+            float2 hv[HPT];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                e1[d] = a.rot[(int64_t)ii * 9 + d];
-                e2[d] = a.rot[(int64_t)ii * 9 + 3 + d];
+            for (int k = 0; k < HPT; ++k) {
+                const int t = threadIdx.x + k * kBT;
+                const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
+                const int qx = o[0] - 1 + hx, qy = o[1] - 1 + hy, qz = o[2] - 1 + hz;
+                hv[k] = make_float2(0.f, 0.f);
+                if (t < HALO && in_grid(qx, M) && in_grid(qy, M) && in_grid(qz, M))
+                    hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
             }
-            if (r == 0) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    slot[s].e1[d] = (double)e1[d];
-                    slot[s].e2[d] = (double)e2[d];
-                }
-                slot[s].ctfA = g.ctf_a * (double)a.defocus[ii] * g.inv_s2;
-            }
-            // rows: range of e2 . (g - half) over the box
-            float ylo = 0.f, yhi = 0.f;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const float u = e2[d] * (lo[d] - halff), w = e2[d] * (hi[d] - halff);
-                ylo += fminf(u, w);
-                yhi += fmaxf(u, w);
-            }
-            const int ky_lo = max((int)ceilf(ylo - kClipEps), -kymax);
-            const int ky_hi = min((int)floorf(yhi + kClipEps), kymax);
-            ky = ky_lo + r;
-            if (ky <= ky_hi) {
-                int x0, x1;
-                clip_row(e1, e2, halff, ky, lo, hi, x0, x1);
-                // the disk: |kx| <= floor(sqrt(k2max - ky^2))
-                const int rem = g.k2max - ky * ky;
-                int kxm = (int)sqrtf((float)rem);
-                while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
-                while (kxm * kxm > rem) --kxm;
-                x0 = max(x0, -kxm);
-                x1 = min(x1, kxm);
-                if (x1 >= x0) {
-                    len = x1 - x0 + 1;
-                    kx0 = x0;
-                }
+            for (int k = 0; k < HPT; ++k) {
+                const int t = threadIdx.x + k * kBT;
+                const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
+                if (t < HALO) vh[(hz * VR + hy) * VR + hx] = hv[k];
             }
         }
-        int T;
-        const int pre = block_exclusive_scan(len, wave_sums, &T);
-        seg[threadIdx.x] = make_int4(pre, kx0, (ky + 512) | (s << 16),
-                                     (int)(img_base + (uint32_t)(ky + g.half) * (uint32_t)M + (uint32_t)g.half));
+        if (holds_img) {
+            float e[7];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) e[d] = a.rot[(int64_t)my_ii * 9 + d];
+            e[6] = a.defocus[my_ii];
+            imgdat[threadIdx.x][0] = __int_as_float(my_ii);
+#pragma unroll
+            for (int d = 0; d < 7; ++d) imgdat[threadIdx.x][1 + d] = e[d];
+        }
+        if (SCATTER) {
+            for (int t = threadIdx.x; t < BS * AP; t += kBT) {
+                acc_re[t] = 0.0;
+                acc_im[t] = 0.0;
+            }
+        }
+        // enumeration box (grid coordinates): owned pixels have floor(g) in the
+        // brick, touching pixels have floor(g) in [b0 - 1, b0 + BS - 1]
+        float lo[3], hi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = (float)(OWNER_ONLY ? o[d] : o[d] - 1);
+            hi[d] = (float)(o[d] + BS);
+        }
+        const float halff = (float)g.half;
+        const double halfG = (double)g.half * 0x1p32;
+        const int kymax = (int)floorf(sqrtf((float)g.k2max) + 1e-4f);
+        const double ctfB = g.ctf_b * g.inv_s2 * g.inv_s2;
+        const uint32_t MM = (uint32_t)M * (uint32_t)M;
+        const uint32_t pix_off = (uint32_t)g.half * (uint32_t)M + (uint32_t)g.half;
 
-        for (int wbase = 0; wbase < T; wbase += PIXCAP) {
-            // ---- pixel -> segment table of this window
-            {
-                const int b0 = max(pre, wbase), b1 = min(pre + len, wbase + PIXCAP);
-                for (int q = b0; q < b1; ++q) pix2seg[q - wbase] = (unsigned short)threadIdx.x;
+        for (int w0 = 0; w0 < n_img; w0 += WI) {
+            const int nw = min(WI, n_img - w0);
+            // every wave has finished with the previous window's tables
+            __syncthreads();
+            // ---- the window's images (threads 0..WI-1): constants, first
+            // row, row count
+            const int t = (int)threadIdx.x;
+            if (t < WI) {
+                int nrows = 0;
+                if (t < nw) {
+                    ImgSlot &S = slot[t];
+                    const float *D = imgdat[w0 + t];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        S.E1[d] = rint_scaled(D[1 + d]);
+                        S.E2[d] = rint_scaled(D[4 + d]);
+                        S.E1i[d] = (int64_t)S.E1[d];
+                    }
+                    S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
+                    S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
+                    // rows: range of e2 . (g - half) over the box
+                    float ylo = 0.f, yhi = 0.f;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const float u = D[4 + d] * (lo[d] - halff), w = D[4 + d] * (hi[d] - halff);
+                        ylo += fminf(u, w);
+                        yhi += fmaxf(u, w);
+                    }
+                    // range tests in floating point first, so only bounded values
+                    // are converted
+                    const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
+                    const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
+                    if (fl <= fh) {
+                        S.ky_lo = (int)fl;
+                        nrows = min((int)fh - (int)fl + 1, MAXROWS);
+                    } else {
+                        S.ky_lo = 0;
+                    }
+                }
+                // inclusive scan of the row counts over the 32 lanes
+                int x = nrows;
+#pragma unroll
+                for (int off = 1; off < WI; off <<= 1) {
+                    const int y = __shfl_up(x, off, WI);
+                    if (t >= off) x += y;
+                }
+                if (t < nw) {
+                    slot[t].row0 = x - nrows;
+                    for (int q = 0; q < nrows; ++q) row2img[x - nrows + q] = (unsigned char)t;
+                }
+                if (t == WI - 1) rows_total = x;
             }
             __syncthreads();
-            const int wend = min(T, wbase + PIXCAP);
-            for (int f = wbase + threadIdx.x; f < wend; f += kBT) {
-                const int sl = pix2seg[f - wbase];
-                const int4 rec = seg[sl];
-                const int pkx = rec.y + (f - rec.x);
-                const int pky = (rec.z & 0xFFFF) - 512;
-                const ImgSlot &I = slot[rec.z >> 16];
-                const double dkx = (double)pkx, dky = (double)pky;
-                double rel[3];
-                float t[3];
+            const int n_rows = __builtin_amdgcn_readfirstlane(rows_total);
+            // ---- row intervals (kx range whose cells reach the box), runs per row
+            int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
+            int myruns = 0;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double gd = fma(dkx, I.e1[d], fma(dky, I.e2[d], halfd));
-                    const double fl = floor(gd);
-                    rel[d] = fl - (double)o[d];  // base corner relative to the brick
-                    t[d] = (float)(gd - fl);
+            for (int k = 0; k < RPT; ++k) {
+                const int r = threadIdx.x + k * kBT;
+                rlen[k] = 0;
+                rkx0[k] = 0;
+                rky[k] = 0;
+                rsl[k] = 0;
+                if (r < n_rows) {
+                    const int s = row2img[r];
+                    const ImgSlot &S = slot[s];
+                    const int ky = S.ky_lo + (r - S.row0);
+                    const float *D = imgdat[w0 + s];
+                    const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
+                    int x0, x1;
+                    clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
+                    // the disk: |kx| <= floor(sqrt(k2max - ky^2))
+                    const int rem = g.k2max - ky * ky;
+                    int kxm = (int)sqrtf((float)max(rem, 0));
+                    while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
+                    while (kxm > 0 && kxm * kxm > rem) --kxm;
+                    x0 = max(x0, -kxm);
+                    x1 = min(x1, kxm);
+                    if (rem >= 0 && x1 >= x0) {
+                        rlen[k] = min(x1 - x0 + 1, MAXLEN);
+                        rkx0[k] = x0;
+                    }
+                    rky[k] = ky;
+                    rsl[k] = s;
                 }
-                // range tests in floating point (NaN fails them), so only
-                // in-range values are converted to int
-                const bool owned = rel[0] >= 0.0 && rel[0] <= BS - 1.0 && rel[1] >= 0.0 && rel[1] <= BS - 1.0 &&
-                                   rel[2] >= 0.0 && rel[2] <= BS - 1.0;
-                const bool inside = rel[0] >= -1.0 && rel[0] <= BS - 1.0 && rel[1] >= -1.0 &&
-                                    rel[1] <= BS - 1.0 && rel[2] >= -1.0 && rel[2] <= BS - 1.0;
-                if (OWNER_ONLY ? !owned : !inside) continue;
-                const int l[3] = {(int)rel[0], (int)rel[1], (int)rel[2]};
-                float C = 1.0f;
-                if (g.ctf_on) {
-                    const double k2 = (double)(pkx * pkx + pky * pky);
-                    const double turns = fma(fma(-ctfB, k2, I.ctfA), k2, g.phase0);
-                    C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
-                }
-                const uint32_t j = (uint32_t)rec.w + (uint32_t)pkx;
-                const float wx[2] = {1.0f - t[0], t[0]};
-                const float wy[2] = {1.0f - t[1], t[1]};
-                const float wz[2] = {1.0f - t[2], t[2]};
-                float2 acc = make_float2(0.f, 0.f);
-                if (GATHER) {
-                    // halo index of the base corner: l + 1 in [0, BS]; halo
-                    // voxels outside the grid hold zeros, which drops those
-                    // corners
-                    const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
+                myruns += (rlen[k] + RUN - 1) / RUN;
+            }
+            int T;
+            {
+                int p = block_exclusive_scan(myruns, wave_sums, &T);
+                T = __builtin_amdgcn_readfirstlane(T);
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                        const float w = wx[ax] * wy[ay] * wz[az];
-                        const float2 v = vh[hb + az * VP + ay * VR + ax];
-                        acc.x = fmaf(w, v.x, acc.x);
-                        acc.y = fmaf(w, v.y, acc.y);
+                for (int k = 0; k < RPT; ++k) {
+                    const int r = threadIdx.x + k * kBT;
+                    if (r < n_rows)
+                        seg[r] = make_int2(p | (rlen[k] << 16) | (rsl[k] << 24),
+                                           (rkx0[k] + 32768) | ((rky[k] + 32768) << 16));
+                    p += (rlen[k] + RUN - 1) / RUN;
+                }
+            }
+
+            for (int wbase = 0; wbase < T; wbase += RUNCAP) {
+                // ---- run -> row table of this pass (each thread fills the runs
+                // of its own rows, read back from their records)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int r = threadIdx.x + k * kBT;
+                    if (r < n_rows) {
+                        const int x = seg[r].x;
+                        const int rs = x & 0xFFFF, nr = (((x >> 16) & 0xFF) + RUN - 1) / RUN;
+                        const int b0 = max(rs, wbase), b1 = min(rs + nr, wbase + RUNCAP);
+                        for (int q = b0; q < b1; ++q) run2row[q - wbase] = (unsigned short)r;
                     }
                 }
-                float2 val = make_float2(0.f, 0.f);
-                if (MODE == kBProject) {
-                    float2 y = make_float2(C * acc.x, C * acc.y);
-                    if (a.img) {
-                        const float2 x = a.img[j];
-                        y.x -= x.x;
-                        y.y -= x.y;
-                    }
-                    if (a.out) a.out[j] = y;
-                    lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
-                } else if (MODE == kBBackproject) {
-                    const float2 x = a.img[j];
-                    const float fct = a.scale * ctf_pow(C, a.ctf_power);
-                    val = make_float2(fct * x.x, fct * x.y);
-                } else if (MODE == kBGradient) {
-                    const float2 x = a.img[j];
-                    const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
-                    if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
-                    const float fct = a.scale * C;
-                    val = make_float2(fct * rr.x, fct * rr.y);
-                } else if (MODE == kBHvp) {
-                    const float fct = a.scale * C * C;
-                    val = make_float2(fct * acc.x, fct * acc.y);
-                } else if (MODE == kBFeatures) {
-                    val = make_float2(C * C, 1.0f);
-                } else if (MODE == kBSqDiag) {
-                    val = make_float2(a.scale * C * C, 0.0f);
-                }
-                if (SCATTER) {
-                    // corners inside the brick; a corner beyond the grid edge
-                    // lands in an LDS slot that is never written back
-                    const int lb = l[2] * AP + l[1] * AR + l[0];
+                __syncthreads();
+                const int wend = min(T, wbase + RUNCAP);
+                for (int u = wbase + threadIdx.x; u < wend; u += kBT) {
+                    const int2 rec = seg[run2row[u - wbase]];
+                    const int rs = rec.x & 0xFFFF;
+                    const int len = (rec.x >> 16) & 0xFF;
+                    const ImgSlot &I = slot[(unsigned)rec.x >> 24];
+                    const int kx0 = (rec.y & 0xFFFF) - 32768;
+                    const int ky = (int)((unsigned)rec.y >> 16) - 32768;
+                    const int j0 = (u - rs) * RUN;
+                    const int kxs = kx0 + j0;
+                    const int cnt = min(RUN, len - j0);
+                    const uint32_t jrun = I.img_base + pix_off + (uint32_t)(ky * M) + (uint32_t)kxs;
+                    // the run's image values are requested first, so that their
+                    // latency overlaps the sample-point arithmetic (every pixel of
+                    // a run lies in the disk, hence inside its image)
+                    float2 xin[RUN];
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                        const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
-                        if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS &&
-                            (unsigned)lz < (unsigned)BS) {
-                            const float w = wx[ax] * wy[ay] * wz[az];
-                            const int li = lb + az * AP + ay * AR + ax;
-                            if (MODE == kBSqDiag) {
-                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                            } else {
-                                atomicAdd(&acc_re[li], (double)(w * val.x));
-                                atomicAdd(&acc_im[li], (double)(w * val.y));
+                    for (int jj = 0; jj < RUN; ++jj) {
+                        xin[jj] = make_float2(0.f, 0.f);
+                        if (READS_IMG && a.img && jj < cnt) xin[jj] = a.img[jrun + jj];
+                    }
+                    // fixed-point sample point of the run's first pixel (exact)
+                    int64_t G[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double gd = fma((double)kxs, I.E1[d], fma((double)ky, I.E2[d], halfG));
+                        const double h = floor(gd * 0x1p-32);
+                        const uint32_t l32 = (uint32_t)fma(-h, 0x1p32, gd);
+                        G[d] = (int64_t)(((uint64_t)(uint32_t)(int)h << 32) | l32);
+                    }
+                    const int64_t E1i[3] = {I.E1i[0], I.E1i[1], I.E1i[2]};
+                    const double ctfA = I.ctfA;
+                    const int ky2 = ky * ky;
+#pragma unroll
+                    for (int jj = 0; jj < RUN; ++jj) {
+                        if (jj < cnt) {
+                            int l[3];
+                            float t[3];
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                l[d] = (int)(G[d] >> 32) - o[d];  // base corner relative to the brick
+                                t[d] = (float)(uint32_t)G[d] * 0x1p-32f;
+                            }
+                            const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
+                                               (unsigned)l[2] < (unsigned)BS;
+                            const bool inside = (unsigned)(l[0] + 1) < (unsigned)(BS + 1) &&
+                                                (unsigned)(l[1] + 1) < (unsigned)(BS + 1) &&
+                                                (unsigned)(l[2] + 1) < (unsigned)(BS + 1);
+                            if (OWNER_ONLY ? owned : inside) {
+                                const int kx = kxs + jj;
+                                float C = 1.0f;
+                                if (g.ctf_on) {
+                                    const double k2 = (double)(kx * kx + ky2);
+                                    const double turns = fma(fma(-ctfB, k2, ctfA), k2, g.phase0);
+                                    C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
+                                }
+                                const uint32_t j = jrun + (uint32_t)jj;
+                                const float wx[2] = {1.0f - t[0], t[0]};
+                                const float wy[2] = {1.0f - t[1], t[1]};
+                                const float wz[2] = {1.0f - t[2], t[2]};
+                                float2 acc = make_float2(0.f, 0.f);
+                                if (GATHER) {
+                                    // halo index of the base corner: l + 1 in [0, BS];
+                                    // halo voxels outside the grid hold zeros, which
+                                    // drops those corners
+                                    const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
+#pragma unroll
+                                    for (int c = 0; c < 8; ++c) {
+                                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                        const float w = wx[ax] * wy[ay] * wz[az];
+                                        const float2 v = vh[hb + az * VP + ay * VR + ax];
+                                        acc.x = fmaf(w, v.x, acc.x);
+                                        acc.y = fmaf(w, v.y, acc.y);
+                                    }
+                                }
+                                float2 val = make_float2(0.f, 0.f);
+                                if (MODE == kBProject) {
+                                    float2 y = make_float2(C * acc.x, C * acc.y);
+                                    if (a.img) {
+                                        y.x -= xin[jj].x;
+                                        y.y -= xin[jj].y;
+                                    }
+                                    if (a.out) a.out[j] = y;
+                                    lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
+                                } else if (MODE == kBBackproject) {
+                                    const float2 x = xin[jj];
+                                    const float fct = a.scale * ctf_pow(C, a.ctf_power);
+                                    val = make_float2(fct * x.x, fct * x.y);
+                                } else if (MODE == kBGradient) {
+                                    const float2 x = xin[jj];
+                                    const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
+                                    if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                                    const float fct = a.scale * C;
+                                    val = make_float2(fct * rr.x, fct * rr.y);
+                                } else if (MODE == kBHvp) {
+                                    const float fct = a.scale * C * C;
+                                    val = make_float2(fct * acc.x, fct * acc.y);
+                                } else if (MODE == kBFeatures) {
+                                    val = make_float2(C * C, 1.0f);
+                                } else if (MODE == kBSqDiag) {
+                                    val = make_float2(a.scale * C * C, 0.0f);
+                                }
+                                if (SCATTER) {
+                                    // corners inside the brick; a corner beyond the
+                                    // grid edge lands in an LDS slot that is never
+                                    // written back
+                                    const int lb = l[2] * AP + l[1] * AR + l[0];
+#pragma unroll
+                                    for (int c = 0; c < 8; ++c) {
+                                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                        const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
+                                        if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS &&
+                                            (unsigned)lz < (unsigned)BS) {
+                                            const float w = wx[ax] * wy[ay] * wz[az];
+                                            const int li = lb + az * AP + ay * AR + ax;
+                                            if (MODE == kBSqDiag) {
+                                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                                            } else {
+                                                atomicAdd(&acc_re[li], (double)(w * val.x));
+                                                atomicAdd(&acc_im[li], (double)(w * val.y));
+                                            }
+                                        }
+                                    }
+                                }
                             }
                         }
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) G[d] += E1i[d];
+                    }
+                }
+                __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
+            }
+        }
+
+        if (SCATTER) {
+            __syncthreads();
+            // flush: voxels of a brick with a single work item are updated
+            // with plain loads and stores (all loads of a thread first), the
+            // others with global atomics
+            constexpr int NV = BS * BS * BS;
+            constexpr int FPT = (NV + kBT - 1) / kBT;
+#define CSG_FLUSH_INDEX(k)                                                                  \
+    const int t = threadIdx.x + (k) * kBT;                                                  \
+    const int tx = t % BS, ty = (t / BS) % BS, tz = t / (BS * BS);                          \
+    const bool ok = t < NV && o[0] + tx < M && o[1] + ty < M && o[2] + tz < M;              \
+    const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);          \
+    const int li = tz * AP + ty * AR + tx;
+            if (MODE == kBSqDiag) {
+                float old[FPT];
+#pragma unroll
+                for (int k = 0; k < FPT; ++k) {
+                    CSG_FLUSH_INDEX(k)
+                    (void)li;
+                    old[k] = (single && ok) ? a.accum_real[gi] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < FPT; ++k) {
+                    CSG_FLUSH_INDEX(k)
+                    if (!ok) continue;
+                    const float re = (float)acc_re[li];
+                    if (single) a.accum_real[gi] = old[k] + re;
+                    else if (re != 0.f) atomicAdd(a.accum_real + gi, re);
+                }
+            } else {
+                float2 old[FPT];
+#pragma unroll
+                for (int k = 0; k < FPT; ++k) {
+                    CSG_FLUSH_INDEX(k)
+                    (void)li;
+                    old[k] = (single && ok) ? a.accum[gi] : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int k = 0; k < FPT; ++k) {
+                    CSG_FLUSH_INDEX(k)
+                    if (!ok) continue;
+                    const float re = (float)acc_re[li], im = (float)acc_im[li];
+                    if (single) {
+                        a.accum[gi] = make_float2(old[k].x + re, old[k].y + im);
+                    } else if (re != 0.f || im != 0.f) {
+                        atomicAdd(&a.accum[gi].x, re);
+                        atomicAdd(&a.accum[gi].y, im);
                     }
                 }
             }
-            __syncthreads();  // the table (and, after the last window, the segments) are rebuilt
+#undef CSG_FLUSH_INDEX
         }
-    }
+    }  // work items
 
-    if (SCATTER) {
-        for (int t = threadIdx.x; t < BS * BS * BS; t += kBT) {
-            const int tx = t % BS, ty = (t / BS) % BS, tz = t / (BS * BS);
-            const int qx = o[0] + tx, qy = o[1] + ty, qz = o[2] + tz;
-            if (!(qx < M && qy < M && qz < M)) continue;
-            const int li = tz * AP + ty * AR + tx;
-            const float re = (float)acc_re[li], im = (float)acc_im[li];
-            if (MODE == kBSqDiag) {
-                float *pr = a.accum_real + ((int64_t)qz * M + qy) * M + qx;
-                if (single) *pr += re;
-                else if (re != 0.f) atomicAdd(pr, re);
-                continue;
-            }
-            float2 *p = a.accum + ((int64_t)qz * M + qy) * M + qx;
-            if (single) {
-                float2 v = *p;
-                v.x += re;
-                v.y += im;
-                *p = v;
-            } else if (re != 0.f || im != 0.f) {
-                atomicAdd(&p->x, re);
-                atomicAdd(&p->y, im);
-            }
-        }
-    }
     if ((MODE == kBProject || MODE == kBGradient) && a.loss) {
         const double t = block_sum(lsum, red);
         if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
@@ -474,11 +712,33 @@ int brick_count(int M) {
     return nbx * nbx * nbx;
 }
 
+// Workspace of the brick kernels for a batch of n images (256-byte aligned
+// regions): per-brick image counts, per-brick image lists of one sub-batch,
+// the work items of one launch, and the two work-list scalars.
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static size_t brick_items_cap(int M, int64_t sub) {
+    const int64_t per = (sub + CHUNK_FWD - 1) / CHUNK_FWD;  // the smallest chunk gives the most items
+    return (size_t)brick_count(M) * (size_t)(per > 0 ? per : 1);
+}
+
 size_t brick_workspace_bytes(int M, int64_t n) {
     const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
     const size_t nb = (size_t)brick_count(M);
-    const size_t counts = (nb * 4 + 255) / 256 * 256;
-    return counts + nb * (size_t)(sub > 0 ? sub : 1) * 4;
+    return align256(nb * 4) + align256(nb * (size_t)(sub > 0 ? sub : 1) * 4) + align256(brick_items_cap(M, sub) * 4) +
+           256;
+}
+
+// Resident blocks of one brick-kernel mode on the current device (one wave
+// of blocks that then fetch work items until the list is exhausted).
+template <int MODE>
+static int resident_blocks() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, brick_kernel<MODE>, kBT, 0) != hipSuccess || per <= 0)
+        per = 1;
+    return cus * per;
 }
 
 template <int MODE>
@@ -488,15 +748,29 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
-    int *counts = (int *)ws;
-    int *lists = (int *)((char *)ws + ((size_t)nb * 4 + 255) / 256 * 256);
+    const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
+    char *w = (char *)ws;
+    int *counts = (int *)w;
+    w += align256((size_t)nb * 4);
+    int *lists = (int *)w;
+    w += align256((size_t)nb * (size_t)sub * 4);
+    int *items = (int *)w;
+    w += align256(brick_items_cap(M, sub) * 4);
+    int *scalars = (int *)w;  // [0] number of work items, [1] work counter
     const int64_t img_stride = (int64_t)M * M;
+    constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
+    const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
+    const int grid = (int)(resident_blocks<MODE>() < max_items ? resident_blocks<MODE>() : max_items);
     for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
         const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
         const int stride = (int)ns;
         hipLaunchKernelGGL(brick_cull_kernel, dim3(nb), dim3(kBlock), 0, st, g, rot + s0 * 9, ns, nbx, counts, lists,
                            stride);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(brick_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, counts, nb, chunk, items, scalars,
+                           scalars + 1);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
         BrickArgs a{};
         a.g = g;
@@ -516,11 +790,11 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.stride = stride;
         a.nbx = nbx;
         a.nb = nb;
-        const int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
-        const int64_t chunks = (ns + chunk - 1) / chunk;
-        a.nchunks = (int)chunks;
+        a.items = items;
+        a.n_items = scalars;
+        a.next_item = scalars + 1;
         hipEvent_t t0 = timing_begin(MODE, st);
-        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)(chunks * nb)), dim3(kBT), 0, st, a);
+        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         e = hipGetLastError();
         timing_end(MODE, t0, st);
         if (e != hipSuccess) return e;
