@@ -137,47 +137,6 @@ __global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float 
     if (threadIdx.x == 0) counts[b] = total;
 }
 
-// ---------------------------------------------------------------------------
-// Plan: one work item per brick and chunk of `chunk` images of its list,
-// ordered by the number of images, largest first (the full chunks of the
-// heavily crossed central bricks, then the partial chunks by size), so that
-// the long items start first.  Resets the work counter.  One block.
-// ---------------------------------------------------------------------------
-constexpr int kPlanThreads = 1024;
-constexpr int kMaxChunk = 256;
-
-__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int *items,
-                                                                   int *n_items, int *next_item) {
-    __shared__ int hist[kMaxChunk + 1];
-    __shared__ int cursor[kMaxChunk + 1];
-    for (int k = threadIdx.x; k <= chunk; k += kPlanThreads) hist[k] = 0;
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
-        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
-        if (full) atomicAdd(&hist[chunk], full);
-        if (rem) atomicAdd(&hist[rem], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int k = chunk; k >= 1; --k) {
-            cursor[k] = run;
-            run += hist[k];
-        }
-        *n_items = run;
-        *next_item = 0;
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
-        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
-        if (full) {
-            const int p = atomicAdd(&cursor[chunk], full);
-            for (int k = 0; k < full; ++k) items[p + k] = b | (k << 20);
-        }
-        if (rem) items[atomicAdd(&cursor[rem], 1)] = b | (full << 20);
-    }
-}
-
 // Exclusive scan of one int per thread over the block; returns the prefix and
 // writes the total to *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *total) {
@@ -198,6 +157,71 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *
     }
     *total = tot;
     return base + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// Plan: one work item per brick and chunk of `chunk` images of its list,
+// ordered by the number of images, largest first (the full chunks of the
+// heavily crossed central bricks, then the partial chunks by size), so that
+// the long items start first.  Each wave counts into its own histogram copy
+// (fewer colliding LDS atomics).  Resets the work counter.  One block.
+// ---------------------------------------------------------------------------
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanWaves = kPlanThreads / 64;
+constexpr int kMaxChunk = 128;
+static_assert(CHUNK_ADJ <= kMaxChunk && CHUNK_FWD <= kMaxChunk, "plan histogram too small");
+
+__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int *items,
+                                                                   int *n_items, int *next_item) {
+    __shared__ int hist[kPlanWaves][kMaxChunk + 1];
+    __shared__ int base[kMaxChunk + 1];
+    const int wv = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < kPlanWaves * (kMaxChunk + 1); k += kPlanThreads) (&hist[0][0])[k] = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
+        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        if (full) atomicAdd(&hist[wv][chunk], full);
+        if (rem) atomicAdd(&hist[wv][rem], 1);
+    }
+    __syncthreads();
+    // bucket starts (largest key first), then per-wave cursors inside each
+    // bucket (in place of the counts)
+    if (threadIdx.x <= chunk) {
+        const int k = threadIdx.x;
+        int tot = 0;
+        for (int w = 0; w < kPlanWaves; ++w) tot += hist[w][k];
+        base[k] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = chunk; k >= 1; --k) {
+            const int t = base[k];
+            base[k] = run;
+            run += t;
+        }
+        *n_items = run;
+        *next_item = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x <= chunk) {
+        const int k = threadIdx.x;
+        int run = base[k];
+        for (int w = 0; w < kPlanWaves; ++w) {
+            const int t = hist[w][k];
+            hist[w][k] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
+        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        if (full) {
+            const int p = atomicAdd(&hist[wv][chunk], full);
+            for (int k = 0; k < full; ++k) items[p + k] = b | (k << 20);
+        }
+        if (rem) items[atomicAdd(&hist[wv][rem], 1)] = b | (full << 20);
+    }
 }
 
 // Interval of kx for which the sample point of row ky lies in the box
@@ -690,17 +714,28 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
 }
 
 // Zero the pixels outside the disk (the brick kernels write only the disk).
-// One thread per (image row, pixel); only the pixels outside the disk are
-// stored.
+// One wave per image row: it stores the columns left and right of the row's
+// disk interval (the whole row where the disk does not reach it).
 __global__ __launch_bounds__(kBlock) void zero_outside_disk_kernel(float2 *out, int64_t n, int M, int half,
                                                                     int k2max) {
     const int64_t rows = n * (int64_t)M;
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t row = wave; row < rows; row += waves) {
         const int ky = (int)(row % M) - half;
-        for (int x = threadIdx.x; x < M; x += blockDim.x) {
-            const int kx = x - half;
-            if (kx * kx + ky * ky > k2max) out[row * M + x] = make_float2(0.f, 0.f);
+        const int rem = k2max - ky * ky;
+        int left = M, right = M;  // columns [0, left) and [right, M) are outside
+        if (rem >= 0) {
+            int kxm = (int)sqrtf((float)rem);
+            while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
+            while (kxm > 0 && kxm * kxm > rem) --kxm;
+            left = half - kxm;
+            right = half + kxm + 1;
         }
+        float2 *p = out + row * M;
+        for (int x = lane; x < left; x += 64) p[x] = make_float2(0.f, 0.f);
+        for (int x = right + lane; x < M; x += 64) p[x] = make_float2(0.f, 0.f);
     }
 }
 
@@ -810,8 +845,8 @@ hipError_t launch_brick_project(const Geom &g, const float *rot, const float *de
     if (g.interp == 0) return launch_project(g, rot, defocus, n, vol, subtract, out, loss, st);
     hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws, st);
     if (e != hipSuccess || !out) return e;
-    int64_t blocks = n * (int64_t)g.M;
-    if (blocks > 65536) blocks = 65536;
+    int64_t blocks = (n * (int64_t)g.M + 3) / 4;  // four waves (rows) per block
+    if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(zero_outside_disk_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, out, n, g.M, g.half,
                        g.k2max);
     return hipGetLastError();
