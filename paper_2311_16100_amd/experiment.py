@@ -39,11 +39,14 @@ CHUNK = 2048  # images per library call when sweeping a whole data set
 
 @dataclass
 class Dataset:
+    """Poses, defocus and ground truth of a synthetic data set, with its
+    images either resident (`x`) or, for sets larger than device memory,
+    regenerated batch by batch from v_true (noise-free sets only)."""
     grid: B.Grid
     optics: B.Optics
     rot: torch.Tensor
     defocus: torch.Tensor
-    x: torch.Tensor
+    x: torch.Tensor | None
     v_true: torch.Tensor
     sigma2: float
     lam: float
@@ -57,6 +60,21 @@ class Dataset:
     def M(self) -> int:
         return self.grid.M
 
+    @property
+    def device(self):
+        return self.v_true.device
+
+    @property
+    def streamed(self) -> bool:
+        return self.x is None
+
+    def images(self, idx) -> torch.Tensor:
+        """Images of the index tensor or slice `idx` (contiguous)."""
+        if self.x is not None:
+            return self.x[idx].contiguous()
+        return B.project(self.grid, self.optics, self.rot[idx].contiguous(), self.defocus[idx].contiguous(),
+                         self.v_true)
+
 
 def disk_mask(M: int, r: float, device) -> torch.Tensor:
     ax = torch.arange(M, device=device) - M // 2
@@ -69,12 +87,18 @@ def ball_mask(M: int, r: float, device) -> torch.Tensor:
 
 
 def make_dataset(M: int, N: int, n_blobs: int, seed: int, snr: float, defocus_um=(1.0, 3.0), poses="uniform",
-                 kappa: float = 10.0, device="cuda", lam: float | None = None) -> Dataset:
+                 kappa: float = 10.0, device="cuda", lam: float | None = None, stream: bool = False) -> Dataset:
+    """stream=True keeps only poses and defocus resident and regenerates the
+    (noise-free) images of each batch when they are needed."""
     grid, optics = B.Grid(M), B.Optics()
     v_true = torch.from_numpy(synth.blob_volume(M, n_blobs, seed)).to(device)
     rot = synth.vmf_rotations(N, kappa, seed) if poses == "vmf" else synth.uniform_rotations(N, seed)
     rot = torch.from_numpy(rot).to(device)
     df = torch.from_numpy(synth.defocus_values(N, defocus_um[0], defocus_um[1], seed)).to(device)
+    if stream:
+        if math.isfinite(snr) and snr > 0:
+            raise ValueError("streamed data sets are noise-free (snr must be inf)")
+        return Dataset(grid, optics, rot, df, None, v_true, 0.0, float(1e-3 if lam is None else lam), seed)
     x = torch.empty((N, M, M), dtype=torch.complex64, device=device)
     for s in range(0, N, CHUNK):
         e = min(N, s + CHUNK)
@@ -116,15 +140,15 @@ def rhs(ds: Dataset) -> torch.Tensor:
     for s in range(0, ds.N, CHUNK):
         e = min(ds.N, s + CHUNK)
         B.backproject(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(),
-                      ds.x[s:e].contiguous(), ctf_power=1, accum=b)
+                      ds.images(slice(s, e)), ctf_power=1, accum=b)
     return b
 
 
 def exact_diagonal(ds: Dataset, scale: float = 1.0) -> torch.Tensor:
     """diag H = lambda + sum_ij C_ij^2 w_ijk^2 over all N images."""
-    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.x.device)
+    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.device)
     tmp = torch.empty_like(d)
-    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
+    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_BACKPROJECT, ds.device)
     for s in range(0, ds.N, CHUNK):
         e = min(ds.N, s + CHUNK)
         d += B.exact_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(), scale, 0.0,
@@ -132,11 +156,11 @@ def exact_diagonal(ds: Dataset, scale: float = 1.0) -> torch.Tensor:
     return d + ds.lam
 
 
-def ground_truth(ds: Dataset, tol: float = 1e-6, max_iter: int = 500):
+def ground_truth(ds: Dataset, tol: float = 1e-6, max_iter: int = 500, log=None):
     """v* = H^{-1} b by Jacobi-preconditioned CG (double-precision dots)."""
     b = rhs(ds)
     dinv = 1.0 / exact_diagonal(ds)
-    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_GRADIENT, ds.x.device)
+    ws = B.alloc_workspace(ds.grid, min(ds.N, CHUNK), B.CSG_WS_GRADIENT, ds.device)
     x = torch.zeros_like(b)
     r = b.clone()
     z = dinv * r
@@ -147,6 +171,9 @@ def ground_truth(ds: Dataset, tol: float = 1e-6, max_iter: int = 500):
     for it in range(max_iter):
         if torch.linalg.vector_norm(r.to(torch.complex128)) <= tol * bn:
             break
+        if log and it % 20 == 0:
+            log("  cg iteration %d residual %.3e" % (
+                it, float((torch.linalg.vector_norm(r.to(torch.complex128)) / bn).item())))
         Ap = full_hvp(ds, p, ws)
         alpha = rz / torch.vdot(p.reshape(-1).to(torch.complex128), Ap.reshape(-1).to(torch.complex128)).real
         x = x + (alpha * p.to(torch.complex128)).to(torch.complex64)
@@ -174,6 +201,7 @@ class RunResult:
     errors: list = field(default_factory=list)  # (iteration, seconds, ball error, high-band error)
     halvings: int = 0
     capped: int = 0
+    gen_seconds: float = 0.0  # regeneration of streamed images (not in `seconds`)
     note: str = ""
 
     @property
@@ -190,16 +218,19 @@ def high_band_mask(M: int, r_max: float, device) -> torch.Tensor:
 
 def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
             eval_every: int = 5, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
-            seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball") -> RunResult:
+            seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball",
+            deterministic: bool = False, progress=None) -> RunResult:
     """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
     the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target.
     `decay_epochs` > 0 halves the step-size cap every that many epochs
     (identically in every arm).  Wall time counts iterations and error
-    evaluations."""
-    dev = ds.x.device
+    evaluations; for a streamed data set the regeneration of each batch's
+    images is timed apart (`gen_seconds`) and not counted.
+    `deterministic` selects the bitwise-reproducible adjoint."""
+    dev = ds.device
     scale = ds.N / batch
     alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
-    cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17)
+    cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17, deterministic=deterministic)
     kind = {"plain": "plain", "hutchinson": "hutchinson", "learned": "fixed", "exact": "fixed"}[arm]
     v0 = torch.zeros_like(v_star)
     run = Alg1Runner(ds.grid, ds.optics, kind, scale, ds.lam, alpha, cfg, v0, D_fixed=D_fixed, batch=batch)
@@ -208,6 +239,7 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     res = RunResult(arm, False, 0, 0.0, setup_seconds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_log = t0
     it = 0
     eta_cap = eta0
     for epoch in range(max_epochs):
@@ -217,13 +249,24 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
         perm = torch.from_numpy(synth.epoch_permutation(ds.N, seed, epoch)).to(dev)
         for s in range(0, ds.N - batch + 1, batch):
             idx = perm[s:s + batch]
-            res.halvings += run.iteration(ds.rot[idx].contiguous(), ds.defocus[idx].contiguous(),
-                                          ds.x[idx].contiguous())
+            if ds.streamed:
+                torch.cuda.synchronize()
+                tg = time.perf_counter()
+                xb = ds.images(idx)
+                torch.cuda.synchronize()
+                res.gen_seconds += time.perf_counter() - tg
+            else:
+                xb = ds.images(idx)
+            res.halvings += run.iteration(ds.rot[idx].contiguous(), ds.defocus[idx].contiguous(), xb)
+            del xb
             it += 1
+            if progress and time.perf_counter() - t_log > 30.0:
+                t_log = time.perf_counter()
+                progress("  %s: iteration %d, %.1f s" % (arm, it, t_log - t0 - res.gen_seconds))
             if it % eval_every == 0:
                 eb = rel_error(run.state.v, v_star, ball)
                 eh = rel_error(run.state.v, v_star, high)
-                el = time.perf_counter() - t0
+                el = time.perf_counter() - t0 - res.gen_seconds
                 res.errors.append((it, el, eb, eh))
                 if (eb if stop_on == "ball" else eh) <= target:
                     res.reached, res.iterations, res.seconds = True, it, el
@@ -233,14 +276,14 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
                     res.iterations, res.seconds, res.note = it, el, "time limit"
                     res.capped = run.state.capped
                     return res
-    res.iterations, res.seconds, res.note = it, time.perf_counter() - t0, "epoch limit"
+    res.iterations, res.seconds, res.note = it, time.perf_counter() - t0 - res.gen_seconds, "epoch limit"
     res.capped = run.state.capped
     return res
 
 
 def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinson", "learned", "exact"),
                  target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print,
-                 feature_images: int = 8192, judge_images: int = 4096, **kw):
+                 feature_images: int = 8192, judge_images: int = 4096, cg_tol: float = 1e-6, **kw):
     """Time to `target` for each arm on the same data set and ground truth.
     Setup time is charged to the arm that needs it: the exact arm one
     squared-weight pass over the data; the learned arm the feature pass (over
@@ -248,7 +291,7 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
     probe over `judge_images` images); if the judge rejects the prediction the
     arm continues as the Hutchinson arm."""
     from . import learned as L
-    v_star, cg_it, cg_res = ground_truth(ds)
+    v_star, cg_it, cg_res = ground_truth(ds, tol=cg_tol, log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
     out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
     for arm in arms:
         D = None
@@ -270,7 +313,8 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
                 run_as, D, note = "hutchinson", None, note + " -> fallback to hutchinson"
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
-        r = run_arm(ds, v_star, run_as, batch, target=target, D_fixed=D, setup_seconds=setup, stop_on=stop_on, **kw)
+        r = run_arm(ds, v_star, run_as, batch, target=target, D_fixed=D, setup_seconds=setup, stop_on=stop_on,
+                    progress=log, **kw)
         r.arm, r.note = arm, (r.note + " " + note).strip()
         out["arms"][arm] = r
         if log:

@@ -39,15 +39,15 @@ def features(ds: Dataset, n_images: int | None = None, seed: int = 0):
     F3 = sum w.  With n_images < N the sums run over a uniform random subset
     of that many images (an unbiased estimate of the per-image means).
     Returned already multiplied back by N, so both cases have the same scale."""
-    acc = torch.zeros((ds.M,) * 3, dtype=torch.complex64, device=ds.x.device)
+    acc = torch.zeros((ds.M,) * 3, dtype=torch.complex64, device=ds.device)
     n = ds.N if n_images is None else min(ds.N, n_images)
     if n < ds.N:
         idx = torch.from_numpy(np.random.default_rng([seed, synth.STREAM_MISC]).choice(ds.N, n, replace=False)).to(
-            ds.x.device)
+            ds.device)
         rot, df = ds.rot[idx].contiguous(), ds.defocus[idx].contiguous()
     else:
         rot, df = ds.rot, ds.defocus
-    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_BACKPROJECT, ds.x.device)
+    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_BACKPROJECT, ds.device)
     for s in range(0, n, CHUNK):
         e = min(n, s + CHUNK)
         B.feature_sums(ds.grid, ds.optics, rot[s:e].contiguous(), df[s:e].contiguous(), acc, workspace=ws)
@@ -60,8 +60,8 @@ def hutchinson_full(ds: Dataset, n_probe: int, seed: int, n_images: int | None =
     estimate from its first n_images images, rescaled by N / n_images)."""
     n = ds.N if n_images is None else min(ds.N, n_images)
     scale = ds.N / n
-    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.x.device)
-    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_HUTCHINSON, ds.x.device)
+    d = torch.zeros((ds.M,) * 3, dtype=torch.float32, device=ds.device)
+    ws = B.alloc_workspace(ds.grid, min(n, CHUNK), B.CSG_WS_HUTCHINSON, ds.device)
     for s in range(0, n, CHUNK):
         e = min(n, s + CHUNK)
         d += B.hutchinson_diag(ds.grid, ds.optics, ds.rot[s:e].contiguous(), ds.defocus[s:e].contiguous(),

@@ -26,6 +26,12 @@ TRAIN_SPECS = [(64, 10_000, 100, (0.5 + 0.25 * i, 2.0 + 0.25 * i)) for i in rang
 EVAL_SPECS = {
     "mid_128": dict(M=128, N=50_000, n_blobs=200, batch=256, defocus_um=(0.8, 3.0), seed=2128),
     "hires_256": dict(M=256, N=200_000, n_blobs=1000, batch=1024, defocus_um=(1.0, 3.0), seed=3256),
+    # ill-conditioned stress case: preferred orientations (von Mises-Fisher
+    # viewing directions, kappa 10), 500,000 images regenerated per batch
+    # (410 GB would not fit in device memory), deterministic adjoint
+    "stress_320": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
+                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-5, max_epochs=2,
+                       time_limit=120.0),
 }
 
 
@@ -50,19 +56,46 @@ def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: in
         spec = dict(EVAL_SPECS[name])
         batch = spec.pop("batch")
         seed = spec.pop("seed")
-        ds = E.make_dataset(spec["M"], spec["N"], spec["n_blobs"], seed, float("inf"), defocus_um=spec["defocus_um"])
+        ds = E.make_dataset(spec["M"], spec["N"], spec["n_blobs"], seed, float("inf"), defocus_um=spec["defocus_um"],
+                            poses=spec.get("poses", "uniform"), kappa=spec.get("kappa", 10.0),
+                            stream=spec.get("stream", False))
         res = {}
-        for stop in ("ball", "high"):
+        stops = ("high",) if ds.streamed else ("ball", "high")
+        for stop in stops:
             if log:
                 log("[tta] %s stop_on=%s" % (name, stop))
-            r = E.compare_arms(ds, batch, params=params, stop_on=stop, max_epochs=max_epochs, time_limit=time_limit,
-                               eval_every=10 if ds.M <= 128 else 5, log=log)
+            r = E.compare_arms(ds, batch, params=params, stop_on=stop, max_epochs=spec.get("max_epochs", max_epochs),
+                               time_limit=spec.get("time_limit", time_limit), eval_every=10 if ds.M <= 128 else 5,
+                               log=log, deterministic=spec.get("deterministic", False),
+                               cg_tol=spec.get("cg_tol", 1e-6))
             res[stop] = {arm: {"reached": a.reached, "iterations": a.iterations, "run_s": round(a.seconds, 4),
                                "setup_s": round(a.setup_seconds, 4), "total_s": round(a.total_seconds, 4),
-                               "note": a.note}
+                               "gen_s": round(a.gen_seconds, 4), "note": a.note}
                          for arm, a in r["arms"].items()}
             res["cg_iterations"] = r["cg_iterations"]
-        out[name] = dict(M=ds.M, N=ds.N, batch=batch, **res)
+            res["cg_residual"] = r["cg_residual"]
+        out[name] = dict(M=ds.M, N=ds.N, batch=batch, poses=spec.get("poses", "uniform"),
+                         deterministic=spec.get("deterministic", False), streamed=ds.streamed, **res)
         del ds
         torch.cuda.empty_cache()
     return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description="time to 1e-2 of the SGD arms")
+    ap.add_argument("--configs", default="mid_128,hires_256", help="comma-separated names of EVAL_SPECS")
+    ap.add_argument("--out", default=None, help="write the JSON result here as well")
+    args = ap.parse_args()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    params, _ = train_network(log=log)
+    res = evaluate(params, configs=tuple(args.configs.split(",")), log=log)
+    txt = json.dumps(res)
+    print(txt, flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(txt + "\n")
+
