@@ -247,6 +247,16 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
 #define CSG_WS_PROJECT 4
 size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
 
+/* Per-shell sums of two volumes over the Fourier shells round(|k|) = s,
+ * s = 0 .. M/2 - 1 (the shells of the shell correlation, eq. (fsc), Sec. 4.1):
+ *   sums_out[s]         = sum Re(u_k conj(v_k))
+ *   sums_out[M/2 + s]   = sum |u_k|^2
+ *   sums_out[M + s]     = sum |v_k|^2
+ * so FSC(s) = sums_out[s] / sqrt(sums_out[M/2 + s] sums_out[M + s]).
+ * u, v: device complex64 [M][M][M] (centred); sums_out: device double
+ * [3 M/2], overwritten.  Voxels beyond the last full shell are ignored. */
+int csg_shell_sums(const csg_grid *grid, const float *u, const float *v, double *sums_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support, not part of the method).  While
  * enabled, every launch of a brick-binned operator kernel is bracketed by two

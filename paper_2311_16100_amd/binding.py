@@ -73,6 +73,7 @@ EXPORTS = {
     "csg_learned_diag": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "csg_workspace_bytes": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32],
+    "csg_shell_sums": [ctypes.c_void_p] * 4 + [ctypes.c_void_p],
     "csg_timing_enable": [ctypes.c_int32],
     "csg_timing_read": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
     "csg_last_error": [],
@@ -404,6 +405,27 @@ def learned_diag(grid: Grid, n_images: int, lam: float, params, ctf2, cover, out
     _check(lib().csg_learned_diag(ctypes.byref(g), int(n_images), float(lam), _ptr(params), _ptr(ctf2),
                                   _ptr(cover), _ptr(out), _stream(stream)), "csg_learned_diag")
     return out
+
+
+def shell_sums(grid: Grid, u, v, out=None, stream=None):
+    """Per-shell (Re sum u conj v, sum |u|^2, sum |v|^2), each [M/2], as a
+    device float64 tensor [3, M/2]."""
+    M = grid.M
+    g = grid.c()
+    pu = _cplx(u, (M, M, M), "u")
+    pv = _cplx(v, (M, M, M), "v")
+    if out is None:
+        out = torch.empty((3, M // 2), dtype=torch.float64, device=u.device)
+    _check(lib().csg_shell_sums(ctypes.byref(g), pu, pv, _ptr(out), _stream(stream)), "csg_shell_sums")
+    return out
+
+
+def fsc(grid: Grid, u, v):
+    """Fourier shell correlation per shell s = 0 .. M/2 - 1 (eq. (fsc)); shells
+    where either volume vanishes give 0."""
+    s = shell_sums(grid, u, v)
+    den = torch.sqrt(s[1] * s[2])
+    return torch.where(den > 0, s[0] / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
 
 
 KERNELS = {"project": 0, "backproject": 1, "gradient": 2, "hvp": 3, "features": 4, "sq_diag": 5}

@@ -429,3 +429,12 @@ extern "C" int csg_timing_read(int32_t kernel, double *total_ms, int64_t *launch
     CSG_TRY(csg::timing_read(kernel, total_ms, launches), "csg_timing_read");
     return CSG_OK;
 }
+
+extern "C" int csg_shell_sums(const csg_grid *grid, const float *u, const float *v, double *sums_out, void *stream) {
+    if (!grid || grid->M < 4 || grid->M > 1024 || (grid->M & 1)) return fail(CSG_EINVAL, "csg_shell_sums: invalid grid");
+    if (!u || !v || !sums_out) return fail(CSG_EINVAL, "csg_shell_sums: NULL buffer");
+    CSG_TRY(csg::launch_shell_sums((const float2 *)u, (const float2 *)v, grid->M, sums_out, (hipStream_t)stream),
+            "csg_shell_sums");
+    return CSG_OK;
+}
+

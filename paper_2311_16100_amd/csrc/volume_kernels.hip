@@ -161,6 +161,73 @@ __global__ __launch_bounds__(kBlock) void ctf2_sum_kernel(Geom g, const float *_
     if (threadIdx.x == 0) *alpha_out = ratio * t + (double)lam;
 }
 
+// Per-shell sums of two volumes, shells round(|k|) = s < nsh (the Fourier
+// shells of the shell correlation):
+//   out[s] = sum Re(u conj v),  out[nsh + s] = sum |u|^2,  out[2 nsh + s] = sum |v|^2.
+// One thread walks one row of kx, accumulating while the shell is unchanged;
+// block partials in LDS, then one global double atomic per block and entry.
+// out must be zero on entry.
+__global__ __launch_bounds__(kBlock) void shell_sums_kernel(const float2 *__restrict__ u,
+                                                            const float2 *__restrict__ v, int M, int nsh,
+                                                            double *out) {
+    extern __shared__ double part[];  // [3][nsh]
+    for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x) part[i] = 0.0;
+    __syncthreads();
+    const int half = M / 2;
+    const int64_t rows = (int64_t)M * M;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < rows;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const int ky = (int)(row % M) - half, kz = (int)(row / M) - half;
+        const int base2 = ky * ky + kz * kz;
+        const float2 *pu = u + row * M, *pv = v + row * M;
+        int cur = -1;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int x = 0; x < M; ++x) {
+            const int kx = x - half;
+            const int k2 = base2 + kx * kx;
+            // round(sqrt(k2)) with integers: s^2 - s < k2 <= s^2 + s
+            int sh = (int)sqrtf((float)k2);
+            while (sh * sh + sh < k2) ++sh;
+            while (sh > 0 && sh * sh - sh >= k2) --sh;
+            if (sh != cur) {
+                if (cur >= 0 && cur < nsh) {
+                    atomicAdd(&part[cur], a);
+                    atomicAdd(&part[nsh + cur], b);
+                    atomicAdd(&part[2 * nsh + cur], c);
+                }
+                cur = sh;
+                a = b = c = 0.0;
+            }
+            const float2 U = pu[x], V = pv[x];
+            a += (double)U.x * V.x + (double)U.y * V.y;
+            b += (double)U.x * U.x + (double)U.y * U.y;
+            c += (double)V.x * V.x + (double)V.y * V.y;
+        }
+        if (cur >= 0 && cur < nsh) {
+            atomicAdd(&part[cur], a);
+            atomicAdd(&part[nsh + cur], b);
+            atomicAdd(&part[2 * nsh + cur], c);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * nsh; i += blockDim.x)
+        if (part[i] != 0.0) atomicAdd(&out[i], part[i]);
+}
+
+hipError_t launch_shell_sums(const float2 *u, const float2 *v, int M, double *out, hipStream_t st) {
+    const int nsh = M / 2;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(stream_blocks(6 * nsh)), dim3(kBlock), 0, st, (float *)out,
+                       (int64_t)6 * nsh, 0.0f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t rows = (int64_t)M * M;
+    int64_t blocks = (rows + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(shell_sums_kernel, dim3((unsigned)blocks), dim3(kBlock), (size_t)3 * nsh * sizeof(double), st,
+                       u, v, M, nsh, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, double ratio, float lam,
                         double *alpha_out, hipStream_t st) {
     hipLaunchKernelGGL(ctf2_sum_kernel, dim3(1), dim3(kBlock), 0, st, g, defocus, n, k2, ratio, lam, alpha_out);

@@ -202,6 +202,7 @@ class RunResult:
     halvings: int = 0
     capped: int = 0
     gen_seconds: float = 0.0  # regeneration of streamed images (not in `seconds`)
+    fsc: list = field(default_factory=list)  # (iteration, FSC per shell vs v*) at epoch ends and at the stop
     note: str = ""
 
     @property
@@ -271,11 +272,17 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
                 if (eb if stop_on == "ball" else eh) <= target:
                     res.reached, res.iterations, res.seconds = True, it, el
                     res.capped = run.state.capped
+                    res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
                     return res
                 if el > time_limit:
                     res.iterations, res.seconds, res.note = it, el, "time limit"
                     res.capped = run.state.capped
+                    res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
                     return res
+        # shell correlation with v* after each epoch (Sec. 4.1), outside the timed region
+        tf = time.perf_counter()
+        res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
+        t0 += time.perf_counter() - tf
     res.iterations, res.seconds, res.note = it, time.perf_counter() - t0 - res.gen_seconds, "epoch limit"
     res.capped = run.state.capped
     return res

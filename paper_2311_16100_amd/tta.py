@@ -30,8 +30,8 @@ EVAL_SPECS = {
     # viewing directions, kappa 10), 500,000 images regenerated per batch
     # (410 GB would not fit in device memory), deterministic adjoint
     "stress_320": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
-                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-5, max_epochs=2,
-                       time_limit=120.0),
+                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-5, max_epochs=8,
+                       time_limit=150.0),
 }
 
 
@@ -48,6 +48,14 @@ def train_network(specs=TRAIN_SPECS, steps: int = 2000, n_probe: int = 200, log=
         log("[tta] network trained on %d sets (%d samples) in %.1fs, final loss %.3e" % (
             len(sets), sum(s.X.shape[0] for s in sets), time.perf_counter() - t0, hist[-1][1]))
     return params, hist
+
+
+def fsc_summary(curve):
+    """Lowest shell correlation over shells 1 .. M/2 - 1 and the first shell
+    where it drops below 0.9 and 0.75 (None: never)."""
+    c = curve[1:]
+    first = lambda t: next((i + 1 for i, f in enumerate(c) if f < t), None)
+    return {"min": round(min(c), 6), "below_0.9": first(0.9), "below_0.75": first(0.75)}
 
 
 def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: int = 6, time_limit: float = 60.0):
@@ -70,7 +78,10 @@ def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: in
                                cg_tol=spec.get("cg_tol", 1e-6))
             res[stop] = {arm: {"reached": a.reached, "iterations": a.iterations, "run_s": round(a.seconds, 4),
                                "setup_s": round(a.setup_seconds, 4), "total_s": round(a.total_seconds, 4),
-                               "gen_s": round(a.gen_seconds, 4), "note": a.note}
+                               "gen_s": round(a.gen_seconds, 4), "note": a.note,
+                               "final_error": {"ball": round(a.errors[-1][2], 6), "high": round(a.errors[-1][3], 6)}
+                               if a.errors else None,
+                               "fsc_final": fsc_summary(a.fsc[-1][1]) if a.fsc else None}
                          for arm, a in r["arms"].items()}
             res["cg_iterations"] = r["cg_iterations"]
             res["cg_residual"] = r["cg_residual"]

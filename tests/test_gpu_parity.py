@@ -304,3 +304,17 @@ def test_full_size_backproject_and_adjoint(b, full):
     lhs = torch.vdot(Av.reshape(-1).to(torch.complex128), x.reshape(-1).to(torch.complex128))
     rhs = torch.vdot(v.reshape(-1).to(torch.complex128), acc.reshape(-1).to(torch.complex128))
     assert abs((lhs - rhs).item()) <= 1e-5 * abs(lhs.item())
+
+
+@pytest.mark.parametrize("M", [16, 34])
+def test_fsc_parity(b, M):
+    """Fourier shell correlation (eq. (fsc)) of two related random volumes:
+    library shell sums against the oracle, per shell."""
+    u = synth.random_complex((M, M, M), 100 + M)
+    v = (0.6 * u + 0.8 * synth.random_complex((M, M, M), 200 + M)).astype(np.complex64)
+    ref = oracle.fsc(u, v, M)
+    got = b.fsc(b.Grid(M), *to_dev(u, v)).cpu().numpy()
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) < 1e-6
+    sums = b.shell_sums(b.Grid(M), *to_dev(u, u)).cpu().numpy()
+    assert np.allclose(sums[0], sums[1]) and np.allclose(sums[1], sums[2])
