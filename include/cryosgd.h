@@ -67,19 +67,28 @@ typedef struct csg_optics {
     int32_t ctf_on;
 } csg_optics;
 
-/* Known poses phi_i (Definition "Projection operator"; no in-plane shifts)
- * and per-image CTF parameters of a batch of n >= 0 images. */
+/* Known poses phi_i (Definition "Projection operator", Sec. 2.1): rotation
+ * R_i, CTF defocus and the in-plane shift T_i.  Pixel (kx, ky) of image i
+ * samples the volume at kx R_i[0,:] + ky R_i[1,:] (rows of R_i span the image
+ * plane) and is multiplied by
+ *   T_jj = exp(-2 pi i (kx sx_i + ky sy_i) / M),
+ * the phase of a real-space translation of the image by (sx_i, sy_i) pixels.
+ * shift_px == NULL means T = I.  T is unitary and diagonal, so the Hessian
+ * (csg_hvp, csg_hutchinson_diag, csg_exact_diag) and the preconditioner
+ * features do not depend on it; csg_project, csg_backproject and csg_gradient
+ * apply it. */
 typedef struct csg_poses {
     int64_t n;
     const float *rot;       /* device [n][3][3] */
     const float *defocus_A; /* device [n], Angstrom, underfocus > 0 */
+    const float *shift_px;  /* device [n][2] (sx, sy) in pixels, or NULL */
 } csg_poses;
 
-/* Forward model without noise, eq. (fwd model): y_i = C_i P_i v.
+/* Forward model without noise, eq. (fwd model): y_i = C_i T_i P_i v.
  *   vol      device complex [M^3]
- *   subtract device complex [n][M][M] or NULL: if given, out = C P v - x
+ *   subtract device complex [n][M][M] or NULL: if given, out = C T P v - x
  *   out      device complex [n][M][M] or NULL (then loss_accum is required)
- *   loss_accum device double scalar or NULL: += 1/2 sum_disk |C P v - x|^2
+ *   loss_accum device double scalar or NULL: += 1/2 sum_disk |C T P v - x|^2
  *            (x = 0 when subtract is NULL).  Not zeroed by the call.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_PROJECT) bytes.
  * out and vol must not overlap. */
@@ -89,7 +98,7 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
 
 /* Adjoint / backprojection, the operator P_i^* C_i that appears in the M step
  * (eq. (em v)) and in b = sum_i P_i^* x_i (eq. (lin sys)):
- *   vol_accum += scale * sum_i P_i^T C_i^p img_i,  p = ctf_power in {0,1,2}.
+ *   vol_accum += scale * sum_i P_i^T T_i^* C_i^p img_i,  p = ctf_power in {0,1,2}.
  *   img        device complex [n][M][M] (pixels outside the disk ignored)
  *   vol_accum  device complex [M^3], accumulated into
  *   deterministic 0: fast scatter (floating-point summation order varies
@@ -104,8 +113,8 @@ int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_po
 /* Minibatch gradient and loss of the known-pose least-squares problem,
  * eq. (optim cp) with the CTF re-inserted (eq. (em v)) and the batch scaled
  * by `scale` (N/B for an unbiased estimate of the full objective):
- *   f(v)     = scale * 1/2 sum_i ||C_i P_i v - x_i||^2 + lambda/2 ||v||^2
- *   grad_out = scale * sum_i P_i^T C_i (C_i P_i v - x_i) + lambda v
+ *   f(v)     = scale * 1/2 sum_i ||C_i T_i P_i v - x_i||^2 + lambda/2 ||v||^2
+ *   grad_out = scale * sum_i P_i^T T_i^* C_i (C_i T_i P_i v - x_i) + lambda v
  * (complex gradient convention d/dRe + i d/dIm).  The residual images are
  * never written to memory.
  *   vol       device complex [M^3];  x device complex [n][M][M]

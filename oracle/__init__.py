@@ -68,8 +68,8 @@ def lib():
         L.or_wavelength_A.restype = d
         L.or_ctf.argtypes = [P(_Optics), i32, d, d]
         L.or_ctf.restype = d
-        L.or_project.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp]
-        L.or_backproject.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, i32, d, vp]
+        L.or_project.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp, vp]
+        L.or_backproject.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp, i32, d, vp]
         L.or_sq_backproject.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, d, vp]
         L.or_features.argtypes = [P(_Grid), P(_Optics), i64, vp, vp, vp, vp]
         _lib = L
@@ -115,22 +115,26 @@ NO_CTF = Optics(ctf_on=False)
 class Poses:
     rot: np.ndarray      # float32 [n,3,3]
     defocus: np.ndarray  # float32 [n], Angstrom
+    shift: np.ndarray | None = None  # float32 [n,2] in-plane shift (sx, sy) in pixels, or None (T = I)
 
     def __post_init__(self):
         self.rot = np.ascontiguousarray(self.rot, dtype=np.float32).reshape(-1, 3, 3)
         self.defocus = np.ascontiguousarray(self.defocus, dtype=np.float32).reshape(-1)
         assert self.rot.shape[0] == self.defocus.shape[0]
+        if self.shift is not None:
+            self.shift = np.ascontiguousarray(self.shift, dtype=np.float32).reshape(-1, 2)
+            assert self.shift.shape[0] == self.rot.shape[0]
 
     @property
     def n(self) -> int:
         return self.rot.shape[0]
 
     def subset(self, idx) -> "Poses":
-        return Poses(self.rot[idx], self.defocus[idx])
+        return Poses(self.rot[idx], self.defocus[idx], None if self.shift is None else self.shift[idx])
 
 
-def _ptr(a: np.ndarray):
-    return a.ctypes.data_as(ctypes.c_void_p)
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _c128(a) -> np.ndarray:
@@ -176,7 +180,7 @@ def project(grid: Grid, optics: Optics, poses: Poses, vol) -> np.ndarray:
     out = np.zeros((poses.n, M, M), dtype=np.complex128)
     g, o = grid.c(), optics.c()
     lib().or_project(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
-                     _ptr(v), _ptr(out))
+                     _ptr(poses.shift), _ptr(v), _ptr(out))
     return out
 
 
@@ -188,7 +192,7 @@ def backproject(grid: Grid, optics: Optics, poses: Poses, img, ctf_power: int = 
     out = np.zeros((M, M, M), dtype=np.complex128) if accum is None else _c128(accum).copy()
     g, o = grid.c(), optics.c()
     lib().or_backproject(ctypes.byref(g), ctypes.byref(o), poses.n, _ptr(poses.rot), _ptr(poses.defocus),
-                         _ptr(im), int(ctf_power), float(scale), _ptr(out))
+                         _ptr(poses.shift), _ptr(im), int(ctf_power), float(scale), _ptr(out))
     return out
 
 

@@ -194,11 +194,26 @@ static int in_disk(const or_grid *g, int kx, int ky)
 }
 
 /*
- * Forward model without noise, eq. (fwd model): out_i = C_i P_i v.
+ * In-plane shift of image i, the diagonal T_i of Definition "Projection
+ * operator" (Sec. 2.1): translating the image by (sx, sy) pixels multiplies
+ * pixel (kx, ky) of its discrete Fourier transform by
+ *   T_jj = exp(-2 pi i (kx sx + ky sy) / M).
+ * shift == NULL means T = I.
+ */
+static double complex shift_phase(const float *shift, int64_t i, int M, int kx, int ky)
+{
+    if (!shift) return 1.0;
+    double t = -((double)kx * (double)shift[2 * i] + (double)ky * (double)shift[2 * i + 1]) / (double)M;
+    double a = 2.0 * M_PI * t;
+    return cos(a) + I * sin(a);
+}
+
+/*
+ * Forward model without noise, eq. (fwd model): out_i = C_i T_i P_i v.
  * out is [n][M][M]; pixels outside the disk are set to zero.
  */
 void or_project(const or_grid *g, const or_optics *o, int64_t n, const float *rot,
-                const float *defocus, const double complex *vol, double complex *out)
+                const float *defocus, const float *shift, const double complex *vol, double complex *out)
 {
     int M = g->M, h = M / 2;
     for (int64_t i = 0; i < n; ++i) {
@@ -215,7 +230,7 @@ void or_project(const or_grid *g, const or_optics *o, int64_t n, const float *ro
                 double complex acc = 0.0;
                 for (int c = 0; c < cnt; ++c) acc += w[c] * vol[vox[c]];
                 double C = or_ctf(o, M, (double)defocus[i], (double)kx * kx + (double)ky * ky);
-                out[j] = C * acc;
+                out[j] = C * shift_phase(shift, i, M, kx, ky) * acc;
             }
         }
     }
@@ -224,11 +239,12 @@ void or_project(const or_grid *g, const or_optics *o, int64_t n, const float *ro
 /*
  * Adjoint (backprojection), the operator P_i^* C_i^p that appears in the
  * M-step (eq. (em v)) and in b = sum_i P_i^* x_i (Sec. 3.1):
- *   vol_accum += scale * sum_i P_i^T C_i^p img_i.
- * With T = I the adjoint of the real interpolation matrix is its transpose.
+ *   vol_accum += scale * sum_i P_i^T conj(T_i) C_i^p img_i
+ * (the adjoint of the real interpolation matrix is its transpose; T_i is
+ * unitary and diagonal).
  */
 void or_backproject(const or_grid *g, const or_optics *o, int64_t n, const float *rot,
-                    const float *defocus, const double complex *img, int ctf_power,
+                    const float *defocus, const float *shift, const double complex *img, int ctf_power,
                     double scale, double complex *vol_accum)
 {
     int M = g->M, h = M / 2;
@@ -245,7 +261,8 @@ void or_backproject(const or_grid *g, const or_optics *o, int64_t n, const float
                 int64_t vox[8];
                 double w[8];
                 int cnt = pixel_stencil(g, R, kx, ky, vox, w);
-                for (int c = 0; c < cnt; ++c) vol_accum[vox[c]] += scale * w[c] * Cp * img[j];
+                double complex x = conj(shift_phase(shift, i, M, kx, ky)) * img[j];
+                for (int c = 0; c < cnt; ++c) vol_accum[vox[c]] += scale * w[c] * Cp * x;
             }
         }
     }

@@ -41,7 +41,8 @@ class _Optics(ctypes.Structure):
 
 
 class _Poses(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("rot", ctypes.c_void_p), ("defocus_A", ctypes.c_void_p)]
+    _fields_ = [("n", ctypes.c_int64), ("rot", ctypes.c_void_p), ("defocus_A", ctypes.c_void_p),
+                ("shift_px", ctypes.c_void_p)]
 
 
 EXPORTS = {
@@ -149,13 +150,15 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _poses(rot: torch.Tensor, defocus: torch.Tensor) -> _Poses:
+def _poses(rot: torch.Tensor, defocus: torch.Tensor, shift: torch.Tensor | None = None) -> _Poses:
     if rot.dtype != torch.float32 or defocus.dtype != torch.float32:
         raise CsgError("rotations and defocus must be float32")
     n = rot.shape[0] if rot.dim() == 3 else rot.numel() // 9
     if rot.numel() != 9 * n or defocus.numel() != n:
         raise CsgError("rot must be [n,3,3] and defocus [n]")
-    return _Poses(n, _ptr(rot), _ptr(defocus))
+    if shift is not None and (shift.dtype != torch.float32 or shift.numel() != 2 * n):
+        raise CsgError("shift must be float32 [n,2]")
+    return _Poses(n, _ptr(rot), _ptr(defocus), _ptr(shift))
 
 
 def _cplx(t: torch.Tensor, shape, name):
@@ -189,10 +192,11 @@ def _ws(ws):
 # Entry points (same names as the C ABI without the csg_ prefix)
 # ---------------------------------------------------------------------------
 def project(grid: Grid, optics: Optics, rot, defocus, vol, subtract=None, out=None, loss=None,
-            want_out: bool = True, workspace=None, stream=None):
-    """C P v (- subtract) for each image; returns `out` (allocated if None)."""
+            want_out: bool = True, workspace=None, stream=None, shift=None):
+    """C T P v (- subtract) for each image; returns `out` (allocated if None).
+    `shift`: float32 [n,2] in-plane shifts in pixels (None: no shift)."""
     M = grid.M
-    p = _poses(rot, defocus)
+    p = _poses(rot, defocus, shift)
     if want_out and out is None:
         out = torch.empty((p.n, M, M), dtype=torch.complex64, device=vol.device)
     if workspace is None:
@@ -207,10 +211,10 @@ def project(grid: Grid, optics: Optics, rot, defocus, vol, subtract=None, out=No
 
 
 def backproject(grid: Grid, optics: Optics, rot, defocus, img, ctf_power: int = 1, scale: float = 1.0,
-                accum=None, deterministic: bool = False, workspace=None, stream=None):
-    """accum += scale P^T C^p img; returns accum (zeros if None)."""
+                accum=None, deterministic: bool = False, workspace=None, stream=None, shift=None):
+    """accum += scale P^T T^* C^p img; returns accum (zeros if None)."""
     M = grid.M
-    p = _poses(rot, defocus)
+    p = _poses(rot, defocus, shift)
     if accum is None:
         accum = torch.zeros((M, M, M), dtype=torch.complex64, device=img.device)
     if workspace is None and not deterministic:
@@ -225,10 +229,10 @@ def backproject(grid: Grid, optics: Optics, rot, defocus, img, ctf_power: int = 
 
 
 def gradient(grid: Grid, optics: Optics, rot, defocus, vol, x, scale: float, lam: float, grad_out=None,
-             loss_out=None, deterministic: bool = False, workspace=None, stream=None):
-    """grad = scale P^T C (C P v - x) + lam v; loss_out (device float64 [1]) = f(v)."""
+             loss_out=None, deterministic: bool = False, workspace=None, stream=None, shift=None):
+    """grad = scale P^T T^* C (C T P v - x) + lam v; loss_out (device float64 [1]) = f(v)."""
     M = grid.M
-    p = _poses(rot, defocus)
+    p = _poses(rot, defocus, shift)
     if grad_out is None:
         grad_out = torch.empty((M, M, M), dtype=torch.complex64, device=vol.device)
     if workspace is None:

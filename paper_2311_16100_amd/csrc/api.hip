@@ -129,9 +129,9 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
     if (out && out == vol) return fail(CSG_EINVAL, "csg_project: out must not alias vol");
     const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_PROJECT);
     if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_project"))) return rc;
-    CSG_TRY(csg::launch_brick_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
-                                      (const float2 *)subtract, (float2 *)out, loss_accum, workspace,
-                                      (hipStream_t)stream),
+    CSG_TRY(csg::launch_brick_project(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                      (const float2 *)vol, (const float2 *)subtract, (float2 *)out, loss_accum,
+                                      workspace, (hipStream_t)stream),
             "csg_project");
     return CSG_OK;
 }
@@ -148,14 +148,15 @@ int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_po
     if (!img || !vol_accum) return fail(CSG_EINVAL, "csg_backproject: img and vol_accum must be non-NULL");
     hipStream_t st = (hipStream_t)stream;
     if (deterministic) {
-        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
-                                              ctf_power, scale, (float2 *)vol_accum, st),
+        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                              (const float2 *)img, ctf_power, scale, (float2 *)vol_accum, st),
                 "csg_backproject");
     } else {
         const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT);
         if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_backproject"))) return rc;
-        CSG_TRY(csg::launch_brick_backproject(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)img,
-                                              ctf_power, scale, (float2 *)vol_accum, workspace, st),
+        CSG_TRY(csg::launch_brick_backproject(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                              (const float2 *)img, ctf_power, scale, (float2 *)vol_accum, workspace,
+                                              st),
                 "csg_backproject");
     }
     return CSG_OK;
@@ -180,17 +181,17 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
     CSG_TRY(csg::launch_scaled_copy((float2 *)grad_out, (const float2 *)vol, lambda, nv, sc + 1, st), "csg_gradient");
     if (poses->n > 0) {
         if (!deterministic) {
-            CSG_TRY(csg::launch_brick_gradient(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
-                                               (const float2 *)x, scale, (float2 *)grad_out, sc,
+            CSG_TRY(csg::launch_brick_gradient(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                               (const float2 *)vol, (const float2 *)x, scale, (float2 *)grad_out, sc,
                                                (char *)workspace + kScalarBytes, st),
                     "csg_gradient");
         } else {
             float2 *resid = (float2 *)((char *)workspace + kScalarBytes);
-            CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
-                                        (const float2 *)x, resid, sc, st),
+            CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                        (const float2 *)vol, (const float2 *)x, resid, sc, st),
                     "csg_gradient");
-            CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, resid, 1, scale,
-                                                  (float2 *)grad_out, st),
+            CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n, resid,
+                                                  1, scale, (float2 *)grad_out, st),
                     "csg_gradient");
         }
     }
@@ -222,10 +223,11 @@ int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *pos
                 "csg_hvp");
     } else {
         float2 *img = (float2 *)((char *)workspace + kScalarBytes);
-        CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, nullptr, img,
-                                    nullptr, st),
+        // T^* T = I: the Hessian does not involve the in-plane shifts
+        CSG_TRY(csg::launch_project(g, poses->rot, poses->defocus_A, nullptr, poses->n, (const float2 *)z, nullptr,
+                                    img, nullptr, st),
                 "csg_hvp");
-        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->n, img, 1, scale,
+        CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, nullptr, poses->n, img, 1, scale,
                                               (float2 *)hz_out, st),
                 "csg_hvp");
     }

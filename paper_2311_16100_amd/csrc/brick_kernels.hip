@@ -67,6 +67,7 @@ struct BrickArgs {
     Geom g;
     const float *rot;
     const float *defocus;
+    const float *shift; // [n][2] in-plane shifts or NULL (project, backproject, gradient)
     int64_t n;          // images of this sub-batch
     const float2 *src;  // gathered volume
     const float2 *img;  // x (project subtract / gradient) or adjoint input
@@ -261,10 +262,10 @@ struct ImgSlot {
     double E2[3];
     int64_t E1i[3];    // the same as integers (the per-pixel step)
     double ctfA;       // (lambda df / 2) / (M pixel)^2: chi / 2pi = k2 (ctfA - ctfB k2)
-    int ky_lo;         // first row that can reach the box
-    int row0;          // index of that row's record in the window
     uint32_t img_base; // index of pixel (0, 0) of the image: i M^2
-    int pad;
+    short ky_lo;       // first row that can reach the box
+    unsigned short row0; // index of that row's record in the window
+    float sx, sy;      // in-plane shift (pixels)
 };
 
 // rows of one image that reach a brick's enumeration box (side BS + 1):
@@ -302,6 +303,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool OWNER_ONLY = MODE == kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
+    constexpr bool SHIFTED = READS_IMG;  // modes that apply the in-plane shift
     constexpr int CHUNK = OWNER_ONLY ? CHUNK_FWD : CHUNK_ADJ;
     __shared__ float2 vh[GATHER ? BH * VP : 1];
     __shared__ double acc_re[SCATTER ? BS * AP : 1];
@@ -309,8 +311,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
-    // the item's images: index (as int bits), rows 0 and 1 of R, defocus
-    __shared__ float imgdat[CHUNK][8];
+    // the item's images: index (as int bits), rows 0 and 1 of R, defocus,
+    // in-plane shift
+    __shared__ float imgdat[CHUNK][10];
     // row record: x = first run | len << 16 | image slot << 24,
     //             y = (kx0 + 32768) | (ky + 32768) << 16
     __shared__ int2 seg[ROWCAP];
@@ -374,13 +377,15 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
             }
         }
         if (holds_img) {
-            float e[7];
+            float e[9];
 #pragma unroll
             for (int d = 0; d < 6; ++d) e[d] = a.rot[(int64_t)my_ii * 9 + d];
             e[6] = a.defocus[my_ii];
+            e[7] = a.shift ? a.shift[2 * my_ii] : 0.f;
+            e[8] = a.shift ? a.shift[2 * my_ii + 1] : 0.f;
             imgdat[threadIdx.x][0] = __int_as_float(my_ii);
 #pragma unroll
-            for (int d = 0; d < 7; ++d) imgdat[threadIdx.x][1 + d] = e[d];
+            for (int d = 0; d < 9; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         }
         if (SCATTER) {
             for (int t = threadIdx.x; t < BS * AP; t += kBT) {
@@ -423,6 +428,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                     }
                     S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
                     S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
+                    S.sx = D[8];
+                    S.sy = D[9];
                     // rows: range of e2 . (g - half) over the box
                     float ylo = 0.f, yhi = 0.f;
 #pragma unroll
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                     const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
                     const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
                     if (fl <= fh) {
-                        S.ky_lo = (int)fl;
+                        S.ky_lo = (short)(int)fl;
                         nrows = min((int)fh - (int)fl + 1, MAXROWS);
                     } else {
                         S.ky_lo = 0;
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                     if (t >= off) x += y;
                 }
                 if (t < nw) {
-                    slot[t].row0 = x - nrows;
+                    slot[t].row0 = (unsigned short)(x - nrows);
                     for (int q = 0; q < nrows; ++q) row2img[x - nrows + q] = (unsigned char)t;
                 }
                 if (t == WI - 1) rows_total = x;
@@ -594,6 +601,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                         acc.y = fmaf(w, v.y, acc.y);
                                     }
                                 }
+                                // in-plane shift: T on the forward value, conj(T)
+                                // on the adjoint input
+                                float2 T = make_float2(1.f, 0.f);
+                                if (SHIFTED && a.shift) {
+                                    const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
+                                                      (double)M;
+                                    const float fr = (float)(tt - rint(tt));
+                                    T = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+                                    if (GATHER) acc = cmul(acc, T);
+                                }
                                 float2 val = make_float2(0.f, 0.f);
                                 if (MODE == kBProject) {
                                     float2 y = make_float2(C * acc.x, C * acc.y);
@@ -604,7 +621,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                     if (a.out) a.out[j] = y;
                                     lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
                                 } else if (MODE == kBBackproject) {
-                                    const float2 x = xin[jj];
+                                    const float2 x = cmul_conj(xin[jj], T);
                                     const float fct = a.scale * ctf_pow(C, a.ctf_power);
                                     val = make_float2(fct * x.x, fct * x.y);
                                 } else if (MODE == kBGradient) {
@@ -612,7 +629,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                     const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
                                     if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
                                     const float fct = a.scale * C;
-                                    val = make_float2(fct * rr.x, fct * rr.y);
+                                    const float2 rt = cmul_conj(rr, T);
+                                    val = make_float2(fct * rt.x, fct * rt.y);
                                 } else if (MODE == kBHvp) {
                                     const float fct = a.scale * C * C;
                                     val = make_float2(fct * acc.x, fct * acc.y);
@@ -777,9 +795,9 @@ static int resident_blocks() {
 }
 
 template <int MODE>
-static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *src,
-                                 const float2 *img, float2 *out, float2 *accum, double *loss, float scale,
-                                 int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr) {
+static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                                 const float2 *src, const float2 *img, float2 *out, float2 *accum, double *loss,
+                                 float scale, int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr) {
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
@@ -811,6 +829,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.g = g;
         a.rot = rot + s0 * 9;
         a.defocus = defocus + s0;
+        a.shift = shift ? shift + s0 * 2 : nullptr;
         a.n = ns;
         a.src = src;
         a.img = img ? img + s0 * img_stride : nullptr;
@@ -839,11 +858,13 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
 
 // The brick kernels implement trilinear interpolation; nearest-neighbour
 // grids (the exact-pin mode of Sec. 3.1) use the pixel-parallel kernels.
-hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                const float2 *subtract, float2 *out, double *loss, void *ws, hipStream_t st) {
+hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                                const float2 *vol, const float2 *subtract, float2 *out, double *loss, void *ws,
+                                hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (g.interp == 0) return launch_project(g, rot, defocus, n, vol, subtract, out, loss, st);
-    hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws, st);
+    if (g.interp == 0) return launch_project(g, rot, defocus, shift, n, vol, subtract, out, loss, st);
+    hipError_t e = run_brick_mode<kBProject>(g, rot, defocus, shift, n, vol, subtract, out, nullptr, loss, 1.0f, 0, ws,
+                                             st);
     if (e != hipSuccess || !out) return e;
     int64_t blocks = (n * (int64_t)g.M + 3) / 4;  // four waves (rows) per block
     if (blocks > 16384) blocks = 16384;
@@ -852,42 +873,44 @@ hipError_t launch_brick_project(const Geom &g, const float *rot, const float *de
     return hipGetLastError();
 }
 
-hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                    const float2 *img, int ctf_power, float scale, float2 *accum, void *ws,
-                                    hipStream_t st) {
+hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                    void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (g.interp == 0) return launch_backproject_atomic(g, rot, defocus, n, img, ctf_power, scale, accum, st);
-    return run_brick_mode<kBBackproject>(g, rot, defocus, n, nullptr, img, nullptr, accum, nullptr, scale, ctf_power,
-                                         ws, st);
+    if (g.interp == 0) return launch_backproject_atomic(g, rot, defocus, shift, n, img, ctf_power, scale, accum, st);
+    return run_brick_mode<kBBackproject>(g, rot, defocus, shift, n, nullptr, img, nullptr, accum, nullptr, scale,
+                                         ctf_power, ws, st);
 }
 
-hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                 const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st) {
+hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                                 const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
+                                 void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (g.interp == 0) return launch_gradient_atomic(g, rot, defocus, n, vol, x, scale, accum, loss, st);
-    return run_brick_mode<kBGradient>(g, rot, defocus, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
+    if (g.interp == 0) return launch_gradient_atomic(g, rot, defocus, shift, n, vol, x, scale, accum, loss, st);
+    return run_brick_mode<kBGradient>(g, rot, defocus, shift, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
 }
 
 hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,
                                      float2 *accum, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
-    return run_brick_mode<kBFeatures>(g, rot, defocus, n, nullptr, nullptr, nullptr, accum, nullptr, 1.0f, 0, ws, st);
+    return run_brick_mode<kBFeatures>(g, rot, defocus, nullptr, n, nullptr, nullptr, nullptr, accum, nullptr, 1.0f, 0,
+                                      ws, st);
 }
 
 hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
                                 float *diag, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_sq_diag(g, rot, defocus, n, scale, diag, st);
-    return run_brick_mode<kBSqDiag>(g, rot, defocus, n, nullptr, nullptr, nullptr, nullptr, nullptr, scale, 2, ws, st,
-                                    diag);
+    return run_brick_mode<kBSqDiag>(g, rot, defocus, nullptr, n, nullptr, nullptr, nullptr, nullptr, nullptr, scale, 2,
+                                    ws, st, diag);
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
                             float scale, float2 *accum, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_hvp_atomic(g, rot, defocus, n, z, scale, accum, st);
-    return run_brick_mode<kBHvp>(g, rot, defocus, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
+    return run_brick_mode<kBHvp>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
 }
 
 }  // namespace csg

@@ -37,6 +37,24 @@ __device__ __forceinline__ float ctf_value(const Geom &g, double a_i, int k2) {
     return -__builtin_amdgcn_sinf(fr);
 }
 
+// In-plane shift of image i (Definition "Projection operator"): the phase
+// T = exp(-2 pi i (kx sx + ky sy) / M) of a translation by (sx, sy) pixels,
+// returned as (cos, sin).  The angle is formed in double precision in turns
+// and reduced to [-1/2, 1/2] for the hardware turn-sine and turn-cosine.
+__device__ __forceinline__ float2 shift_phase(const float *shift, int64_t i, int M, int kx, int ky) {
+    const double t = -((double)kx * (double)shift[2 * i] + (double)ky * (double)shift[2 * i + 1]) / (double)M;
+    const float fr = (float)(t - rint(t));
+    return make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+}
+
+// a * t and a * conj(t) for complex values held as float2
+__device__ __forceinline__ float2 cmul(float2 a, float2 t) {
+    return make_float2(a.x * t.x - a.y * t.y, a.x * t.y + a.y * t.x);
+}
+__device__ __forceinline__ float2 cmul_conj(float2 a, float2 t) {
+    return make_float2(a.x * t.x + a.y * t.y, a.y * t.x - a.x * t.y);
+}
+
 __device__ __forceinline__ float ctf_pow(float c, int p) {
     return p == 0 ? 1.0f : (p == 1 ? c : c * c);
 }

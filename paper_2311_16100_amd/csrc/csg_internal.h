@@ -23,13 +23,15 @@ hipError_t timing_read(int kernel, double *total_ms, int64_t *launches);
 // brick-binned kernels (brick_kernels.hip)
 int brick_count(int M);
 size_t brick_workspace_bytes(int M, int64_t n);
-hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                const float2 *subtract, float2 *out, double *loss, void *ws, hipStream_t st);
-hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                    const float2 *img, int ctf_power, float scale, float2 *accum, void *ws,
-                                    hipStream_t st);
-hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                 const float2 *x, float scale, float2 *accum, double *loss, void *ws, hipStream_t st);
+hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                                const float2 *vol, const float2 *subtract, float2 *out, double *loss, void *ws,
+                                hipStream_t st);
+hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                    void *ws, hipStream_t st);
+hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                                 const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
+                                 void *ws, hipStream_t st);
 hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,
                                      float2 *accum, void *ws, hipStream_t st);
 hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
@@ -38,20 +40,23 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
                             float scale, float2 *accum, void *ws, hipStream_t st);
 
 // pixel-parallel kernels (pixel_kernels.hip)
-hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                          const float2 *subtract, float2 *out, double *loss, hipStream_t st);
-hipError_t launch_backproject_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                     const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st);
-hipError_t launch_gradient_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                  const float2 *x, float scale, float2 *accum, double *loss, hipStream_t st);
+hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                          const float2 *vol, const float2 *subtract, float2 *out, double *loss, hipStream_t st);
+hipError_t launch_backproject_atomic(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                     int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                     hipStream_t st);
+hipError_t launch_gradient_atomic(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                  int64_t n, const float2 *vol, const float2 *x, float scale, float2 *accum,
+                                  double *loss, hipStream_t st);
 hipError_t launch_hvp_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
                              float scale, float2 *accum, hipStream_t st);
 hipError_t launch_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
                           float *accum, hipStream_t st);
 
 // voxel-parallel (owner computes) kernels (voxel_kernels.hip)
-hipError_t launch_backproject_owner(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                    const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st);
+hipError_t launch_backproject_owner(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                    hipStream_t st);
 hipError_t launch_features(const Geom &g, const float *rot, const float *defocus, int64_t n, float *ctf2,
                            float *cover, hipStream_t st);
 

@@ -25,6 +25,7 @@ struct PixelArgs {
     Geom g;
     const float *rot;
     const float *defocus;
+    const float *shift;  // [n][2] in-plane shifts or NULL
     int64_t n;
     const float2 *src;   // gathered volume (project / gradient / hvp)
     const float2 *img;   // image stack read (subtract, backproject input, data x)
@@ -92,6 +93,11 @@ __global__ __launch_bounds__(kBlock) void pixel_kernel(PixelArgs a) {
                 acc.y = fmaf(s.w[c], v.y, acc.y);
             }
         }
+        // in-plane shift: T on the forward value, conj(T) on the adjoint input
+        float2 T = make_float2(1.f, 0.f);
+        if (a.shift && (MODE == kProject || MODE == kBackproject || MODE == kGradient))
+            T = shift_phase(a.shift, i, M, kx, ky);
+        if (MODE == kProject || MODE == kGradient) acc = cmul(acc, T);
         float2 val = make_float2(0.f, 0.f);
         if (MODE == kProject) {
             float2 y = make_float2(C * acc.x, C * acc.y);
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void pixel_kernel(PixelArgs a) {
             if (a.out) a.out[j] = y;
             lsum = 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
         } else if (MODE == kBackproject) {
-            const float2 x = a.img[j];
+            const float2 x = cmul_conj(a.img[j], T);
             const float f = a.scale * ctf_pow(C, a.ctf_power);
             val = make_float2(f * x.x, f * x.y);
         } else if (MODE == kGradient) {
@@ -111,7 +117,8 @@ __global__ __launch_bounds__(kBlock) void pixel_kernel(PixelArgs a) {
             const float2 r = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
             lsum = 0.5 * ((double)r.x * r.x + (double)r.y * r.y);
             const float f = a.scale * C;
-            val = make_float2(f * r.x, f * r.y);
+            const float2 rt = cmul_conj(r, T);
+            val = make_float2(f * rt.x, f * rt.y);
         } else if (MODE == kHvp) {
             const float f = a.scale * C * C;
             val = make_float2(f * acc.x, f * acc.y);
@@ -152,26 +159,28 @@ static hipError_t launch_mode(const PixelArgs &a0, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                          const float2 *subtract, float2 *out, double *loss, hipStream_t st) {
+hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
+                          const float2 *vol, const float2 *subtract, float2 *out, double *loss, hipStream_t st) {
     PixelArgs a{};
-    a.g = g; a.rot = rot; a.defocus = defocus; a.n = n;
+    a.g = g; a.rot = rot; a.defocus = defocus; a.shift = shift; a.n = n;
     a.src = vol; a.img = subtract; a.out = out; a.loss = loss;
     return launch_mode<kProject>(a, st);
 }
 
-hipError_t launch_backproject_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                     const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st) {
+hipError_t launch_backproject_atomic(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                     int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                     hipStream_t st) {
     PixelArgs a{};
-    a.g = g; a.rot = rot; a.defocus = defocus; a.n = n;
+    a.g = g; a.rot = rot; a.defocus = defocus; a.shift = shift; a.n = n;
     a.img = img; a.accum = accum; a.ctf_power = ctf_power; a.scale = scale;
     return launch_mode<kBackproject>(a, st);
 }
 
-hipError_t launch_gradient_atomic(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *vol,
-                                  const float2 *x, float scale, float2 *accum, double *loss, hipStream_t st) {
+hipError_t launch_gradient_atomic(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                  int64_t n, const float2 *vol, const float2 *x, float scale, float2 *accum,
+                                  double *loss, hipStream_t st) {
     PixelArgs a{};
-    a.g = g; a.rot = rot; a.defocus = defocus; a.n = n;
+    a.g = g; a.rot = rot; a.defocus = defocus; a.shift = shift; a.n = n;
     a.src = vol; a.img = x; a.accum = accum; a.scale = scale; a.loss = loss;
     return launch_mode<kGradient>(a, st);
 }

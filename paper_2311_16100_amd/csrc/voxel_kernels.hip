@@ -29,6 +29,7 @@ struct VoxArgs {
     Geom g;
     const float *rot;
     const float *defocus;
+    const float *shift;  // [n][2] in-plane shifts or NULL (backprojection)
     int64_t n;
     const float2 *img;
     float2 *accum;
@@ -44,6 +45,7 @@ struct ImgEntry {
     float l1;  // |e3|_1, the reach of the plane into the L-infinity unit ball
     double a;  // CTF defocus term of the image
     int64_t idx;
+    float sx, sy;  // in-plane shift (pixels)
 };
 
 template <int MODE, int INTERP>
@@ -87,6 +89,8 @@ __global__ __launch_bounds__(kBlock) void voxel_kernel(VoxArgs a) {
             keep = fabsf(h) <= reach + 1e-3f;
             e.a = g.ctf_a * (double)a.defocus[ii];
             e.idx = ii;
+            e.sx = a.shift ? a.shift[2 * ii] : 0.f;
+            e.sy = a.shift ? a.shift[2 * ii + 1] : 0.f;
         }
         const uint64_t mask = __ballot(keep);
         if (lane == 0) wave_count[wv] = __popcll(mask);
@@ -141,7 +145,12 @@ __global__ __launch_bounds__(kBlock) void voxel_kernel(VoxArgs a) {
                     const float C = ctf_value(g, E.a, k2);
                     if (MODE == kVoxBackproject) {
                         const int64_t j = (E.idx * M + (ky + g.half)) * (int64_t)M + (kx + g.half);
-                        const float2 x = a.img[j];
+                        float2 x = a.img[j];
+                        if (a.shift) {
+                            // conj(T) of the in-plane shift (exact zero shift: T = 1)
+                            const float sh[2] = {E.sx, E.sy};
+                            x = cmul_conj(x, shift_phase(sh, 0, M, kx, ky));
+                        }
                         const float f = a.scale * ctf_pow(C, a.ctf_power);
                         const float fx = f * x.x, fy = f * x.y;
                         accx = fmaf(w, fx, accx);
@@ -188,10 +197,11 @@ static hipError_t launch_vox(const VoxArgs &a0, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_backproject_owner(const Geom &g, const float *rot, const float *defocus, int64_t n,
-                                    const float2 *img, int ctf_power, float scale, float2 *accum, hipStream_t st) {
+hipError_t launch_backproject_owner(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                    hipStream_t st) {
     VoxArgs a{};
-    a.g = g; a.rot = rot; a.defocus = defocus; a.n = n;
+    a.g = g; a.rot = rot; a.defocus = defocus; a.shift = shift; a.n = n;
     a.img = img; a.accum = accum; a.ctf_power = ctf_power; a.scale = scale;
     return launch_vox<kVoxBackproject>(a, st);
 }

@@ -30,7 +30,7 @@ EVAL_SPECS = {
     # viewing directions, kappa 10), 500,000 images regenerated per batch
     # (410 GB would not fit in device memory), deterministic adjoint
     "stress_320": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
-                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-5, max_epochs=8,
+                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-9, max_epochs=8,
                        time_limit=150.0),
 }
 

@@ -318,3 +318,37 @@ def test_fsc_parity(b, M):
     assert np.max(np.abs(got - ref)) < 1e-6
     sums = b.shell_sums(b.Grid(M), *to_dev(u, u)).cpu().numpy()
     assert np.allclose(sums[0], sums[1]) and np.allclose(sums[1], sums[2])
+
+
+SHIFT_CASES = [
+    dict(M=36, n=37, seed=41, interp=1, ctf=True),
+    dict(M=32, n=300, seed=42, interp=1, ctf=True, poses="vmf"),
+    dict(M=16, n=9, seed=43, interp=0, ctf=True),
+]
+
+
+@pytest.mark.parametrize("case", SHIFT_CASES, ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+def test_in_plane_shift_parity(b, case):
+    """Forward, adjoint (fast and deterministic) and gradient with in-plane
+    shifts T_i against the oracle; the Hessian ignores them."""
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    shifts = np.random.default_rng(case["seed"]).uniform(-0.3 * case["M"], 0.3 * case["M"], (P.n, 2))
+    Ps = oracle.Poses(P.rot, P.defocus, shifts.astype(np.float32))
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x, sh = to_dev(P.rot, P.defocus, vol, img, Ps.shift)
+    want = oracle.project(grid_o, opt_o, Ps, vol)
+    assert rel(b.project(g, o, rot, df, v, shift=sh).cpu().numpy(), want) <= 1e-5
+    want_b = oracle.backproject(grid_o, opt_o, Ps, img, ctf_power=1, scale=1.3)
+    for det in (False, True):
+        acc = b.backproject(g, o, rot, df, x, ctf_power=1, scale=1.3, deterministic=det, shift=sh)
+        assert rel(acc.cpu().numpy(), want_b) <= 1e-4, det
+    img_d = img * _disk(grid_o)[None]
+    want_g = oracle.gradient(grid_o, opt_o, Ps, vol, img_d, 2.0, 0.1)
+    want_f = oracle.loss(grid_o, opt_o, Ps, vol, img_d, 2.0, 0.1)
+    for det in (False, True):
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gr = b.gradient(g, o, rot, df, v, x, 2.0, 0.1, loss_out=loss, deterministic=det, shift=sh)
+        assert rel(gr.cpu().numpy(), want_g) <= 1e-4, det
+        assert loss.item() == pytest.approx(want_f, rel=1e-5), det
+    # without shifts the results differ (the shift is applied at all)
+    assert rel(b.project(g, o, rot, df, v).cpu().numpy(), want) > 1e-2

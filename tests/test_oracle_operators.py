@@ -228,3 +228,67 @@ def test_discrete_slice_identity_of_volume_pipeline():
     an = analytic_blob_ft(blobs, grid_k(M2), M2)
     vol2 = synth.centred_fftn(synth.blob_density(M2, blobs))
     assert np.linalg.norm(an - vol2) / np.linalg.norm(an) < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# In-plane shifts T_i (Definition "Projection operator", Sec. 2.1)
+# ---------------------------------------------------------------------------
+def test_shift_is_the_discrete_shift_theorem(orc):
+    """An integer shift (sx, sy) multiplies the centred 2D transform so that
+    the real-space image is translated by (sx, sy) pixels (np.roll), i.e.
+    T_jj = exp(-2 pi i (kx sx + ky sy) / M)."""
+    M, n = 16, 3
+    grid = orc.Grid(M)
+    rot = synth.uniform_rotations(n, seed=21)
+    df = synth.defocus_values(n, 1.0, 3.0, seed=21)
+    shifts = np.array([[2, -3], [-5, 1], [0, 4]], np.float32)
+    vol = synth.random_complex((M, M, M), seed=22).astype(np.complex128)
+    y0 = orc.project(grid, orc.Optics(), orc.Poses(rot, df), vol)
+    y1 = orc.project(grid, orc.Optics(), orc.Poses(rot, df, shifts), vol)
+    for i in range(n):
+        real0 = np.fft.ifft2(np.fft.ifftshift(y0[i]))
+        real1 = np.fft.ifft2(np.fft.ifftshift(y1[i]))
+        sx, sy = int(shifts[i, 0]), int(shifts[i, 1])
+        assert np.allclose(real1, np.roll(real0, (sy, sx), axis=(0, 1)), atol=1e-12 * np.abs(real0).max())
+
+
+def test_fourier_slice_exact_with_shift(orc):
+    """Cube-group rotations and fractional shifts: the slice of the analytic
+    blob transform with the projected centres moved by the shift."""
+    M = 16
+    blobs = synth.blob_params(M, 4, seed=12, sigma_range=(1.0, 2.0), centre_halfwidth=M / 8)
+    vol = analytic_blob_ft(blobs, grid_k(M), M)
+    rots = synth.cube_group()
+    shifts = np.random.default_rng(4).uniform(-3, 3, (len(rots), 2)).astype(np.float32)
+    grid = orc.Grid(M)
+    out = orc.project(grid, orc.NO_CTF, orc.Poses(rots, np.zeros(len(rots), np.float32), shifts), vol)
+    mask, kx, ky = disk(M, grid.rmax)
+    k2 = kx ** 2 + ky ** 2
+    for i, R in enumerate(rots.astype(np.float64)):
+        t = shifts[i].astype(np.float64)
+        exp2d = np.zeros((M, M), dtype=np.complex128)
+        for c, s, a in zip(blobs.centres, blobs.sigmas, blobs.amps):
+            rc = R @ c
+            exp2d += a * (2 * np.pi * s * s) ** 1.5 * np.exp(-2 * np.pi ** 2 * s * s * k2 / M ** 2) \
+                * np.exp(-2j * np.pi * (kx * (rc[0] + t[0]) + ky * (rc[1] + t[1])) / M)
+        err = np.linalg.norm(out[i][mask] - exp2d[mask]) / np.linalg.norm(exp2d[mask])
+        assert err < 1e-12, (i, err)
+
+
+@pytest.mark.parametrize("interp", [0, 1])
+def test_adjoint_identity_with_shift_and_hessian_unchanged(orc, interp):
+    M, n = 16, 5
+    grid = orc.Grid(M, interp=interp)
+    opt = orc.Optics()
+    rot, df = synth.uniform_rotations(n, seed=31), synth.defocus_values(n, 1.0, 3.0, seed=31)
+    shifts = np.random.default_rng(6).uniform(-6, 6, (n, 2)).astype(np.float32)
+    P = orc.Poses(rot, df, shifts)
+    x = synth.random_complex((M, M, M), seed=32).astype(np.complex128)
+    y = synth.random_complex((n, M, M), seed=33).astype(np.complex128)
+    lhs = np.vdot(orc.project(grid, opt, P, x), y)
+    rhs = np.vdot(x, orc.backproject(grid, opt, P, y, ctf_power=1))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * n
+    # T is unitary and diagonal: P^T T^* C^2 T P = P^T C^2 P (eq. (hessian))
+    h_shift = orc.hvp(grid, opt, P, x, 1.0, 0.0)
+    h_none = orc.hvp(grid, opt, orc.Poses(rot, df), x, 1.0, 0.0)
+    assert np.linalg.norm(h_shift - h_none) <= 1e-12 * np.linalg.norm(h_none)
