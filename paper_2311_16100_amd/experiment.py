@@ -296,7 +296,8 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
 
 def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinson", "learned", "exact"),
                  target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print,
-                 feature_images: int = 8192, judge_images: int = 4096, cg_tol: float = 1e-6, **kw):
+                 feature_images: int = 8192, judge_images: int = 4096, cg_tol: float = 1e-6, cg_max_iter: int = 500,
+                 **kw):
     """Time to `target` for each arm on the same data set and ground truth.
     Setup time is charged to the arm that needs it: the exact arm one
     squared-weight pass over the data; the learned arm the feature pass (over
@@ -304,7 +305,8 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
     probe over `judge_images` images); if the judge rejects the prediction the
     arm continues as the Hutchinson arm."""
     from . import learned as L
-    v_star, cg_it, cg_res = ground_truth(ds, tol=cg_tol, log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
+    v_star, cg_it, cg_res = ground_truth(ds, tol=cg_tol, max_iter=cg_max_iter,
+                                         log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
     out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
     for arm in arms:
         D = None

@@ -30,7 +30,7 @@ EVAL_SPECS = {
     # viewing directions, kappa 10), 500,000 images regenerated per batch
     # (410 GB would not fit in device memory), deterministic adjoint
     "stress_320": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
-                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-9, max_epochs=8,
+                       poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-9, cg_max_iter=150, max_epochs=8,
                        time_limit=150.0),
 }
 
@@ -75,7 +75,7 @@ def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: in
             r = E.compare_arms(ds, batch, params=params, stop_on=stop, max_epochs=spec.get("max_epochs", max_epochs),
                                time_limit=spec.get("time_limit", time_limit), eval_every=10 if ds.M <= 128 else 5,
                                log=log, deterministic=spec.get("deterministic", False),
-                               cg_tol=spec.get("cg_tol", 1e-6))
+                               cg_tol=spec.get("cg_tol", 1e-6), cg_max_iter=spec.get("cg_max_iter", 500))
             res[stop] = {arm: {"reached": a.reached, "iterations": a.iterations, "run_s": round(a.seconds, 4),
                                "setup_s": round(a.setup_seconds, 4), "total_s": round(a.total_seconds, 4),
                                "gen_s": round(a.gen_seconds, 4), "note": a.note,
