@@ -81,7 +81,7 @@ struct BrickArgs {
     const int *lists;   // [nb][stride]
     int stride;
     int nbx, nb;
-    const int *items;   // work items, heaviest first: brick | chunk << 20
+    const int2 *items;  // work items, heaviest first: (brick | chunk << 20, images of the brick)
     const int *n_items; // number of work items
     int *next_item;     // work counter (zero at launch)
 };
@@ -172,7 +172,7 @@ constexpr int kPlanWaves = kPlanThreads / 64;
 constexpr int kMaxChunk = 128;
 static_assert(CHUNK_ADJ <= kMaxChunk && CHUNK_FWD <= kMaxChunk, "plan histogram too small");
 
-__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int *items,
+__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int2 *items,
                                                                    int *n_items, int *next_item) {
     __shared__ int hist[kPlanWaves][kMaxChunk + 1];
     __shared__ int base[kMaxChunk + 1];
@@ -219,9 +219,9 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
         const int c = counts[b], full = c / chunk, rem = c - full * chunk;
         if (full) {
             const int p = atomicAdd(&hist[wv][chunk], full);
-            for (int k = 0; k < full; ++k) items[p + k] = b | (k << 20);
+            for (int k = 0; k < full; ++k) items[p + k] = make_int2(b | (k << 20), c);
         }
-        if (rem) items[atomicAdd(&hist[wv][rem], 1)] = b | (full << 20);
+        if (rem) items[atomicAdd(&hist[wv][rem], 1)] = make_int2(b | (full << 20), c);
     }
 }
 
@@ -297,13 +297,15 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // waves per SIMD the register allocation must allow: three blocks per CU
 // where the LDS footprint permits it (project, backproject, features,
 // squared weights), two for gradient and HVP
-template <int MODE>
+template <int MODE, bool SHIFT>
 __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool OWNER_ONLY = MODE == kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
-    constexpr bool SHIFTED = READS_IMG;  // modes that apply the in-plane shift
+    // the in-plane shift is compiled in only where a launch carries shifts
+    constexpr bool SHIFTED = SHIFT && READS_IMG;
+    constexpr int IMGDAT = SHIFTED ? 10 : 8;
     constexpr int CHUNK = OWNER_ONLY ? CHUNK_FWD : CHUNK_ADJ;
     __shared__ float2 vh[GATHER ? BH * VP : 1];
     __shared__ double acc_re[SCATTER ? BS * AP : 1];
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
     __shared__ ImgSlot slot[WI];
     // the item's images: index (as int bits), rows 0 and 1 of R, defocus,
     // in-plane shift
-    __shared__ float imgdat[CHUNK][10];
+    __shared__ float imgdat[CHUNK][IMGDAT];
     // row record: x = first run | len << 16 | image slot << 24,
     //             y = (kx0 + 32768) | (ky + 32768) << 16
     __shared__ int2 seg[ROWCAP];
@@ -339,10 +341,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
         // uniform values read from LDS are moved to scalar registers
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= total) break;
-        const int code = a.items[item];
+        const int2 rec = a.items[item];
+        const int code = rec.x;
         const int brick = code & 0xFFFFF;
         const int first = (code >> 20) * CHUNK;
-        const int count = a.counts[brick];
+        const int count = rec.y;
         const int n_img = min(CHUNK, count - first);
         const bool single = count <= CHUNK;
         int o[3];
@@ -381,11 +384,13 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
 #pragma unroll
             for (int d = 0; d < 6; ++d) e[d] = a.rot[(int64_t)my_ii * 9 + d];
             e[6] = a.defocus[my_ii];
-            e[7] = a.shift ? a.shift[2 * my_ii] : 0.f;
-            e[8] = a.shift ? a.shift[2 * my_ii + 1] : 0.f;
+            if (SHIFTED) {
+                e[7] = a.shift[2 * my_ii];
+                e[8] = a.shift[2 * my_ii + 1];
+            }
             imgdat[threadIdx.x][0] = __int_as_float(my_ii);
 #pragma unroll
-            for (int d = 0; d < 9; ++d) imgdat[threadIdx.x][1 + d] = e[d];
+            for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         }
         if (SCATTER) {
             for (int t = threadIdx.x; t < BS * AP; t += kBT) {
@@ -428,8 +433,10 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                     }
                     S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
                     S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
-                    S.sx = D[8];
-                    S.sy = D[9];
+                    if (SHIFTED) {
+                        S.sx = D[IMGDAT - 2];
+                        S.sy = D[IMGDAT - 1];
+                    }
                     // rows: range of e2 . (g - half) over the box
                     float ylo = 0.f, yhi = 0.f;
 #pragma unroll
@@ -462,6 +469,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                 }
                 if (t == WI - 1) rows_total = x;
             }
+
             __syncthreads();
             const int n_rows = __builtin_amdgcn_readfirstlane(rows_total);
             // ---- row intervals (kx range whose cells reach the box), runs per row
@@ -604,7 +612,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                 // in-plane shift: T on the forward value, conj(T)
                                 // on the adjoint input
                                 float2 T = make_float2(1.f, 0.f);
-                                if (SHIFTED && a.shift) {
+                                if (SHIFTED) {
                                     const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
                                                       (double)M;
                                     const float fr = (float)(tt - rint(tt));
@@ -778,7 +786,7 @@ static size_t brick_items_cap(int M, int64_t sub) {
 size_t brick_workspace_bytes(int M, int64_t n) {
     const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
     const size_t nb = (size_t)brick_count(M);
-    return align256(nb * 4) + align256(nb * (size_t)(sub > 0 ? sub : 1) * 4) + align256(brick_items_cap(M, sub) * 4) +
+    return align256(nb * 4) + align256(nb * (size_t)(sub > 0 ? sub : 1) * 4) + align256(brick_items_cap(M, sub) * 8) +
            256;
 }
 
@@ -789,7 +797,7 @@ static int resident_blocks() {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, brick_kernel<MODE>, kBT, 0) != hipSuccess || per <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, brick_kernel<MODE, false>, kBT, 0) != hipSuccess || per <= 0)
         per = 1;
     return cus * per;
 }
@@ -807,8 +815,8 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     w += align256((size_t)nb * 4);
     int *lists = (int *)w;
     w += align256((size_t)nb * (size_t)sub * 4);
-    int *items = (int *)w;
-    w += align256(brick_items_cap(M, sub) * 4);
+    int2 *items = (int2 *)w;
+    w += align256(brick_items_cap(M, sub) * 8);
     int *scalars = (int *)w;  // [0] number of work items, [1] work counter
     const int64_t img_stride = (int64_t)M * M;
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
@@ -848,7 +856,10 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.n_items = scalars;
         a.next_item = scalars + 1;
         hipEvent_t t0 = timing_begin(MODE, st);
-        hipLaunchKernelGGL((brick_kernel<MODE>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+        if (shift)
+            hipLaunchKernelGGL((brick_kernel<MODE, true>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+        else
+            hipLaunchKernelGGL((brick_kernel<MODE, false>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         e = hipGetLastError();
         timing_end(MODE, t0, st);
         if (e != hipSuccess) return e;
