@@ -50,6 +50,20 @@ def train_network(specs=TRAIN_SPECS, steps: int = 2000, n_probe: int = 200, log=
     return params, hist
 
 
+MILESTONES = (0.1, 0.05, 0.02, 0.01)
+
+
+def milestones(errors, col):
+    """First (iteration, seconds) at which the error in column `col` of the
+    recorded (iteration, seconds, ball error, high-band error) rows is at or
+    below each milestone (None: not reached)."""
+    out = {}
+    for m in MILESTONES:
+        hit = next(((it, round(t, 4)) for it, t, *e in errors if e[col - 2] <= m), None)
+        out[str(m)] = hit
+    return out
+
+
 def fsc_summary(curve):
     """Lowest shell correlation over shells 1 .. M/2 - 1 and the first shell
     where it drops below 0.9 and 0.75 (None: never)."""
@@ -81,7 +95,8 @@ def evaluate(params, configs=("mid_128", "hires_256"), log=print, max_epochs: in
                                "gen_s": round(a.gen_seconds, 4), "note": a.note,
                                "final_error": {"ball": round(a.errors[-1][2], 6), "high": round(a.errors[-1][3], 6)}
                                if a.errors else None,
-                               "fsc_final": fsc_summary(a.fsc[-1][1]) if a.fsc else None}
+                               "fsc_final": fsc_summary(a.fsc[-1][1]) if a.fsc else None,
+                               "milestones_ball": milestones(a.errors, 2), "milestones_high": milestones(a.errors, 3)}
                          for arm, a in r["arms"].items()}
             res["cg_iterations"] = r["cg_iterations"]
             res["cg_residual"] = r["cg_residual"]
