@@ -307,6 +307,14 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
     from . import learned as L
     v_star, cg_it, cg_res = ground_truth(ds, tol=cg_tol, max_iter=cg_max_iter,
                                          log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
+    # one untimed pass through every setup kernel on a few images, so that no
+    # arm is charged for first-launch costs
+    few = min(ds.N, 64)
+    B.exact_diag(ds.grid, ds.optics, ds.rot[:few].contiguous(), ds.defocus[:few].contiguous(), 1.0, 0.0)
+    if params is not None:
+        c2, cv = L.features(ds, n_images=few)
+        L.judge(ds, L.predict(ds, params, c2, cv), n_images=few)
+    torch.cuda.synchronize()
     out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
     for arm in arms:
         D = None
