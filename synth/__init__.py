@@ -1,5 +1,5 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests, the
-benchmark and the SGD driver.
+benchmark and the SGD runs.
 
 This module holds none of the method's arithmetic: no projection, no CTF, no
 adjoint, no Hessian.  It only draws the inputs the method is applied to
