@@ -6,15 +6,16 @@
 // the forward mode, 128 for the adjoint modes), ordered by size, largest
 // first.  One wave of resident blocks takes the items from that list with an
 // atomic counter.  For each item the block
-//   - stages the brick plus a one-voxel halo of the gathered volume in LDS
-//     (14^3 complex values), so every trilinear gather is 8 LDS reads;
-//   - accumulates the adjoint into an LDS copy of the brick with double-
-//     precision LDS atomics, and writes it to HBM once per voxel at the end (a
-//     plain read-modify-write when the brick has a single work item, global
-//     atomics only for the central bricks that more than 128 images cross).
-//     On gfx950 the LDS double atomic add sustains about 20x the lane rate of
-//     the single-precision one, so the wider accumulator is also the faster
-//     one.
+//   - stages the brick and the voxels one step above it on each axis (13^3
+//     complex values of the gathered volume) in LDS, so every trilinear
+//     gather is 8 LDS reads;
+//   - accumulates the adjoint into an LDS array of the same extent with
+//     double-precision LDS atomics, and adds it to HBM once per voxel at the
+//     end with global atomics (the upper faces of the extent belong to the
+//     neighbouring bricks, which other blocks may be flushing at the same
+//     time).  On gfx950 the LDS double atomic add sustains about 20x the lane
+//     rate of the single-precision one, so the wider accumulator is also the
+//     faster one.
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
@@ -25,11 +26,11 @@
 // and writes).  Within a run the sample point advances in exact fixed-point
 // arithmetic (see ImgSlot), so every brick sees identical cells.
 //
-// A pixel is "touching" a brick when one of its eight cell corners lies in
-// the brick, and "owned" by the brick that contains its base corner
-// floor(g).  The adjoint adds, for every touching pixel, the corners inside
-// the brick -- so each (pixel, corner) contribution is added exactly once over
-// all bricks; forward outputs and loss terms are produced by the owner only.
+// A pixel is handled by exactly one brick: the one that contains its base
+// corner floor(g).  Its eight corners lie in that brick's extended extent
+// (the brick plus one voxel above on each axis), so the gather, the forward
+// value, the loss term and all eight adjoint contributions of the pixel are
+// computed once, with no per-corner bounds tests.
 //
 // Modes:
 //   kBProject      out = C P v (- x) for owned pixels; loss
@@ -49,13 +50,12 @@ namespace csg {
 #define CSG_BRICK_SIDE 12
 #endif
 constexpr int BS = CSG_BRICK_SIDE;  // brick side
-constexpr int BH = BS + 2;       // staged side: one halo voxel below and above
+constexpr int BX = BS + 1;       // extended side: the brick and one voxel above
 // LDS strides are odd (in elements) so that lanes stepping along any axis of
 // the brick fall into different banks.
-constexpr int AR = BS + 1;       // accumulator row stride
-constexpr int AP = AR * AR;      // accumulator plane stride (289)
-constexpr int VR = BH + 1;       // staged-volume row stride (19)
-constexpr int VP = VR * VR;      // staged-volume plane stride (361)
+constexpr int XR = BX | 1;       // row stride of the staged volume and the accumulator (13)
+constexpr int XP = XR * XR;      // plane stride (169)
+constexpr int XN = BX * XP;      // elements of one staged array
 constexpr int kBT = 512;         // threads per brick block (8 waves)
 constexpr int CHUNK_ADJ = 128;   // images per work item of the adjoint modes
 constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
@@ -93,8 +93,9 @@ __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
 }
 
 // ---------------------------------------------------------------------------
-// Cull: lists[b] = images whose plane meets the box of cells touching brick b
-// (grid coordinates [b0 - 1, b0 + BS]^3), in increasing image order.
+// Cull: lists[b] = images whose plane meets the box of sample points whose
+// base corner lies in brick b (grid coordinates [b0, b0 + BS]^3), in
+// increasing image order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float *rot, int64_t n, int nbx,
                                                              int *counts, int *lists, int stride) {
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float 
     float dist2 = 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const float lo = (float)(o[d] - 1 - g.half), hi = (float)(o[d] + BS - g.half);
+        const float lo = (float)(o[d] - g.half), hi = (float)(o[d] + BS - g.half);
         c[d] = 0.5f * (lo + hi);
         hw[d] = 0.5f * (hi - lo);
         const float near = fmaxf(fmaxf(lo, -hi), 0.f);  // distance of the box to the origin along d
@@ -268,10 +269,10 @@ struct ImgSlot {
     float sx, sy;      // in-plane shift (pixels)
 };
 
-// rows of one image that reach a brick's enumeration box (side BS + 1):
-// at most the box diagonal plus the clipping margins
-constexpr int MAXROWS = (int)((BS + 1) * 1.7321f) + 2;
-constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument)
+// rows of one image that reach a brick's box (side BS): the box's extent
+// along e2 is at most BS sqrt(3), plus the clipping margins
+constexpr int MAXROWS = (int)(BS * 1.7321f) + 2;
+constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument along e1)
 
 // Window sizes per mode: images per window (a whole forward chunk, whose
 // LDS footprint leaves room; 32 images for the adjoint modes) and runs per
@@ -301,15 +302,14 @@ template <int MODE, bool SHIFT>
 __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
-    constexpr bool OWNER_ONLY = MODE == kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
     // the in-plane shift is compiled in only where a launch carries shifts
     constexpr bool SHIFTED = SHIFT && READS_IMG;
     constexpr int IMGDAT = SHIFTED ? 10 : 8;
-    constexpr int CHUNK = OWNER_ONLY ? CHUNK_FWD : CHUNK_ADJ;
-    __shared__ float2 vh[GATHER ? BH * VP : 1];
-    __shared__ double acc_re[SCATTER ? BS * AP : 1];
-    __shared__ double acc_im[SCATTER ? BS * AP : 1];
+    constexpr int CHUNK = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
+    __shared__ float2 vh[GATHER ? XN : 1];
+    __shared__ double acc_re[SCATTER ? XN : 1];
+    __shared__ double acc_im[SCATTER ? XN : 1];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -347,7 +347,6 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
         const int first = (code >> 20) * CHUNK;
         const int count = rec.y;
         const int n_img = min(CHUNK, count - first);
-        const bool single = count <= CHUNK;
         int o[3];
         brick_origin(brick, a.nbx, o);
 
@@ -359,24 +358,24 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
         int my_ii = 0;
         if (holds_img) my_ii = list[threadIdx.x];
         if (GATHER) {
-            // every load of the halo is issued before the first LDS store
-            constexpr int HALO = BH * BH * BH;
+            // the extended brick of the gathered volume; every load is issued
+            // before the first LDS store
+            constexpr int HALO = BX * BX * BX;
             constexpr int HPT = (HALO + kBT - 1) / kBT;
             float2 hv[HPT];
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
                 const int t = threadIdx.x + k * kBT;
-                const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
-                const int qx = o[0] - 1 + hx, qy = o[1] - 1 + hy, qz = o[2] - 1 + hz;
+                const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
+                const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
                 hv[k] = make_float2(0.f, 0.f);
-                if (t < HALO && in_grid(qx, M) && in_grid(qy, M) && in_grid(qz, M))
-                    hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
+                if (t < HALO && qx < M && qy < M && qz < M) hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
             }
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
                 const int t = threadIdx.x + k * kBT;
-                const int hx = t % BH, hy = (t / BH) % BH, hz = t / (BH * BH);
-                if (t < HALO) vh[(hz * VR + hy) * VR + hx] = hv[k];
+                const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
+                if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
             }
         }
         if (holds_img) {
@@ -393,17 +392,17 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
             for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         }
         if (SCATTER) {
-            for (int t = threadIdx.x; t < BS * AP; t += kBT) {
+            for (int t = threadIdx.x; t < XN; t += kBT) {
                 acc_re[t] = 0.0;
                 acc_im[t] = 0.0;
             }
         }
-        // enumeration box (grid coordinates): owned pixels have floor(g) in the
-        // brick, touching pixels have floor(g) in [b0 - 1, b0 + BS - 1]
+        // enumeration box (grid coordinates): the brick's pixels have floor(g)
+        // in the brick
         float lo[3], hi[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            lo[d] = (float)(OWNER_ONLY ? o[d] : o[d] - 1);
+            lo[d] = (float)o[d];
             hi[d] = (float)(o[d] + BS);
         }
         const float halff = (float)g.half;
@@ -579,10 +578,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                             }
                             const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
                                                (unsigned)l[2] < (unsigned)BS;
-                            const bool inside = (unsigned)(l[0] + 1) < (unsigned)(BS + 1) &&
-                                                (unsigned)(l[1] + 1) < (unsigned)(BS + 1) &&
-                                                (unsigned)(l[2] + 1) < (unsigned)(BS + 1);
-                            if (OWNER_ONLY ? owned : inside) {
+                            if (owned) {
                                 const int kx = kxs + jj;
                                 float C = 1.0f;
                                 if (g.ctf_on) {
@@ -595,16 +591,17 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                 const float wy[2] = {1.0f - t[1], t[1]};
                                 const float wz[2] = {1.0f - t[2], t[2]};
                                 float2 acc = make_float2(0.f, 0.f);
+                                // index of the base corner in the extended brick; the
+                                // eight corners lie in it
+                                const int lb = (l[2] * XR + l[1]) * XR + l[0];
                                 if (GATHER) {
-                                    // halo index of the base corner: l + 1 in [0, BS];
-                                    // halo voxels outside the grid hold zeros, which
+                                    // staged voxels outside the grid hold zeros, which
                                     // drops those corners
-                                    const int hb = ((l[2] + 1) * VR + (l[1] + 1)) * VR + (l[0] + 1);
 #pragma unroll
                                     for (int c = 0; c < 8; ++c) {
                                         const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                                         const float w = wx[ax] * wy[ay] * wz[az];
-                                        const float2 v = vh[hb + az * VP + ay * VR + ax];
+                                        const float2 v = vh[lb + az * XP + ay * XR + ax];
                                         acc.x = fmaf(w, v.x, acc.x);
                                         acc.y = fmaf(w, v.y, acc.y);
                                     }
@@ -635,7 +632,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                 } else if (MODE == kBGradient) {
                                     const float2 x = xin[jj];
                                     const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
-                                    if (owned) lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                                    lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
                                     const float fct = a.scale * C;
                                     const float2 rt = cmul_conj(rr, T);
                                     val = make_float2(fct * rt.x, fct * rt.y);
@@ -648,24 +645,18 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                                     val = make_float2(a.scale * C * C, 0.0f);
                                 }
                                 if (SCATTER) {
-                                    // corners inside the brick; a corner beyond the
-                                    // grid edge lands in an LDS slot that is never
-                                    // written back
-                                    const int lb = l[2] * AP + l[1] * AR + l[0];
+                                    // all eight corners; a corner beyond the grid edge
+                                    // lands in a slot that is never written back
 #pragma unroll
                                     for (int c = 0; c < 8; ++c) {
                                         const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                        const int lx = l[0] + ax, ly = l[1] + ay, lz = l[2] + az;
-                                        if ((unsigned)lx < (unsigned)BS && (unsigned)ly < (unsigned)BS &&
-                                            (unsigned)lz < (unsigned)BS) {
-                                            const float w = wx[ax] * wy[ay] * wz[az];
-                                            const int li = lb + az * AP + ay * AR + ax;
-                                            if (MODE == kBSqDiag) {
-                                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                                            } else {
-                                                atomicAdd(&acc_re[li], (double)(w * val.x));
-                                                atomicAdd(&acc_im[li], (double)(w * val.y));
-                                            }
+                                        const float w = wx[ax] * wy[ay] * wz[az];
+                                        const int li = lb + az * XP + ay * XR + ax;
+                                        if (MODE == kBSqDiag) {
+                                            atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                                        } else {
+                                            atomicAdd(&acc_re[li], (double)(w * val.x));
+                                            atomicAdd(&acc_im[li], (double)(w * val.y));
                                         }
                                     }
                                 }
@@ -681,55 +672,24 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
 
         if (SCATTER) {
             __syncthreads();
-            // flush: voxels of a brick with a single work item are updated
-            // with plain loads and stores (all loads of a thread first), the
-            // others with global atomics
-            constexpr int NV = BS * BS * BS;
-            constexpr int FPT = (NV + kBT - 1) / kBT;
-#define CSG_FLUSH_INDEX(k)                                                                  \
-    const int t = threadIdx.x + (k) * kBT;                                                  \
-    const int tx = t % BS, ty = (t / BS) % BS, tz = t / (BS * BS);                          \
-    const bool ok = t < NV && o[0] + tx < M && o[1] + ty < M && o[2] + tz < M;              \
-    const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);          \
-    const int li = tz * AP + ty * AR + tx;
-            if (MODE == kBSqDiag) {
-                float old[FPT];
-#pragma unroll
-                for (int k = 0; k < FPT; ++k) {
-                    CSG_FLUSH_INDEX(k)
-                    (void)li;
-                    old[k] = (single && ok) ? a.accum_real[gi] : 0.f;
-                }
-#pragma unroll
-                for (int k = 0; k < FPT; ++k) {
-                    CSG_FLUSH_INDEX(k)
-                    if (!ok) continue;
-                    const float re = (float)acc_re[li];
-                    if (single) a.accum_real[gi] = old[k] + re;
-                    else if (re != 0.f) atomicAdd(a.accum_real + gi, re);
-                }
-            } else {
-                float2 old[FPT];
-#pragma unroll
-                for (int k = 0; k < FPT; ++k) {
-                    CSG_FLUSH_INDEX(k)
-                    (void)li;
-                    old[k] = (single && ok) ? a.accum[gi] : make_float2(0.f, 0.f);
-                }
-#pragma unroll
-                for (int k = 0; k < FPT; ++k) {
-                    CSG_FLUSH_INDEX(k)
-                    if (!ok) continue;
-                    const float re = (float)acc_re[li], im = (float)acc_im[li];
-                    if (single) {
-                        a.accum[gi] = make_float2(old[k].x + re, old[k].y + im);
-                    } else if (re != 0.f || im != 0.f) {
-                        atomicAdd(&a.accum[gi].x, re);
-                        atomicAdd(&a.accum[gi].y, im);
-                    }
+            // flush: every voxel of the extended brick that lies in the grid is
+            // added with global atomics (voxels that received nothing are
+            // skipped)
+            constexpr int NV = BX * BX * BX;
+            for (int t = threadIdx.x; t < NV; t += kBT) {
+                const int tx = t % BX, ty = (t / BX) % BX, tz = t / (BX * BX);
+                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
+                const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
+                const int li = (tz * XR + ty) * XR + tx;
+                const float re = (float)acc_re[li];
+                if (MODE == kBSqDiag) {
+                    if (re != 0.f) atomicAdd(a.accum_real + gi, re);
+                } else {
+                    const float im = (float)acc_im[li];
+                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
+                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
                 }
             }
-#undef CSG_FLUSH_INDEX
         }
     }  // work items
 
