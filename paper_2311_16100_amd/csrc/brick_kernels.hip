@@ -57,8 +57,34 @@ constexpr int XR = BX | 1;       // row stride of the staged volume and the accu
 constexpr int XP = XR * XR;      // plane stride (169)
 constexpr int XN = BX * XP;      // elements of one staged array
 constexpr int kBT = 512;         // threads per brick block (8 waves)
-constexpr int CHUNK_ADJ = 128;   // images per work item of the adjoint modes
-constexpr int CHUNK_FWD = 64;    // images per work item of the forward mode (no flush)
+// Tuning constants (measured at 256^3 with 1024 images); each may be set at
+// compile time.
+#ifndef CSG_CHUNK_ADJ
+#define CSG_CHUNK_ADJ 128
+#endif
+#ifndef CSG_CHUNK_FWD
+#define CSG_CHUNK_FWD 64
+#endif
+#ifndef CSG_RUN_ADJ
+#define CSG_RUN_ADJ 2
+#endif
+#ifndef CSG_WI_ADJ
+#define CSG_WI_ADJ 32
+#endif
+#ifndef CSG_WI_GH
+#define CSG_WI_GH 64
+#endif
+#ifndef CSG_RUN_FWD
+#define CSG_RUN_FWD 1
+#endif
+#ifndef CSG_WI_FWD
+#define CSG_WI_FWD 64
+#endif
+#ifndef CSG_BRICK_WAVES_GH
+#define CSG_BRICK_WAVES_GH 4
+#endif
+constexpr int CHUNK_ADJ = CSG_CHUNK_ADJ;  // images per work item of the adjoint modes
+constexpr int CHUNK_FWD = CSG_CHUNK_FWD;  // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
 enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5 };
@@ -274,15 +300,16 @@ struct ImgSlot {
 constexpr int MAXROWS = (int)(BS * 1.7321f) + 2;
 constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument along e1)
 
-// Window sizes per mode: images per window (a whole forward chunk, whose
-// LDS footprint leaves room; 32 images for the adjoint modes) and runs per
-// pass of the run -> row table.
+// Window sizes per mode: images per window (a whole forward chunk; 64 for
+// gradient and HVP, whose LDS footprint allows two blocks per CU either way;
+// 32 for the other adjoint modes, which keeps them at three blocks per CU)
+// and runs per pass of the run -> row table.
 template <int MODE>
 struct Win {
     // consecutive pixels of a row per lane: one for the forward mode, two
     // for the adjoint modes (measured fastest)
-    static constexpr int RUN = MODE == kBProject ? 1 : 2;
-    static constexpr int WI = MODE == kBProject ? 64 : 32;
+    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : CSG_RUN_ADJ;
+    static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || MODE == kBHvp) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
     static constexpr int RUNCAP = MODE == kBProject ? 3072 : 2048;
@@ -299,7 +326,7 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // where the LDS footprint permits it (project, backproject, features,
 // squared weights), two for gradient and HVP
 template <int MODE, bool SHIFT>
-__global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
+__global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
@@ -455,7 +482,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? 4 : CS
                         S.ky_lo = 0;
                     }
                 }
-                // inclusive scan of the row counts over the 32 lanes
+                // inclusive scan of the row counts over the window's lanes
                 int x = nrows;
 #pragma unroll
                 for (int off = 1; off < WI; off <<= 1) {
