@@ -80,6 +80,9 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #ifndef CSG_WI_FWD
 #define CSG_WI_FWD 64
 #endif
+#ifndef CSG_RUNCAP_GH
+#define CSG_RUNCAP_GH 2048
+#endif
 #ifndef CSG_BRICK_WAVES_GH
 #define CSG_BRICK_WAVES_GH 4
 #endif
@@ -291,7 +294,7 @@ struct ImgSlot {
     double ctfA;       // (lambda df / 2) / (M pixel)^2: chi / 2pi = k2 (ctfA - ctfB k2)
     uint32_t img_base; // index of pixel (0, 0) of the image: i M^2
     short ky_lo;       // first row that can reach the box
-    unsigned short row0; // index of that row's record in the window
+    unsigned short nrows; // rows that can reach the box (at most MAXROWS)
     float sx, sy;      // in-plane shift (pixels)
 };
 
@@ -312,7 +315,7 @@ struct Win {
     static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || MODE == kBHvp) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
-    static constexpr int RUNCAP = MODE == kBProject ? 3072 : 2048;
+    static constexpr int RUNCAP = MODE == kBProject ? 3072 : (MODE == kBGradient || MODE == kBHvp) ? CSG_RUNCAP_GH : 2048;
 };
 
 __device__ __forceinline__ double rint_scaled(float e) {
@@ -346,10 +349,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
     // row record: x = first run | len << 16 | image slot << 24,
     //             y = (kx0 + 32768) | (ky + 32768) << 16
     __shared__ int2 seg[ROWCAP];
-    __shared__ unsigned char row2img[ROWCAP];
     __shared__ unsigned short run2row[RUNCAP];
     __shared__ int wave_sums[kBT / 64];
-    __shared__ int rows_total;
     __shared__ int s_item;
     __shared__ double red[16];
 
@@ -392,7 +393,10 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
             float2 hv[HPT];
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
-                const int t = threadIdx.x + k * kBT;
+                int t = threadIdx.x + k * kBT;
+                // in the forward mode (80-register budget) recomputed per item
+                // instead of being kept live across the item loop
+                if (MODE == kBProject) asm volatile("" : "+v"(t));
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
                 hv[k] = make_float2(0.f, 0.f);
@@ -443,12 +447,12 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
             const int nw = min(WI, n_img - w0);
             // every wave has finished with the previous window's tables
             __syncthreads();
-            // ---- the window's images (threads 0..WI-1): constants, first
-            // row, row count
+            // ---- the window's images (one thread each): constants, first row,
+            // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
+            // MAXROWS - 1 of the window; those past its row count stay empty.
             const int t = (int)threadIdx.x;
-            if (t < WI) {
-                int nrows = 0;
-                if (t < nw) {
+            if (t < nw) {
+                {
                     ImgSlot &S = slot[t];
                     const float *D = imgdat[w0 + t];
 #pragma unroll
@@ -477,27 +481,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                     const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
                     if (fl <= fh) {
                         S.ky_lo = (short)(int)fl;
-                        nrows = min((int)fh - (int)fl + 1, MAXROWS);
+                        S.nrows = (unsigned short)min((int)fh - (int)fl + 1, MAXROWS);
                     } else {
                         S.ky_lo = 0;
+                        S.nrows = 0;
                     }
                 }
-                // inclusive scan of the row counts over the window's lanes
-                int x = nrows;
-#pragma unroll
-                for (int off = 1; off < WI; off <<= 1) {
-                    const int y = __shfl_up(x, off, WI);
-                    if (t >= off) x += y;
-                }
-                if (t < nw) {
-                    slot[t].row0 = (unsigned short)(x - nrows);
-                    for (int q = 0; q < nrows; ++q) row2img[x - nrows + q] = (unsigned char)t;
-                }
-                if (t == WI - 1) rows_total = x;
             }
 
             __syncthreads();
-            const int n_rows = __builtin_amdgcn_readfirstlane(rows_total);
+            const int n_rows = nw * MAXROWS;
             // ---- row intervals (kx range whose cells reach the box), runs per row
             int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
             int myruns = 0;
@@ -508,10 +501,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                 rkx0[k] = 0;
                 rky[k] = 0;
                 rsl[k] = 0;
-                if (r < n_rows) {
-                    const int s = row2img[r];
+                const int s = r / MAXROWS;
+                const int q = r - s * MAXROWS;
+                if (r < n_rows && q < (int)slot[s].nrows) {
                     const ImgSlot &S = slot[s];
-                    const int ky = S.ky_lo + (r - S.row0);
+                    const int ky = S.ky_lo + q;
                     const float *D = imgdat[w0 + s];
                     const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
                     int x0, x1;
