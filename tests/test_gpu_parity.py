@@ -7,7 +7,11 @@ gradient, HVP, Hutchinson and the exact diagonal 1e-4; integer outputs
 bitwise reproducible.  Sizes span several pixel chunks and voxel bricks with
 ragged tails (M = 36: 1296 pixels per image = 5 chunks of 256 + 16; 4.5
 bricks of 8 per axis), two image-cull rounds of 256 in the voxel kernels
-(n = 300), and the benchmark's full 256^3 / 1024-image configuration.
+(n = 300), and the benchmark's full 256^3 / 1024-image configuration.  At
+full size the oracle checks sampled images (forward) and 32-image subsets
+(adjoint, gradient); the full batch is checked by the adjoint identity and by
+the fused gradient and HVP against the composition of the forward and adjoint
+kernels.
 """
 import numpy as np
 import pytest
@@ -304,6 +308,47 @@ def test_full_size_backproject_and_adjoint(b, full):
     lhs = torch.vdot(Av.reshape(-1).to(torch.complex128), x.reshape(-1).to(torch.complex128))
     rhs = torch.vdot(v.reshape(-1).to(torch.complex128), acc.reshape(-1).to(torch.complex128))
     assert abs((lhs - rhs).item()) <= 1e-5 * abs(lhs.item())
+
+
+def test_full_size_gradient_matches_composition(b, full):
+    """The fused gradient of the full 1024-image batch (the launch the
+    benchmark times) equals the composition of the separately checked
+    forward and adjoint kernels, lam v + scale P^T C (C P v - x), and its loss
+    the forward pass's residual norm."""
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    x = torch.from_numpy(synth.random_complex((P.n, 256, 256), 7, stream=14)).cuda()
+    scale, lam = 195.3, 0.05
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr = b.gradient(g, o, rot, df, v, x, scale, lam, loss_out=loss)
+    l_res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    r = b.project(g, o, rot, df, v, subtract=x, loss=l_res)
+    want = b.backproject(g, o, rot, df, r, ctf_power=1, scale=scale) + lam * v
+    assert rel(gr.cpu().numpy(), want.cpu().numpy()) <= 1e-5
+    vn2 = torch.vdot(v.reshape(-1).to(torch.complex128), v.reshape(-1).to(torch.complex128)).real
+    assert loss.item() == pytest.approx(scale * l_res.item() + 0.5 * lam * vn2.item(), rel=1e-6)
+
+
+def test_full_size_gradient_subset_vs_oracle(b, full):
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    sub = list(range(32))
+    x = synth.random_complex((32, 256, 256), 8, stream=15)
+    x_d = torch.from_numpy(x).cuda()
+    scale, lam = 6250.0, 0.05
+    gr = b.gradient(g, o, rot[sub].contiguous(), df[sub].contiguous(), v, x_d, scale, lam)
+    want = oracle.gradient(grid_o, oracle.Optics(), P.subset(sub), vol, x * _disk(grid_o)[None], scale, lam)
+    assert rel(gr.cpu().numpy(), want) <= 1e-4
+
+
+def test_full_size_hvp_matches_composition(b, full):
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    z = torch.from_numpy(synth.random_complex((256, 256, 256), 9, stream=16)).cuda()
+    scale, lam = 195.3, 0.05
+    hz = b.hvp(g, o, rot, df, z, scale, lam)
+    want = b.backproject(g, o, rot, df, b.project(g, o, rot, df, z), ctf_power=1, scale=scale) + lam * z
+    assert rel(hz.cpu().numpy(), want.cpu().numpy()) <= 1e-5
 
 
 @pytest.mark.parametrize("M", [16, 34])
