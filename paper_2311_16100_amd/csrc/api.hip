@@ -266,7 +266,7 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
         CSG_TRY(csg::launch_scaled_copy(hz, z, lambda, nv, nullptr, st), "csg_hutchinson_diag");
         if (poses->n > 0)
             CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz,
-                                          (char *)(hz + nv), st),
+                                          (char *)(hz + nv), st, /*probe=*/true),
                     "csg_hutchinson_diag");
         CSG_TRY(csg::launch_zhz_accum(diag_out, z, hz, nv, w, st), "csg_hutchinson_diag");
     }

@@ -37,6 +37,9 @@
 //   kBBackproject  accum += scale C^p img
 //   kBGradient     r = C P v - x; loss (owner); accum += scale C r
 //   kBHvp          accum += scale C^2 P z
+//   kBHvpProbe     the same for a Rademacher probe pair z (Hutchinson): both
+//                  components of a contribution go into one 64-bit integer LDS
+//                  atomic as fixed-point numbers (see PackedScale)
 //   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
 //                  sum of every voxel (no image is read)
 //   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
@@ -90,7 +93,9 @@ constexpr int CHUNK_ADJ = CSG_CHUNK_ADJ;  // images per work item of the adjoint
 constexpr int CHUNK_FWD = CSG_CHUNK_FWD;  // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
-enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5 };
+enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5,
+                 kBHvpProbe = 6 };
+constexpr bool is_hvp(int mode) { return mode == kBHvp || mode == kBHvpProbe; }
 
 struct BrickArgs {
     Geom g;
@@ -312,15 +317,58 @@ struct Win {
     // consecutive pixels of a row per lane: one for the forward mode, two
     // for the adjoint modes (measured fastest)
     static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : CSG_RUN_ADJ;
-    static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || MODE == kBHvp) ? CSG_WI_GH : CSG_WI_ADJ;
+    static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
-    static constexpr int RUNCAP = MODE == kBProject ? 3072 : (MODE == kBGradient || MODE == kBHvp) ? CSG_RUNCAP_GH : 2048;
+    static constexpr int RUNCAP = MODE == kBProject ? 3072 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : 2048;
 };
 
 __device__ __forceinline__ double rint_scaled(float e) {
     return rint((double)fminf(fmaxf(e, -2.0f), 2.0f) * 0x1p32);
 }
+
+// Fixed-point packing of a complex contribution for the 64-bit integer LDS
+// accumulator.  Each component is rounded to an integer multiple of 1/S and the
+// pair is added as re + im 2^32; the 64-bit sum is exact, and since both
+// component sums stay below 2^31 in magnitude they are recovered exactly: re
+// is the low word read as a signed integer, im the rest shifted down.
+//
+// The bound: a contribution is w val with val = scale C^2 (P z)_pixel, so
+// |val| <= |scale| max|z| over the staged brick (|C| <= 1 and the trilinear
+// weights sum to 1).  A voxel receives from one image at most the pixels of
+// the plane lattice inside its 2x2x2 neighbourhood, whose section has diameter
+// at most 2 sqrt(3): at most 16 pixels, each with weight <= 1.  Over an item of
+// at most 128 images a component sum is therefore below
+// 2048 |scale| max|z| = B, and S = 2^e with B S <= 2^30 keeps every sum (and
+// every rounded contribution) below 2^30.  The rounding error is at most
+// 1/(2S) per contribution, i.e. 2^-31 B per contribution (relative 5e-10 of B).
+struct PackedScale {
+    float S = 1.f, invS = 1.f;
+    static __device__ __forceinline__ PackedScale make(int zmax_bits, float scale) {
+        static_assert(CHUNK_ADJ <= 128, "the fixed-point bound assumes at most 128 images per item");
+        PackedScale p;
+        const float B = 2048.f * fabsf(scale) * __int_as_float(zmax_bits);
+        int e = 0;
+        if (B > 0.f && B < 3.0e38f) {
+            int k;
+            (void)frexpf(B, &k);  // B < 2^k
+            e = min(max(30 - k, -126), 100);
+        }
+        p.S = ldexpf(1.f, e);
+        p.invS = ldexpf(1.f, -e);
+        return p;
+    }
+    __device__ __forceinline__ unsigned long long pack(float re, float im) const {
+        const int qr = (int)rintf(re * S), qi = (int)rintf(im * S);
+        return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
+    }
+    __device__ __forceinline__ void unpack(unsigned long long v, float &re, float &im) const {
+        const int lo = (int)(unsigned)v;
+        const long long hi = ((long long)v - (long long)lo) >> 32;
+        re = (float)lo * invS;
+        im = (float)(int)hi * invS;
+    }
+};
 
 #ifndef CSG_BRICK_WAVES
 #define CSG_BRICK_WAVES 6
@@ -329,17 +377,23 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // where the LDS footprint permits it (project, backproject, features,
 // squared weights), two for gradient and HVP
 template <int MODE, bool SHIFT>
-__global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
-    constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || MODE == kBHvp;
+__global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
+    constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || is_hvp(MODE);
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
     // the in-plane shift is compiled in only where a launch carries shifts
     constexpr bool SHIFTED = SHIFT && READS_IMG;
     constexpr int IMGDAT = SHIFTED ? 10 : 8;
     constexpr int CHUNK = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
+    // probe HVP: both components of a contribution go into one 64-bit integer
+    // LDS atomic, as 32-bit fixed-point numbers with a per-item power-of-two
+    // scale (see PackedScale); the other adjoint modes accumulate in double
+    constexpr bool PACKED = MODE == kBHvpProbe;
     __shared__ float2 vh[GATHER ? XN : 1];
-    __shared__ double acc_re[SCATTER ? XN : 1];
-    __shared__ double acc_im[SCATTER ? XN : 1];
+    __shared__ double acc_re[SCATTER && !PACKED ? XN : 1];
+    __shared__ double acc_im[SCATTER && !PACKED ? XN : 1];
+    __shared__ unsigned long long acc_pk[PACKED ? XN : 1];
+    __shared__ float s_wmax[kBT / 64];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -408,6 +462,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
             }
+            if (PACKED) {
+                // bound on |z| over the staged brick (|re| + |im| >= modulus),
+                // per wave; combined after the next barrier
+                float zb = 0.f;
+#pragma unroll
+                for (int k = 0; k < HPT; ++k) zb = fmaxf(zb, fabsf(hv[k].x) + fabsf(hv[k].y));
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) zb = fmaxf(zb, __shfl_xor(zb, off, 64));
+                if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = zb;
+            }
         }
         if (holds_img) {
             float e[9];
@@ -422,12 +486,15 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
 #pragma unroll
             for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         }
-        if (SCATTER) {
+        if (SCATTER && PACKED) {
+            for (int t = threadIdx.x; t < XN; t += kBT) acc_pk[t] = 0ull;
+        } else if (SCATTER) {
             for (int t = threadIdx.x; t < XN; t += kBT) {
                 acc_re[t] = 0.0;
                 acc_im[t] = 0.0;
             }
         }
+        PackedScale pk;  // set in the first window (after a barrier)
         // enumeration box (grid coordinates): the brick's pixels have floor(g)
         // in the brick
         float lo[3], hi[3];
@@ -447,6 +514,12 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
             const int nw = min(WI, n_img - w0);
             // every wave has finished with the previous window's tables
             __syncthreads();
+            if (PACKED && w0 == 0) {
+                float zb = 0.f;
+#pragma unroll
+                for (int w = 0; w < kBT / 64; ++w) zb = fmaxf(zb, s_wmax[w]);
+                pk = PackedScale::make(__builtin_amdgcn_readfirstlane(__float_as_int(zb)), a.scale);
+            }
             // ---- the window's images (one thread each): constants, first row,
             // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
             // MAXROWS - 1 of the window; those past its row count stay empty.
@@ -657,7 +730,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                                     const float fct = a.scale * C;
                                     const float2 rt = cmul_conj(rr, T);
                                     val = make_float2(fct * rt.x, fct * rt.y);
-                                } else if (MODE == kBHvp) {
+                                } else if (is_hvp(MODE)) {
                                     const float fct = a.scale * C * C;
                                     val = make_float2(fct * acc.x, fct * acc.y);
                                 } else if (MODE == kBFeatures) {
@@ -675,6 +748,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                                         const int li = lb + az * XP + ay * XR + ax;
                                         if (MODE == kBSqDiag) {
                                             atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                                        } else if (PACKED) {
+                                            atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
                                         } else {
                                             atomicAdd(&acc_re[li], (double)(w * val.x));
                                             atomicAdd(&acc_im[li], (double)(w * val.y));
@@ -702,6 +777,13 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || MODE == kBHvp) ? CSG_BR
                 if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
                 const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
                 const int li = (tz * XR + ty) * XR + tx;
+                if (PACKED) {
+                    float re, im;
+                    pk.unpack(acc_pk[li], re, im);
+                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
+                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
+                    continue;
+                }
                 const float re = (float)acc_re[li];
                 if (MODE == kBSqDiag) {
                     if (re != 0.f) atomicAdd(a.accum_real + gi, re);
@@ -836,13 +918,15 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.items = items;
         a.n_items = scalars;
         a.next_item = scalars + 1;
-        hipEvent_t t0 = timing_begin(MODE, st);
+        // the probe HVP is timed with the HVP
+        constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
+        hipEvent_t t0 = timing_begin(TMODE, st);
         if (shift)
             hipLaunchKernelGGL((brick_kernel<MODE, true>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         else
             hipLaunchKernelGGL((brick_kernel<MODE, false>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         e = hipGetLastError();
-        timing_end(MODE, t0, st);
+        timing_end(TMODE, t0, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -899,9 +983,12 @@ hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *de
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
-                            float scale, float2 *accum, void *ws, hipStream_t st) {
+                            float scale, float2 *accum, void *ws, hipStream_t st, bool probe) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_hvp_atomic(g, rot, defocus, n, z, scale, accum, st);
+    if (probe)
+        return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws,
+                                          st);
     return run_brick_mode<kBHvp>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
 }
 

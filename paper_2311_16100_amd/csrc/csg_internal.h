@@ -36,8 +36,10 @@ hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const floa
                                      float2 *accum, void *ws, hipStream_t st);
 hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
                                 float *diag, void *ws, hipStream_t st);
+// probe: z is a Rademacher probe pair (entries 0 or +-1 per component), which
+// allows the packed fixed-point accumulator
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
-                            float scale, float2 *accum, void *ws, hipStream_t st);
+                            float scale, float2 *accum, void *ws, hipStream_t st, bool probe = false);
 
 // pixel-parallel kernels (pixel_kernels.hip)
 hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,

@@ -171,6 +171,18 @@ def test_hutchinson_parity(b, n_probe):
     assert rel(got, want) <= 1e-4
 
 
+def test_hutchinson_parity_many_images(b):
+    """More than 128 images per brick: several work items per brick, several
+    image windows per item, and their fixed-point accumulators flushed into one
+    voxel by global atomics."""
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=300, seed=22)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df = to_dev(P.rot, P.defocus)
+    got = b.hutchinson_diag(g, o, rot, df, 2, seed=5, scale=0.7, lam=0.02, probe0=11).cpu().numpy()
+    want = oracle.hutchinson_diag(grid_o, opt_o, P, 2, 5, 0.7, 0.02, probe0=11)
+    assert rel(got, want) <= 1e-4
+
+
 @pytest.mark.parametrize("interp", [0, 1])
 def test_exact_diag_and_features_parity(b, interp):
     grid_o, opt_o, P, vol, img = make_case(M=36, n=37, seed=31, interp=interp)
@@ -349,6 +361,23 @@ def test_full_size_hvp_matches_composition(b, full):
     hz = b.hvp(g, o, rot, df, z, scale, lam)
     want = b.backproject(g, o, rot, df, b.project(g, o, rot, df, z), ctf_power=1, scale=scale) + lam * z
     assert rel(hz.cpu().numpy(), want.cpu().numpy()) <= 1e-5
+
+
+def test_full_size_hutchinson_matches_general_hvp(b, full):
+    """The Hutchinson probe product of the full batch (fixed-point packed
+    accumulator) against the general HVP (double accumulator) of the same
+    Rademacher pair: z_a (H z_a) / 2 + z_b (H z_b) / 2."""
+    grid_o, P, vol, rot, df, v = full
+    g, o = b.Grid(256), b.Optics()
+    nv = 256 ** 3
+    scale, lam = 195.3, 0.05
+    za = b.rademacher(nv, 99, 6)
+    zb = b.rademacher(nv, 99, 7)
+    z = torch.complex(za, zb).reshape(256, 256, 256)
+    hz = b.hvp(g, o, rot, df, z, scale, lam)
+    want = (za * hz.real.reshape(-1) + zb * hz.imag.reshape(-1)) / 2
+    got = b.hutchinson_diag(g, o, rot, df, 2, seed=99, scale=scale, lam=lam, probe0=6).reshape(-1)
+    assert rel(got.cpu().numpy(), want.cpu().numpy()) <= 1e-5
 
 
 @pytest.mark.parametrize("M", [16, 34])
