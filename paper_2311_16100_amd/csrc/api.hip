@@ -257,18 +257,18 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
     const int64_t nv = nvox_of(g);
     float2 *z = (float2 *)((char *)workspace + kScalarBytes);
     float2 *hz = z + nv;
-    CSG_TRY(csg::launch_fill_f32(diag_out, nv, 0.0f, st), "csg_hutchinson_diag");
     const float w = 1.0f / (float)n_probe;
     for (int32_t p = 0; p < n_probe; p += 2) {
         const int has_b = (p + 1 < n_probe) ? 1 : 0;
-        CSG_TRY(csg::launch_rademacher_pair(z, nv, seed, (uint64_t)(probe0 + p), (uint64_t)(probe0 + p + 1), has_b, st),
+        // z = probe pair, hz = lambda z
+        CSG_TRY(csg::launch_probe_init(z, hz, nv, seed, (uint64_t)(probe0 + p), (uint64_t)(probe0 + p + 1), has_b,
+                                       lambda, st),
                 "csg_hutchinson_diag");
-        CSG_TRY(csg::launch_scaled_copy(hz, z, lambda, nv, nullptr, st), "csg_hutchinson_diag");
         if (poses->n > 0)
             CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz,
                                           (char *)(hz + nv), st, /*probe=*/true),
                     "csg_hutchinson_diag");
-        CSG_TRY(csg::launch_zhz_accum(diag_out, z, hz, nv, w, st), "csg_hutchinson_diag");
+        CSG_TRY(csg::launch_zhz_accum(diag_out, z, hz, nv, w, /*first=*/p == 0, st), "csg_hutchinson_diag");
     }
     return CSG_OK;
 }

@@ -71,7 +71,12 @@ hipError_t launch_finish_loss(double *loss_out, const double *data, const double
 hipError_t launch_rademacher(float *z, int64_t nvox, uint64_t seed, uint64_t probe, hipStream_t st);
 hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                                   hipStream_t st);
-hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, hipStream_t st);
+// first: the sum starts with this probe pair (diag is written, not read)
+hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,
+                            hipStream_t st);
+// z = Rademacher probe pair (as launch_rademacher_pair), hz = lam z
+hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
+                             float lam, hipStream_t st);
 hipError_t launch_shell_sums(const float2 *u, const float2 *v, int M, double *out, hipStream_t st);
 hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, double ratio, float lam,
                         double *alpha_out, hipStream_t st);

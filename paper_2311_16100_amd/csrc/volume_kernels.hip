@@ -41,6 +41,24 @@ __global__ __launch_bounds__(kBlock) void scaled_copy_kernel(float2 *__restrict_
     }
 }
 
+// The same over pairs of voxels (16-byte accesses; pointers 16-byte aligned,
+// nvox even).
+__global__ __launch_bounds__(kBlock) void scaled_copy2_kernel(float4 *__restrict__ out, const float4 *__restrict__ in,
+                                                               float lam, int64_t npair, double *norm2) {
+    __shared__ double red[16];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npair; k += stride) {
+        const float4 v = in[k];
+        out[k] = make_float4(lam * v.x, lam * v.y, lam * v.z, lam * v.w);
+        s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+    }
+    if (norm2) {
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) atomicAdd(norm2, t);
+    }
+}
+
 __global__ void fill_f64_kernel(double *p, int n, double v) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
@@ -98,6 +116,38 @@ __global__ __launch_bounds__(kBlock) void rademacher_pair_kernel(float2 *__restr
     }
 }
 
+// Probe pair and the start of its product in one pass: z = z_pa + i z_pb and
+// hz = lam z.  Thread t covers voxels 8t .. 8t+7, eight bits of one 128-bit
+// Philox block (the same bits rademacher4 assigns them); nvox is a multiple of
+// 8 and both pointers are 16-byte aligned.
+__global__ __launch_bounds__(kBlock) void probe_init_kernel(float4 *__restrict__ z, float4 *__restrict__ hz,
+                                                             int64_t n8, uint64_t seed, uint64_t pa, uint64_t pb,
+                                                             int has_b, float lam) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n8; t += stride) {
+        const int64_t k = t * 8;
+        const int bit = (int)(k & 127);
+        const uint32_t ctr0 = (uint32_t)(k >> 7);
+        const U4 ra = philox4x32_10(U4{ctr0, (uint32_t)pa, (uint32_t)(pa >> 32), kRademacherTag}, (uint32_t)seed,
+                                    (uint32_t)(seed >> 32));
+        const uint32_t wa = ((bit < 32) ? ra.x : (bit < 64) ? ra.y : (bit < 96) ? ra.z : ra.w) >> (bit & 31);
+        uint32_t wb = 0;
+        if (has_b) {
+            const U4 rb = philox4x32_10(U4{ctr0, (uint32_t)pb, (uint32_t)(pb >> 32), kRademacherTag}, (uint32_t)seed,
+                                        (uint32_t)(seed >> 32));
+            wb = ((bit < 32) ? rb.x : (bit < 64) ? rb.y : (bit < 96) ? rb.z : rb.w) >> (bit & 31);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const float a0 = (wa >> e) & 1u ? -1.f : 1.f, a1 = (wa >> (e + 1)) & 1u ? -1.f : 1.f;
+            const float b0 = has_b ? ((wb >> e) & 1u ? -1.f : 1.f) : 0.f;
+            const float b1 = has_b ? ((wb >> (e + 1)) & 1u ? -1.f : 1.f) : 0.f;
+            z[t * 4 + e / 2] = make_float4(a0, b0, a1, b1);
+            hz[t * 4 + e / 2] = make_float4(lam * a0, lam * b0, lam * a1, lam * b1);
+        }
+    }
+}
+
 // diag += w * (Re z Re hz + Im z Im hz)
 __global__ __launch_bounds__(kBlock) void zhz_accum_kernel(float *__restrict__ diag, const float2 *__restrict__ z,
                                                             const float2 *__restrict__ hz, int64_t nvox, float w) {
@@ -105,6 +155,19 @@ __global__ __launch_bounds__(kBlock) void zhz_accum_kernel(float *__restrict__ d
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
         const float2 a = z[k], b = hz[k];
         diag[k] = fmaf(w, fmaf(a.x, b.x, a.y * b.y), diag[k]);
+    }
+}
+
+// The same over pairs of voxels; with `first` the sum starts here (diag is not
+// read).  16-byte aligned z and hz, 8-byte aligned diag, nvox even.
+__global__ __launch_bounds__(kBlock) void zhz_accum2_kernel(float2 *__restrict__ diag, const float4 *__restrict__ z,
+                                                             const float4 *__restrict__ hz, int64_t npair, float w,
+                                                             int first) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npair; k += stride) {
+        const float4 a = z[k], b = hz[k];
+        const float2 d = first ? make_float2(0.f, 0.f) : diag[k];
+        diag[k] = make_float2(fmaf(w, fmaf(a.x, b.x, a.y * b.y), d.x), fmaf(w, fmaf(a.z, b.z, a.w * b.w), d.y));
     }
 }
 
@@ -138,6 +201,47 @@ __global__ __launch_bounds__(kBlock) void precond_step_kernel(int64_t nvox, cons
         v_out[k] = o;
         s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh;
         s1 += (double)o.x * o.x + (double)o.y * o.y;
+    }
+    const double t0 = block_sum(s0, red);
+    const double t1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&stats[0], t0);
+        atomicAdd(&stats[1], t1);
+    }
+}
+
+// The same over pairs of voxels (complex arrays 16-byte aligned, real arrays
+// 8-byte aligned, nvox even).
+__global__ __launch_bounds__(kBlock) void precond_step2_kernel(int64_t npair, const float4 *__restrict__ v,
+                                                                const float4 *__restrict__ g, float2 *D, float2 *D_avg,
+                                                                const float2 *__restrict__ zHz, float wk_old,
+                                                                float wk_new, float beta, float alpha, float eta,
+                                                                float4 *v_out, float2 *Dhat_out, double *stats) {
+    __shared__ double red[16];
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npair; k += stride) {
+        float2 dh = make_float2(1.0f, 1.0f);
+        if (D) {
+            float2 d = D[k];
+            if (zHz) {
+                const float2 za = zHz[k], av = D_avg[k];
+                const float2 da = make_float2(fmaf(wk_old, av.x, wk_new * za.x), fmaf(wk_old, av.y, wk_new * za.y));
+                D_avg[k] = da;
+                d = make_float2(fmaf(beta, d.x, (1.0f - beta) * da.x), fmaf(beta, d.y, (1.0f - beta) * da.y));
+                D[k] = d;
+            }
+            dh = make_float2(fmaxf(fabsf(d.x), alpha), fmaxf(fabsf(d.y), alpha));
+        }
+        if (Dhat_out) Dhat_out[k] = dh;
+        const float4 gk = g[k], vk = v[k];
+        const float i0 = 1.0f / dh.x, i1 = 1.0f / dh.y;
+        const float4 o = make_float4(vk.x - eta * gk.x * i0, vk.y - eta * gk.y * i0, vk.z - eta * gk.z * i1,
+                                     vk.w - eta * gk.w * i1);
+        v_out[k] = o;
+        s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh.x +
+              ((double)gk.z * gk.z + (double)gk.w * gk.w) / (double)dh.y;
+        s1 += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
     }
     const double t0 = block_sum(s0, red);
     const double t1 = block_sum(s1, red);
@@ -234,9 +338,17 @@ hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, 
     return hipGetLastError();
 }
 
+static inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
 hipError_t launch_scaled_copy(float2 *out, const float2 *in, float lam, int64_t nvox, double *norm2, hipStream_t st) {
-    hipLaunchKernelGGL(scaled_copy_kernel, dim3(norm2 ? reduce_blocks(nvox) : stream_blocks(nvox)), dim3(kBlock), 0,
-                       st, out, in, lam, nvox, norm2);
+    if (nvox % 2 == 0 && aligned(out, 16) && aligned(in, 16)) {
+        const int64_t np = nvox / 2;
+        hipLaunchKernelGGL(scaled_copy2_kernel, dim3(norm2 ? reduce_blocks(np) : stream_blocks(np)), dim3(kBlock), 0,
+                           st, (float4 *)out, (const float4 *)in, lam, np, norm2);
+    } else {
+        hipLaunchKernelGGL(scaled_copy_kernel, dim3(norm2 ? reduce_blocks(nvox) : stream_blocks(nvox)), dim3(kBlock),
+                           0, st, out, in, lam, nvox, norm2);
+    }
     return hipGetLastError();
 }
 
@@ -269,7 +381,31 @@ hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64
     return hipGetLastError();
 }
 
-hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, hipStream_t st) {
+hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
+                             float lam, hipStream_t st) {
+    if (nvox % 8 == 0 && aligned(z, 16) && aligned(hz, 16)) {
+        const int64_t n8 = nvox / 8;
+        hipLaunchKernelGGL(probe_init_kernel, dim3(stream_blocks(n8)), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz,
+                           n8, seed, pa, pb, has_b, lam);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_rademacher_pair(z, nvox, seed, pa, pb, has_b, st);
+    if (e != hipSuccess) return e;
+    return launch_scaled_copy(hz, z, lam, nvox, nullptr, st);
+}
+
+hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,
+                            hipStream_t st) {
+    if (nvox % 2 == 0 && aligned(diag, 8) && aligned(z, 16) && aligned(hz, 16)) {
+        const int64_t np = nvox / 2;
+        hipLaunchKernelGGL(zhz_accum2_kernel, dim3(stream_blocks(np)), dim3(kBlock), 0, st, (float2 *)diag,
+                           (const float4 *)z, (const float4 *)hz, np, w, first ? 1 : 0);
+        return hipGetLastError();
+    }
+    if (first) {
+        hipError_t e = launch_fill_f32(diag, nvox, 0.0f, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(zhz_accum_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, diag, z, hz, nvox, w);
     return hipGetLastError();
 }
@@ -281,8 +417,16 @@ hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, f
     const float wk_new = k > 0 ? (float)(1.0 / (double)k) : 0.f;
     hipError_t e = launch_fill_f64(stats, 2, 0.0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(precond_step_kernel, dim3(reduce_blocks(nvox)), dim3(kBlock), 0, st, nvox, v, g, D, D_avg, zHz,
-                       wk_old, wk_new, beta, alpha, eta, v_out, Dhat_out, stats);
+    if (nvox % 2 == 0 && aligned(v, 16) && aligned(g, 16) && aligned(v_out, 16) && aligned(D, 8) &&
+        aligned(D_avg, 8) && aligned(zHz, 8) && aligned(Dhat_out, 8)) {
+        const int64_t np = nvox / 2;
+        hipLaunchKernelGGL(precond_step2_kernel, dim3(reduce_blocks(np)), dim3(kBlock), 0, st, np, (const float4 *)v,
+                           (const float4 *)g, (float2 *)D, (float2 *)D_avg, (const float2 *)zHz, wk_old, wk_new, beta,
+                           alpha, eta, (float4 *)v_out, (float2 *)Dhat_out, stats);
+    } else {
+        hipLaunchKernelGGL(precond_step_kernel, dim3(reduce_blocks(nvox)), dim3(kBlock), 0, st, nvox, v, g, D, D_avg,
+                           zHz, wk_old, wk_new, beta, alpha, eta, v_out, Dhat_out, stats);
+    }
     return hipGetLastError();
 }
 
