@@ -129,48 +129,65 @@ __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
 // ---------------------------------------------------------------------------
 // Cull: lists[b] = images whose plane meets the box of sample points whose
 // base corner lies in brick b (grid coordinates [b0, b0 + BS]^3), in
-// increasing image order.
+// increasing image order.  One wave per brick, eight bricks per block: the
+// block stages the third rows of R for a chunk of images in LDS once, and each
+// wave tests them against its brick.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void brick_cull_kernel(Geom g, const float *rot, int64_t n, int nbx,
-                                                             int *counts, int *lists, int stride) {
-    __shared__ int wave_count[kBlock / 64];
-    const int b = blockIdx.x;
-    int o[3];
-    brick_origin(b, nbx, o);
-    float c[3], hw[3];
-    float dist2 = 0.f;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const float lo = (float)(o[d] - g.half), hi = (float)(o[d] + BS - g.half);
-        c[d] = 0.5f * (lo + hi);
-        hw[d] = 0.5f * (hi - lo);
-        const float near = fmaxf(fmaxf(lo, -hi), 0.f);  // distance of the box to the origin along d
-        dist2 += near * near;
-    }
-    // sample points lie within |p| <= r_max; the box must come that close
-    const float rmax = sqrtf((float)g.k2max) + 2.0f;
-    const bool reachable = dist2 <= rmax * rmax;
+constexpr int kCullWaves = 8;
+constexpr int kCullThreads = kCullWaves * 64;
+
+__global__ __launch_bounds__(kCullThreads) void brick_cull_kernel(Geom g, const float *rot, int64_t n, int nbx, int nb,
+                                                                   int *counts, int *lists, int stride) {
+    __shared__ float se[kCullThreads][3];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int total = 0;
-    for (int64_t base = 0; base < n; base += kBlock) {
-        const int64_t i = base + threadIdx.x;
-        bool keep = false;
-        if (reachable && i < n) {
-            const float e0 = rot[i * 9 + 6], e1 = rot[i * 9 + 7], e2 = rot[i * 9 + 8];
-            const float h = e0 * c[0] + e1 * c[1] + e2 * c[2];
-            const float reach = fabsf(e0) * hw[0] + fabsf(e1) * hw[1] + fabsf(e2) * hw[2];
-            keep = fabsf(h) <= reach + kClipEps;
+    const int b = blockIdx.x * kCullWaves + wv;
+    float c[3] = {0.f, 0.f, 0.f}, hw[3] = {0.f, 0.f, 0.f};
+    bool reachable = false;
+    if (b < nb) {
+        int o[3];
+        brick_origin(b, nbx, o);
+        float dist2 = 0.f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float lo = (float)(o[d] - g.half), hi = (float)(o[d] + BS - g.half);
+            c[d] = 0.5f * (lo + hi);
+            hw[d] = 0.5f * (hi - lo);
+            const float near = fmaxf(fmaxf(lo, -hi), 0.f);  // distance of the box to the origin along d
+            dist2 += near * near;
         }
-        const uint64_t mask = __ballot(keep);
-        if (lane == 0) wave_count[wv] = __popcll(mask);
+        // sample points lie within |p| <= r_max; the box must come that close
+        const float rmax = sqrtf((float)g.k2max) + 2.0f;
+        reachable = dist2 <= rmax * rmax;
+    }
+    const uint64_t below = (1ull << lane) - 1ull;
+    int total = 0;
+    for (int64_t base = 0; base < n; base += kCullThreads) {
+        const int64_t i = base + threadIdx.x;
+        if (i < n) {
+            se[threadIdx.x][0] = rot[i * 9 + 6];
+            se[threadIdx.x][1] = rot[i * 9 + 7];
+            se[threadIdx.x][2] = rot[i * 9 + 8];
+        }
         __syncthreads();
-        int off = total;
-        for (int w = 0; w < wv; ++w) off += wave_count[w];
-        if (keep) lists[(int64_t)b * stride + off + __popcll(mask & ((1ull << lane) - 1ull))] = (int)i;
-        for (int w = 0; w < kBlock / 64; ++w) total += wave_count[w];
+        const int cnt = (int)min((int64_t)kCullThreads, n - base);
+        if (reachable) {
+            for (int s0 = 0; s0 < cnt; s0 += 64) {
+                const int ii = s0 + lane;
+                bool keep = false;
+                if (ii < cnt) {
+                    const float e0 = se[ii][0], e1 = se[ii][1], e2 = se[ii][2];
+                    const float h = e0 * c[0] + e1 * c[1] + e2 * c[2];
+                    const float reach = fabsf(e0) * hw[0] + fabsf(e1) * hw[1] + fabsf(e2) * hw[2];
+                    keep = fabsf(h) <= reach + kClipEps;
+                }
+                const uint64_t mask = __ballot(keep);
+                if (keep) lists[(int64_t)b * stride + total + __popcll(mask & below)] = (int)(base + ii);
+                total += __popcll(mask);
+            }
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) counts[b] = total;
+    if (b < nb && lane == 0) counts[b] = total;
 }
 
 // Exclusive scan of one int per thread over the block; returns the prefix and
@@ -229,15 +246,27 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
         base[k] = tot;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int k = chunk; k >= 1; --k) {
-            const int t = base[k];
-            base[k] = run;
-            run += t;
+    // bucket starts in the order chunk, chunk - 1, ..., 1: an exclusive scan
+    // over the first chunk threads (thread r holds bucket chunk - r)
+    {
+        __shared__ int wsum[kPlanWaves];
+        const int r = threadIdx.x, lane = r & 63;
+        const int val = r < chunk ? base[chunk - r] : 0;
+        int x = val;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
         }
-        *n_items = run;
-        *next_item = 0;
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int pre = 0;
+        for (int w = 0; w < wv; ++w) pre += wsum[w];
+        if (r < chunk) base[chunk - r] = pre + x - val;
+        if (r == chunk - 1) {
+            *n_items = pre + x;
+            *next_item = 0;
+        }
     }
     __syncthreads();
     if (threadIdx.x <= chunk) {
@@ -334,20 +363,23 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // is the low word read as a signed integer, im the rest shifted down.
 //
 // The bound: a contribution is w val with val = scale C^2 (P z)_pixel, so
-// |val| <= |scale| max|z| over the staged brick (|C| <= 1 and the trilinear
-// weights sum to 1).  A voxel receives from one image at most the pixels of
-// the plane lattice inside its 2x2x2 neighbourhood, whose section has diameter
-// at most 2 sqrt(3): at most 16 pixels, each with weight <= 1.  Over an item of
-// at most 128 images a component sum is therefore below
-// 2048 |scale| max|z| = B, and S = 2^e with B S <= 2^30 keeps every sum (and
-// every rounded contribution) below 2^30.  The rounding error is at most
-// 1/(2S) per contribution, i.e. 2^-31 B per contribution (relative 5e-10 of B).
+// |val| <= V = |scale| max|z| over the staged brick (|C| <= 1 and the
+// trilinear weights sum to 1).  A voxel receives from one image at most
+// the pixels of the plane lattice inside its 2x2x2 neighbourhood, whose section
+// has diameter at most 2 sqrt(3): at most 16 pixels, each with weight <= 1.
+// Over an item of at most 128 images a component sum is therefore below
+// 2048 V = B, and S = 2^e with B S <= 2^30 keeps every sum (and every rounded
+// contribution) below 2^30.  The rounding error is at most 1/(2S) per
+// contribution, i.e. 2^-31 B (relative 5e-10 of B).  Because B is a worst
+// case, the result is about 1e-5 relative (measured), well below the noise of
+// a two-probe Hutchinson estimate; the gradient and the general HVP, whose
+// sums need float accuracy, keep the double accumulator.
 struct PackedScale {
     float S = 1.f, invS = 1.f;
-    static __device__ __forceinline__ PackedScale make(int zmax_bits, float scale) {
+    static __device__ __forceinline__ PackedScale make(float V) {
         static_assert(CHUNK_ADJ <= 128, "the fixed-point bound assumes at most 128 images per item");
         PackedScale p;
-        const float B = 2048.f * fabsf(scale) * __int_as_float(zmax_bits);
+        const float B = 2048.f * V;
         int e = 0;
         if (B > 0.f && B < 3.0e38f) {
             int k;
@@ -385,14 +417,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     constexpr bool SHIFTED = SHIFT && READS_IMG;
     constexpr int IMGDAT = SHIFTED ? 10 : 8;
     constexpr int CHUNK = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
-    // probe HVP: both components of a contribution go into one 64-bit integer
-    // LDS atomic, as 32-bit fixed-point numbers with a per-item power-of-two
-    // scale (see PackedScale); the other adjoint modes accumulate in double
-    constexpr bool PACKED = MODE == kBHvpProbe;
+    // Packed accumulation (see PackedScale): both components of a contribution
+    // go into one 64-bit integer LDS atomic, as 32-bit fixed-point numbers with
+    // a per-item power-of-two scale.  Only the probe HVP packs; the other
+    // adjoint modes accumulate in double.
+    constexpr bool PK_ALWAYS = MODE == kBHvpProbe;
     __shared__ float2 vh[GATHER ? XN : 1];
-    __shared__ double acc_re[SCATTER && !PACKED ? XN : 1];
-    __shared__ double acc_im[SCATTER && !PACKED ? XN : 1];
-    __shared__ unsigned long long acc_pk[PACKED ? XN : 1];
+    __shared__ double acc_re[SCATTER ? XN : 1];
+    __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN : 1];
+    // the packed accumulator shares the storage of acc_re
+    unsigned long long *const acc_pk = reinterpret_cast<unsigned long long *>(acc_re);
     __shared__ float s_wmax[kBT / 64];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
@@ -462,7 +496,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
             }
-            if (PACKED) {
+            if (PK_ALWAYS) {
                 // bound on |z| over the staged brick (|re| + |im| >= modulus),
                 // per wave; combined after the next barrier
                 float zb = 0.f;
@@ -486,7 +520,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
 #pragma unroll
             for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         }
-        if (SCATTER && PACKED) {
+        if (SCATTER && PK_ALWAYS) {
             for (int t = threadIdx.x; t < XN; t += kBT) acc_pk[t] = 0ull;
         } else if (SCATTER) {
             for (int t = threadIdx.x; t < XN; t += kBT) {
@@ -514,11 +548,12 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             const int nw = min(WI, n_img - w0);
             // every wave has finished with the previous window's tables
             __syncthreads();
-            if (PACKED && w0 == 0) {
+            if (PK_ALWAYS && w0 == 0) {
                 float zb = 0.f;
 #pragma unroll
                 for (int w = 0; w < kBT / 64; ++w) zb = fmaxf(zb, s_wmax[w]);
-                pk = PackedScale::make(__builtin_amdgcn_readfirstlane(__float_as_int(zb)), a.scale);
+                zb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(zb)));
+                pk = PackedScale::make(fabsf(a.scale) * zb);
             }
             // ---- the window's images (one thread each): constants, first row,
             // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
@@ -748,7 +783,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                         const int li = lb + az * XP + ay * XR + ax;
                                         if (MODE == kBSqDiag) {
                                             atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                                        } else if (PACKED) {
+                                        } else if (PK_ALWAYS) {
                                             atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
                                         } else {
                                             atomicAdd(&acc_re[li], (double)(w * val.x));
@@ -777,7 +812,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
                 const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
                 const int li = (tz * XR + ty) * XR + tx;
-                if (PACKED) {
+                if (PK_ALWAYS) {
                     float re, im;
                     pk.unpack(acc_pk[li], re, im);
                     if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
@@ -888,8 +923,8 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
         const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
         const int stride = (int)ns;
-        hipLaunchKernelGGL(brick_cull_kernel, dim3(nb), dim3(kBlock), 0, st, g, rot + s0 * 9, ns, nbx, counts, lists,
-                           stride);
+        hipLaunchKernelGGL(brick_cull_kernel, dim3((unsigned)((nb + kCullWaves - 1) / kCullWaves)), dim3(kCullThreads), 0,
+                           st, g, rot + s0 * 9, ns, nbx, nb, counts, lists, stride);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(brick_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, counts, nb, chunk, items, scalars,

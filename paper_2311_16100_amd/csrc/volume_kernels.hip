@@ -117,34 +117,56 @@ __global__ __launch_bounds__(kBlock) void rademacher_pair_kernel(float2 *__restr
 }
 
 // Probe pair and the start of its product in one pass: z = z_pa + i z_pb and
-// hz = lam z.  Thread t covers voxels 8t .. 8t+7, eight bits of one 128-bit
-// Philox block (the same bits rademacher4 assigns them); nvox is a multiple of
-// 8 and both pointers are 16-byte aligned.
+// hz = lam z.  Voxel k takes bit k mod 128 of Philox block k / 128, as in
+// rademacher4.  A wave covers 8192 consecutive voxels: each lane evaluates one
+// Philox block (per probe) into LDS, then the wave writes the voxels two per
+// lane and store, consecutive lanes at consecutive 16-byte addresses.  nvox is
+// even and both pointers are 16-byte aligned.
 __global__ __launch_bounds__(kBlock) void probe_init_kernel(float4 *__restrict__ z, float4 *__restrict__ hz,
-                                                             int64_t n8, uint64_t seed, uint64_t pa, uint64_t pb,
+                                                             int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb,
                                                              int has_b, float lam) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n8; t += stride) {
-        const int64_t k = t * 8;
-        const int bit = (int)(k & 127);
-        const uint32_t ctr0 = (uint32_t)(k >> 7);
-        const U4 ra = philox4x32_10(U4{ctr0, (uint32_t)pa, (uint32_t)(pa >> 32), kRademacherTag}, (uint32_t)seed,
+    constexpr int NW = kBlock / 64;
+    __shared__ uint32_t words[NW][2][4][64];  // [wave][probe][word][block of the chunk]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nchunk = (nvox + 8191) / 8192;
+    const int64_t npair = nvox / 2;
+    for (int64_t c = (int64_t)blockIdx.x * NW + wv; c < nchunk; c += (int64_t)gridDim.x * NW) {
+        const uint32_t blk = (uint32_t)(c * 64 + lane);
+        const U4 ra = philox4x32_10(U4{blk, (uint32_t)pa, (uint32_t)(pa >> 32), kRademacherTag}, (uint32_t)seed,
                                     (uint32_t)(seed >> 32));
-        const uint32_t wa = ((bit < 32) ? ra.x : (bit < 64) ? ra.y : (bit < 96) ? ra.z : ra.w) >> (bit & 31);
-        uint32_t wb = 0;
-        if (has_b) {
-            const U4 rb = philox4x32_10(U4{ctr0, (uint32_t)pb, (uint32_t)(pb >> 32), kRademacherTag}, (uint32_t)seed,
-                                        (uint32_t)(seed >> 32));
-            wb = ((bit < 32) ? rb.x : (bit < 64) ? rb.y : (bit < 96) ? rb.z : rb.w) >> (bit & 31);
+        U4 rb = U4{0u, 0u, 0u, 0u};
+        if (has_b)
+            rb = philox4x32_10(U4{blk, (uint32_t)pb, (uint32_t)(pb >> 32), kRademacherTag}, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+        words[wv][0][0][lane] = ra.x;
+        words[wv][0][1][lane] = ra.y;
+        words[wv][0][2][lane] = ra.z;
+        words[wv][0][3][lane] = ra.w;
+        words[wv][1][0][lane] = rb.x;
+        words[wv][1][1][lane] = rb.y;
+        words[wv][1][2][lane] = rb.z;
+        words[wv][1][3][lane] = rb.w;
+        // the words were written by this wave: its LDS accesses complete in
+        // order, and the barrier keeps the compiler from moving them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // store j: voxels c 8192 + 128 j + 2 lane (+1), bits 2 lane (+1) of
+        // block c 64 + j
+        const int w = lane >> 4, sh = (2 * lane) & 31;
+        for (int j = 0; j < 64; ++j) {
+            const int64_t q = c * 4096 + (int64_t)j * 64 + lane;
+            if (q >= npair) break;
+            const uint32_t ba = words[wv][0][w][j] >> sh, bb = words[wv][1][w][j] >> sh;
+            const float a0 = (ba & 1u) ? -1.f : 1.f, a1 = (ba & 2u) ? -1.f : 1.f;
+            const float b0 = has_b ? ((bb & 1u) ? -1.f : 1.f) : 0.f;
+            const float b1 = has_b ? ((bb & 2u) ? -1.f : 1.f) : 0.f;
+            z[q] = make_float4(a0, b0, a1, b1);
+            hz[q] = make_float4(lam * a0, lam * b0, lam * a1, lam * b1);
         }
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-            const float a0 = (wa >> e) & 1u ? -1.f : 1.f, a1 = (wa >> (e + 1)) & 1u ? -1.f : 1.f;
-            const float b0 = has_b ? ((wb >> e) & 1u ? -1.f : 1.f) : 0.f;
-            const float b1 = has_b ? ((wb >> (e + 1)) & 1u ? -1.f : 1.f) : 0.f;
-            z[t * 4 + e / 2] = make_float4(a0, b0, a1, b1);
-            hz[t * 4 + e / 2] = make_float4(lam * a0, lam * b0, lam * a1, lam * b1);
-        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -383,10 +405,12 @@ hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64
 
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st) {
-    if (nvox % 8 == 0 && aligned(z, 16) && aligned(hz, 16)) {
-        const int64_t n8 = nvox / 8;
-        hipLaunchKernelGGL(probe_init_kernel, dim3(stream_blocks(n8)), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz,
-                           n8, seed, pa, pb, has_b, lam);
+    if (nvox % 2 == 0 && aligned(z, 16) && aligned(hz, 16)) {
+        // one wave per 8192 voxels, four waves per block
+        int64_t blocks = ((nvox + 8191) / 8192 + kBlock / 64 - 1) / (kBlock / 64);
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(probe_init_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz,
+                           nvox, seed, pa, pb, has_b, lam);
         return hipGetLastError();
     }
     hipError_t e = launch_rademacher_pair(z, nvox, seed, pa, pb, has_b, st);

@@ -144,6 +144,22 @@ def test_gradient_and_loss_parity(b, case):
         assert loss.item() == pytest.approx(want_f, rel=1e-5), det
 
 
+@pytest.mark.parametrize("blob", [False, True])
+def test_gradient_parity_mid_size(b, blob):
+    """M = 72 with 200 images (several work items per central brick), random
+    and blob volumes: against the oracle, and against the deterministic
+    (owner-computes) adjoint."""
+    grid_o, opt_o, P, vol, img = make_case(M=72, n=200, seed=31, blob=blob)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    scale, lam = 12.5, 0.07
+    want = oracle.gradient(grid_o, opt_o, P, vol, img * _disk(grid_o)[None], scale, lam)
+    got = b.gradient(g, o, rot, df, v, x, scale, lam)
+    det = b.gradient(g, o, rot, df, v, x, scale, lam, deterministic=True)
+    assert rel(got.cpu().numpy(), want) <= 1e-4
+    assert rel(got.cpu().numpy(), det.cpu().numpy()) <= 1e-5
+
+
 @pytest.mark.parametrize("case", CASES[:4], ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
 def test_hvp_parity(b, case):
     grid_o, opt_o, P, vol, img = make_case(**case)
