@@ -146,7 +146,11 @@ int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, voi
 
 /* Hutchinson's diagonal estimate D = mean_p z_p (.) H z_p (eq. (hutch)) over
  * the probes probe0 .. probe0 + n_probe - 1 (as csg_rademacher), with H the
- * minibatch Hessian of csg_hvp.  Two probes share one complex product.
+ * minibatch Hessian of csg_hvp.  Two probes share one complex product, whose
+ * adjoint sums are kept in 32-bit fixed point per component with a scale
+ * from a worst-case bound (the probe entries are +-1): the estimate matches
+ * the one formed with csg_hvp to about 1e-5 relative, far below its own
+ * sampling noise.
  *   diag_out device float [M^3], overwritten.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_HUTCHINSON). */
 int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,

@@ -10,7 +10,8 @@
 //     complex values of the gathered volume) in LDS, so every trilinear
 //     gather is 8 LDS reads;
 //   - accumulates the adjoint into an LDS array of the same extent with
-//     double-precision LDS atomics, and adds it to HBM once per voxel at the
+//     double-precision LDS atomics (the probe HVP: packed fixed point, see
+//     PackedScale), and adds it to HBM once per voxel at the
 //     end with global atomics (the upper faces of the extent belong to the
 //     neighbouring bricks, which other blocks may be flushing at the same
 //     time).  On gfx950 the LDS double atomic add sustains about 20x the lane
@@ -19,8 +20,8 @@
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
-// line against the box.  The rows of a window of images are numbered densely,
-// a block scan turns their intervals into one flat range of runs (one or two
+// line against the box.  Each image of a window owns a fixed block of row
+// records, a block scan turns their intervals into one flat range of runs (one or two
 // consecutive pixels of a row), and the lanes walk that range together, so
 // neighbouring lanes take neighbouring pixels of a row (coalesced image reads
 // and writes).  Within a run the sample point advances in exact fixed-point
