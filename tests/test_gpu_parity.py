@@ -295,6 +295,80 @@ def test_empty_and_degenerate_inputs(b):
         b.project(g, o, rd, dd, torch.ones((M, M, M + 2), dtype=torch.complex64, device="cuda"))
 
 
+@pytest.mark.parametrize("scale", [1e-12, 1e12])
+def test_hutchinson_extreme_scales(b, scale):
+    """The fixed-point scale of the probe product follows the bound over 24
+    orders of magnitude of the data scale."""
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=50, seed=23)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df = to_dev(P.rot, P.defocus)
+    nv = 36 ** 3
+    za = b.rademacher(nv, 3, 0)
+    zb = b.rademacher(nv, 3, 1)
+    hz = b.hvp(g, o, rot, df, torch.complex(za, zb).reshape(36, 36, 36), scale, 0.0)
+    want = (za * hz.real.reshape(-1) + zb * hz.imag.reshape(-1)) / 2
+    got = b.hutchinson_diag(g, o, rot, df, 2, seed=3, scale=scale, lam=0.0, probe0=0).reshape(-1)
+    assert rel(got.cpu().numpy(), want.cpu().numpy()) <= 1e-4
+
+
+def _vdot_chunked(a, c):
+    """<a, c> in complex128 over z-planes (a 1024^3 volume is too large to
+    promote at once)."""
+    t = torch.zeros((), dtype=torch.complex128, device=a.device)
+    for z0 in range(0, a.shape[0], 64):
+        t += torch.vdot(a[z0:z0 + 64].reshape(-1).to(torch.complex128), c[z0:z0 + 64].reshape(-1).to(torch.complex128))
+    return t
+
+
+def test_max_grid_side(b):
+    """M = 1024, the largest grid the library accepts; comparisons on the
+    device (one volume is 8.6 GB).  Axis-aligned rotations put every sample
+    point on a voxel, so their projections are exact copies of the central
+    plane; for random rotations the adjoint identity holds, and the fused
+    gradient equals the forward/adjoint composition."""
+    M, h = 1024, 512
+    gen = torch.Generator(device="cuda").manual_seed(1024)
+    v = torch.complex(torch.randn((M, M, M), generator=gen, device="cuda"),
+                      torch.randn((M, M, M), generator=gen, device="cuda"))
+    g = b.Grid(M)
+    # identity and a quarter turn about z, no CTF
+    rot = torch.tensor([[[1, 0, 0], [0, 1, 0], [0, 0, 1]], [[0, -1, 0], [1, 0, 0], [0, 0, 1]]],
+                       dtype=torch.float32, device="cuda")
+    df = torch.full((2,), 1.5e4, dtype=torch.float32, device="cuda")
+    y = b.project(g, b.NO_CTF, rot, df, v)
+    ax = torch.arange(M, device="cuda") - h
+    KY, KX = torch.meshgrid(ax, ax, indexing="ij")
+    disk = KX ** 2 + KY ** 2 <= (h - 1) ** 2
+    zero = torch.zeros((), dtype=torch.complex64, device="cuda")
+    plane = v[h]
+    assert torch.equal(y[0], torch.where(disk, plane, zero))
+    # pixel (kx, ky) of the quarter turn samples voxel (x, y, z) = (ky, -kx, 0) + h
+    assert torch.equal(y[1], torch.where(disk, plane[(-KX + h).clamp(0, M - 1), (KY + h).clamp(0, M - 1)], zero))
+    del y
+    # random rotations, CTF on
+    n = 3
+    rr = torch.from_numpy(synth.uniform_rotations(n, 77)).cuda()
+    dd = torch.from_numpy(synth.defocus_values(n, 1.0, 3.0, 77)).cuda()
+    x = torch.complex(torch.randn((n, M, M), generator=gen, device="cuda"),
+                      torch.randn((n, M, M), generator=gen, device="cuda"))
+    o = b.Optics()
+    Av = b.project(g, o, rr, dd, v)
+    At = b.backproject(g, o, rr, dd, x, ctf_power=1)
+    lhs = torch.vdot(Av.reshape(-1).to(torch.complex128), x.reshape(-1).to(torch.complex128))
+    rhs = _vdot_chunked(v, At)
+    assert abs((lhs - rhs).item()) <= 1e-5 * abs(lhs.item())
+    del At, Av
+    scale, lam = 3.0, 0.05
+    gr = b.gradient(g, o, rr, dd, v, x, scale, lam)
+    comp = b.backproject(g, o, rr, dd, b.project(g, o, rr, dd, v, subtract=x), ctf_power=1, scale=scale)
+    comp += lam * v
+    diff = gr - comp
+    del gr
+    err = _vdot_chunked(diff, diff).real.sqrt()
+    ref = _vdot_chunked(comp, comp).real.sqrt()
+    assert (err / ref).item() <= 1e-5
+
+
 # ---------------------------------------------------------------------------
 # Full size: 256^3 volume, a batch of 1024 images of 256 x 256 -- the
 # configuration the benchmark times, in the same launch configuration.
