@@ -74,7 +74,8 @@ hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64
 // first: the sum starts with this probe pair (diag is written, not read)
 hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,
                             hipStream_t st);
-// z = Rademacher probe pair (as launch_rademacher_pair), hz = lam z
+// z = Rademacher probe pair (as launch_rademacher_pair), hz = lam z; z and hz
+// 16-byte aligned, nvox even
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st);
 hipError_t launch_shell_sums(const float2 *u, const float2 *v, int M, double *out, hipStream_t st);

@@ -405,17 +405,14 @@ hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64
 
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st) {
-    if (nvox % 2 == 0 && aligned(z, 16) && aligned(hz, 16)) {
-        // one wave per 8192 voxels, four waves per block
-        int64_t blocks = ((nvox + 8191) / 8192 + kBlock / 64 - 1) / (kBlock / 64);
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(probe_init_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz,
-                           nvox, seed, pa, pb, has_b, lam);
-        return hipGetLastError();
-    }
-    hipError_t e = launch_rademacher_pair(z, nvox, seed, pa, pb, has_b, st);
-    if (e != hipSuccess) return e;
-    return launch_scaled_copy(hz, z, lam, nvox, nullptr, st);
+    // z and hz live in the (256-byte aligned) workspace and nvox = M^3 is even
+    if (nvox % 2 != 0 || !aligned(z, 16) || !aligned(hz, 16)) return hipErrorInvalidValue;
+    // one wave per 8192 voxels, four waves per block
+    int64_t blocks = ((nvox + 8191) / 8192 + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(probe_init_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz, nvox,
+                       seed, pa, pb, has_b, lam);
+    return hipGetLastError();
 }
 
 hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,

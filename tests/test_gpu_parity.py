@@ -226,8 +226,9 @@ def test_feature_sums_parity(b):
     assert rel(acc.real, f2) <= 1e-5
 
 
-def test_precond_step_parity(b):
-    n = 36 ** 3 + 5
+@pytest.mark.parametrize("n", [36 ** 3, 36 ** 3 + 5], ids=["pairs", "odd"])
+def test_precond_step_parity(b, n):
+    # an even count takes the two-voxel kernel, an odd one the one-voxel kernel
     g0 = np.random.default_rng(3)
     v = synth.random_complex(n, 1).astype(np.complex64)
     gr = synth.random_complex(n, 2).astype(np.complex64)
@@ -252,6 +253,43 @@ def test_precond_step_parity(b):
     vo2, st2 = b.precond_sgd_step(vd, gd, None, None, None, 0, beta, alpha, eta)
     wv2, wgn2 = oracle.precond_step(v, gr, None, eta)
     assert rel(vo2.cpu().numpy(), wv2) <= 1e-6 and st2[0].item() == pytest.approx(wgn2, rel=1e-6)
+
+
+def test_unaligned_buffers_take_the_one_voxel_kernels(b):
+    """Buffers that are 8- but not 16-byte aligned: the step and the
+    Hutchinson product give the same results as with aligned buffers."""
+    nv = 36 ** 3
+    v = torch.from_numpy(synth.random_complex(nv, 4).astype(np.complex64)).cuda()
+    g = torch.from_numpy(synth.random_complex(nv, 5).astype(np.complex64)).cuda()
+    D = torch.rand(nv, device="cuda") + 0.5
+    Da = torch.rand(nv, device="cuda")
+    z = torch.rand(nv, device="cuda")
+    # offset copies: element 1 of a buffer one element longer
+    def off(t):
+        big = torch.empty(t.numel() + 1, dtype=t.dtype, device="cuda")
+        big[1:] = t
+        return big[1:]
+    vu, gu, Du, Dau, zu = off(v), off(g), off(D), off(Da), off(z)
+    assert vu.data_ptr() % 16 == 8
+    vo, st = b.precond_sgd_step(v, g, D, Da, z, 3, 0.9, 0.2, 0.5)
+    vou = off(torch.empty_like(v))
+    _, stu = b.precond_sgd_step(vu, gu, Du, Dau, zu, 3, 0.9, 0.2, 0.5, v_out=vou)
+    assert torch.equal(vo, vou) and torch.equal(D, Du) and torch.equal(Da, Dau)
+    assert stu.cpu().numpy() == pytest.approx(st.cpu().numpy(), rel=1e-12)
+    # the Hutchinson diagonal into a 4-byte-offset output, the gradient into an
+    # 8-byte-offset one
+    grid_o, opt_o, P, vol, img = make_case(M=36, n=40, seed=24)
+    gg, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, vd, xd = to_dev(P.rot, P.defocus, vol, img)
+    d1 = b.hutchinson_diag(gg, o, rot, df, 3, seed=9, scale=1.5, lam=0.1)
+    d2 = off(torch.empty(nv, device="cuda"))
+    assert d2.data_ptr() % 8 == 4
+    b.hutchinson_diag(gg, o, rot, df, 3, seed=9, scale=1.5, lam=0.1, diag_out=d2)
+    assert rel(d2.cpu().numpy(), d1.reshape(-1).cpu().numpy()) <= 1e-6
+    g1 = b.gradient(gg, o, rot, df, vd, xd, 2.0, 0.1)
+    g2 = off(torch.empty(nv, dtype=torch.complex64, device="cuda")).reshape(36, 36, 36)
+    b.gradient(gg, o, rot, df, vd, xd, 2.0, 0.1, grad_out=g2)
+    assert rel(g2.cpu().numpy(), g1.cpu().numpy()) <= 1e-6
 
 
 def test_sub_batches_beyond_2048_images(b):
