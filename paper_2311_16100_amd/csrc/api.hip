@@ -316,7 +316,7 @@ int csg_threshold_alpha(const csg_grid *grid, const csg_optics *optics, const cs
     // Shell counts: round(|k|) == R  <=>  R^2 - R + 1 <= |k|^2 <= R^2 + R
     // (|k|^2 is an integer and |k| is never exactly R + 1/2).
     const int64_t lo = (int64_t)R * R - R + 1, hi = (int64_t)R * R + R;
-    const int M = g.M, h = g.half;
+    const int h = g.half;
     int64_t px = 0, pv = 0;
     for (int y = -h; y < h; ++y)
         for (int x = -h; x < h; ++x) {

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
     __syncthreads();
     // bucket starts (largest key first), then per-wave cursors inside each
     // bucket (in place of the counts)
-    if (threadIdx.x <= chunk) {
+    if ((int)threadIdx.x <= chunk) {
         const int k = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < kPlanWaves; ++w) tot += hist[w][k];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
         }
     }
     __syncthreads();
-    if (threadIdx.x <= chunk) {
+    if ((int)threadIdx.x <= chunk) {
         const int k = threadIdx.x;
         int run = base[k];
         for (int w = 0; w < kPlanWaves; ++w) {
