@@ -13,7 +13,9 @@ image read 8P, gather 8U, scatter read-modify-write 16U; P disk pixels, U
 distinct voxels an image's stencils touch) over its average launch duration
 from HIP events recorded around each launch on its stream; `traffic` is the
 measured HBM rate of the same launches from the committed counter summary,
-when it was taken on the current kernel sources.
+when it was taken on the current kernel sources.  `fwd_adj_roofline` is the
+same figure for the separate forward and adjoint kernels together (16P + 24U
+bytes per image over the sum of their average durations).
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload.
 """
@@ -144,11 +146,16 @@ def main():
     y = torch.empty_like(x_b)
     acc = torch.zeros_like(v_true)
     ws_bp = B.alloc_workspace(grid, Bsz, B.CSG_WS_BACKPROJECT, dev)
+    B.timing_enable(True)
+    for k in B.KERNELS:
+        B.timing_read(k)
     for _ in range(args.steps):
         timed("project", lambda: B.project(grid, optics, rot_b, df_b, v_true, out=y, workspace=run.ws_proj))
         timed("backproject", lambda: B.backproject(grid, optics, rot_b, df_b, x_b, ctf_power=1, accum=acc,
                                                    deterministic=args.deterministic, workspace=ws_bp))
     torch.cuda.synchronize()
+    B.timing_enable(False)
+    kern_fa = {k: B.timing_read(k) for k in ("project", "backproject")}
     ms = {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in calls.items()}
     fwd_adj = Bsz / ((ms["project"] + ms["backproject"]) * 1e-3)
 
@@ -178,6 +185,18 @@ def main():
                 "kernel": "brick_kernel<%s>" % dominant, "kernel_avg_ms": round(avg_ms, 4), "launches": launches,
                 "bytes_per_image": round(per_image[dominant]), "P": P, "U": round(U),
                 "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items()}}
+    # the separate forward + adjoint pair: disk-pixel write 8P and gather 8U
+    # (project), image read 8P and read-modify-write 16U (backproject), over
+    # the two kernels' average durations (the zero fill outside the disk is a
+    # separate kernel and not counted)
+    fwd_adj_roofline = None
+    if all(kern_fa[k][1] > 0 for k in kern_fa):
+        pair_ms = sum(kern_fa[k][0] / kern_fa[k][1] for k in kern_fa)
+        fa = (16 * P + 24 * U) * Bsz / (pair_ms * 1e-3) / 1e9
+        fwd_adj_roofline = {"bound": "hbm", "achieved": round(fa, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(fa / HBM_PEAK_GBS, 4),
+                            "kernels_avg_ms": {k: round(kern_fa[k][0] / kern_fa[k][1], 4) for k in kern_fa},
+                            "bytes_per_image": round(16 * P + 24 * U)}
     tr = traffic_record(dominant, Bsz, M)
     if tr:
         # measured HBM bytes of one launch over the same average duration (GB/s)
@@ -215,6 +234,7 @@ def main():
                                "trilinear, CTF 300kV/Cs2.7/A0.1, defocus 1-3um" % (Bsz, M, M, M, W.n_blobs, N),
                    "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic)},
         "fwd_adj_images_per_s": round(fwd_adj, 1),
+        "fwd_adj_roofline": fwd_adj_roofline,
         "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
