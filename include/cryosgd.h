@@ -102,10 +102,17 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
  *   img        device complex [n][M][M] (pixels outside the disk ignored)
  *   vol_accum  device complex [M^3], accumulated into
  *   deterministic 0: fast scatter (floating-point summation order varies
- *                 between runs); 1: each voxel sums its contributions in a
- *                 fixed order (bitwise reproducible, slower).
+ *                 between runs); 1: bitwise reproducible.  On trilinear grids
+ *                 every contribution is rounded to a multiple of 2^-e
+ *                 (64-bit fixed point, with 2^e the largest power of two for
+ *                 which 32 n |scale| max(|re| + |im|) of img stays below 2^61)
+ *                 and the integers are summed exactly, so the order of
+ *                 summation cannot matter; the rounding is far below float
+ *                 precision.  A non-finite img value makes every voxel NaN.
+ *                 Nearest-neighbour grids sum each voxel in a fixed order.
  *   workspace  device scratch of at least csg_workspace_bytes(grid, n,
- *              CSG_WS_BACKPROJECT) bytes (may be NULL when that is 0). */
+ *              CSG_WS_BACKPROJECT or CSG_WS_BACKPROJECT_DETERMINISTIC) bytes
+ *              (may be NULL when that is 0). */
 int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
                     const float *img, int32_t ctf_power, float scale, float *vol_accum,
                     int32_t deterministic, void *workspace, size_t workspace_bytes, void *stream);
@@ -120,7 +127,10 @@ int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_po
  *   vol       device complex [M^3];  x device complex [n][M][M]
  *   grad_out  device complex [M^3], overwritten (must not alias vol)
  *   loss_out  device double scalar or NULL, overwritten with f(v).
- *   deterministic as in csg_backproject.
+ *   deterministic as in csg_backproject (for the fixed-point bound, img is
+ *             replaced by the largest |re| + |im| of vol plus that of x); the
+ *             gradient is bitwise reproducible, the loss is a double sum
+ *             whose order may vary.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_GRADIENT or
  *             CSG_WS_GRADIENT_DETERMINISTIC). */
 int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
@@ -247,17 +257,23 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
 
 /* Workspace sizes (bytes) for a batch of n images:
  *   CSG_WS_PROJECT                 csg_project
- *   CSG_WS_BACKPROJECT             csg_backproject (either mode)
+ *   CSG_WS_BACKPROJECT             csg_backproject, deterministic = 0
+ *   CSG_WS_BACKPROJECT_DETERMINISTIC  csg_backproject, deterministic = 1
+ *                                  (trilinear grids: adds the 64-bit
+ *                                  fixed-point volume, 16 M^3 bytes)
  *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: two complex volumes
  *   CSG_WS_GRADIENT                csg_gradient / csg_hvp, deterministic = 0
  *   CSG_WS_GRADIENT_DETERMINISTIC  csg_gradient / csg_hvp, deterministic = 1
- *                                  (adds one complex image per batch image)
+ *                                  (trilinear grids: the fixed-point volume;
+ *                                  nearest neighbour: one complex image per
+ *                                  batch image)
  * Workspaces must be 256-byte aligned.  Returns 0 for an invalid grid. */
 #define CSG_WS_BACKPROJECT 0
 #define CSG_WS_HUTCHINSON 1
 #define CSG_WS_GRADIENT 2
 #define CSG_WS_GRADIENT_DETERMINISTIC 3
 #define CSG_WS_PROJECT 4
+#define CSG_WS_BACKPROJECT_DETERMINISTIC 5
 size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
 
 /* Per-shell sums of two volumes over the Fourier shells round(|k|) = s,

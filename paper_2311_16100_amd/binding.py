@@ -25,6 +25,7 @@ CSG_WS_HUTCHINSON = 1
 CSG_WS_GRADIENT = 2
 CSG_WS_GRADIENT_DETERMINISTIC = 3
 CSG_WS_PROJECT = 4
+CSG_WS_BACKPROJECT_DETERMINISTIC = 5
 
 
 class CsgError(RuntimeError):
@@ -217,8 +218,9 @@ def backproject(grid: Grid, optics: Optics, rot, defocus, img, ctf_power: int = 
     p = _poses(rot, defocus, shift)
     if accum is None:
         accum = torch.zeros((M, M, M), dtype=torch.complex64, device=img.device)
-    if workspace is None and not deterministic:
-        workspace = alloc_workspace(grid, p.n, CSG_WS_BACKPROJECT, img.device)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_BACKPROJECT_DETERMINISTIC if deterministic else CSG_WS_BACKPROJECT,
+                                    img.device)
     g, o = grid.c(), optics.c()
     wp, wn = _ws(workspace)
     _check(lib().csg_backproject(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),

@@ -95,6 +95,18 @@ int need_workspace(void *ws, size_t have, size_t need, const char *who) {
     return CSG_OK;
 }
 
+// The fixed-point scratch of the deterministic adjoint inside a workspace of
+// kind CSG_WS_*_DETERMINISTIC: the input bounds in the scalar area, then the
+// brick tables, then the fixed-point volume.
+csg::FxBuf fx_buffers(void *ws, int M, int64_t n, void **brick_ws) {
+    char *w = (char *)ws;
+    *brick_ws = w + kScalarBytes;
+    csg::FxBuf fb;
+    fb.maxbits = (unsigned *)(w + 16);  // after the two double scalars
+    fb.fx = (unsigned long long *)(w + kScalarBytes + csg::brick_workspace_bytes(M, n));
+    return fb;
+}
+
 }  // namespace
 
 extern "C" {
@@ -106,11 +118,18 @@ size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
     const int M = grid->M;
     const size_t vol = (size_t)M * M * M * 8u;
     const size_t bricks = csg::brick_workspace_bytes(M, n);
+    // the deterministic adjoint: the fixed-point volume (two 64-bit integers
+    // per voxel) beside the brick tables; the nearest-neighbour grids use the
+    // owner-computes kernel instead (plus one image per batch image for the
+    // gradient and the HVP)
+    const bool trilinear = grid->interp != 0;
+    const size_t fixed = kScalarBytes + bricks + 2 * vol;
     switch (which) {
         case CSG_WS_PROJECT: return bricks;
         case CSG_WS_BACKPROJECT: return bricks;
+        case CSG_WS_BACKPROJECT_DETERMINISTIC: return trilinear ? fixed : 0;
         case CSG_WS_GRADIENT: return kScalarBytes + bricks;
-        case CSG_WS_GRADIENT_DETERMINISTIC: return kScalarBytes + image_bytes(M, n);
+        case CSG_WS_GRADIENT_DETERMINISTIC: return trilinear ? fixed : kScalarBytes + image_bytes(M, n);
         case CSG_WS_HUTCHINSON: return kScalarBytes + 2 * vol + bricks;
         default: return 0;
     }
@@ -147,9 +166,18 @@ int csg_backproject(const csg_grid *grid, const csg_optics *optics, const csg_po
     if (poses->n == 0) return CSG_OK;
     if (!img || !vol_accum) return fail(CSG_EINVAL, "csg_backproject: img and vol_accum must be non-NULL");
     hipStream_t st = (hipStream_t)stream;
-    if (deterministic) {
+    if (deterministic && g.interp == 0) {
         CSG_TRY(csg::launch_backproject_owner(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
                                               (const float2 *)img, ctf_power, scale, (float2 *)vol_accum, st),
+                "csg_backproject");
+    } else if (deterministic) {
+        const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT_DETERMINISTIC);
+        if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_backproject"))) return rc;
+        void *bws;
+        const csg::FxBuf fb = fx_buffers(workspace, g.M, poses->n, &bws);
+        CSG_TRY(csg::launch_brick_backproject_fx(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                                 (const float2 *)img, ctf_power, scale, (float2 *)vol_accum, fb, bws,
+                                                 st),
                 "csg_backproject");
     } else {
         const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_BACKPROJECT);
@@ -184,6 +212,13 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
             CSG_TRY(csg::launch_brick_gradient(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
                                                (const float2 *)vol, (const float2 *)x, scale, (float2 *)grad_out, sc,
                                                (char *)workspace + kScalarBytes, st),
+                    "csg_gradient");
+        } else if (g.interp != 0) {
+            void *bws;
+            const csg::FxBuf fb = fx_buffers(workspace, g.M, poses->n, &bws);
+            CSG_TRY(csg::launch_brick_gradient_fx(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                                  (const float2 *)vol, (const float2 *)x, scale, (float2 *)grad_out,
+                                                  sc, fb, bws, st),
                     "csg_gradient");
         } else {
             float2 *resid = (float2 *)((char *)workspace + kScalarBytes);
@@ -220,6 +255,12 @@ int csg_hvp(const csg_grid *grid, const csg_optics *optics, const csg_poses *pos
     if (!deterministic) {
         CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, scale,
                                       (float2 *)hz_out, (char *)workspace + kScalarBytes, st),
+                "csg_hvp");
+    } else if (g.interp != 0) {
+        void *bws;
+        const csg::FxBuf fb = fx_buffers(workspace, g.M, poses->n, &bws);
+        CSG_TRY(csg::launch_brick_hvp_fx(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)z, scale,
+                                         (float2 *)hz_out, fb, bws, st),
                 "csg_hvp");
     } else {
         float2 *img = (float2 *)((char *)workspace + kScalarBytes);

@@ -119,6 +119,11 @@ struct BrickArgs {
     const int2 *items;  // work items, heaviest first: (brick | chunk << 20, images of the brick)
     const int *n_items; // number of work items
     int *next_item;     // work counter (zero at launch)
+    // deterministic adjoint (fixed point, see FxScale): the 64-bit volume
+    // [M^3][re, im], the input bounds and the images of the whole launch
+    unsigned long long *fx;
+    const unsigned *fx_max;
+    int64_t n_total;
 };
 
 __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
@@ -409,8 +414,14 @@ struct PackedScale {
 // waves per SIMD the register allocation must allow: three blocks per CU
 // where the LDS footprint permits it (project, backproject, features,
 // squared weights), two for gradient and HVP
-template <int MODE, bool SHIFT>
+// FX: the deterministic adjoint (backproject, gradient, HVP): contributions
+// are accumulated as 64-bit fixed-point integers (see FxScale), in LDS and in
+// the fixed-point volume a.fx, so the result does not depend on the order in
+// which blocks and lanes add them.
+template <int MODE, bool SHIFT, bool FX>
 __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
+    static_assert(!FX || MODE == kBBackproject || MODE == kBGradient || MODE == kBHvp,
+                  "fixed-point accumulation is built for backproject, gradient and HVP");
     constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || is_hvp(MODE);
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
@@ -428,6 +439,10 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN : 1];
     // the packed accumulator shares the storage of acc_re
     unsigned long long *const acc_pk = reinterpret_cast<unsigned long long *>(acc_re);
+    // so do the fixed-point accumulators of the deterministic mode (zero bits
+    // are zero in both)
+    unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
+    unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
     __shared__ float s_wmax[kBT / 64];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
@@ -447,6 +462,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     const int M = g.M;
     const int total = *a.n_items;
     double lsum = 0.0;
+    double fxS = 1.0;
+    if (FX) fxS = fx_scale(a.fx_max, a.scale, a.n_total).S;
 
     // work items are taken from the planned list (heaviest first) until it
     // is exhausted
@@ -786,6 +803,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                             atomicAdd(&acc_re[li], (double)(w * w * val.x));
                                         } else if (PK_ALWAYS) {
                                             atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
+                                        } else if (FX) {
+                                            atomicAdd(&acc_qre[li], fx_quant(w * val.x, fxS));
+                                            atomicAdd(&acc_qim[li], fx_quant(w * val.y, fxS));
                                         } else {
                                             atomicAdd(&acc_re[li], (double)(w * val.x));
                                             atomicAdd(&acc_im[li], (double)(w * val.y));
@@ -813,6 +833,12 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
                 const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
                 const int li = (tz * XR + ty) * XR + tx;
+                if (FX) {
+                    const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
+                    if (qr) atomicAdd(&a.fx[2 * gi], qr);
+                    if (qi) atomicAdd(&a.fx[2 * gi + 1], qi);
+                    continue;
+                }
                 if (PK_ALWAYS) {
                     float re, im;
                     pk.unpack(acc_pk[li], re, im);
@@ -891,20 +917,21 @@ size_t brick_workspace_bytes(int M, int64_t n) {
 
 // Resident blocks of one brick-kernel mode on the current device (one wave
 // of blocks that then fetch work items until the list is exhausted).
-template <int MODE>
+template <int MODE, bool FX>
 static int resident_blocks() {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, brick_kernel<MODE, false>, kBT, 0) != hipSuccess || per <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, brick_kernel<MODE, false, FX>, kBT, 0) != hipSuccess || per <= 0)
         per = 1;
     return cus * per;
 }
 
-template <int MODE>
+template <int MODE, bool FX = false>
 static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                  const float2 *src, const float2 *img, float2 *out, float2 *accum, double *loss,
-                                 float scale, int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr) {
+                                 float scale, int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr,
+                                 const FxBuf *fb = nullptr) {
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
@@ -920,7 +947,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     const int64_t img_stride = (int64_t)M * M;
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
-    const int grid = (int)(resident_blocks<MODE>() < max_items ? resident_blocks<MODE>() : max_items);
+    const int grid = (int)(resident_blocks<MODE, FX>() < max_items ? resident_blocks<MODE, FX>() : max_items);
     for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
         const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
         const int stride = (int)ns;
@@ -954,13 +981,18 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.items = items;
         a.n_items = scalars;
         a.next_item = scalars + 1;
+        if (FX) {
+            a.fx = fb->fx;
+            a.fx_max = fb->maxbits;
+            a.n_total = n;
+        }
         // the probe HVP is timed with the HVP
         constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
         hipEvent_t t0 = timing_begin(TMODE, st);
         if (shift)
-            hipLaunchKernelGGL((brick_kernel<MODE, true>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+            hipLaunchKernelGGL((brick_kernel<MODE, true, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         else
-            hipLaunchKernelGGL((brick_kernel<MODE, false>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+            hipLaunchKernelGGL((brick_kernel<MODE, false, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         e = hipGetLastError();
         timing_end(TMODE, t0, st);
         if (e != hipSuccess) return e;
@@ -1026,6 +1058,50 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
         return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws,
                                           st);
     return run_brick_mode<kBHvp>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
+}
+
+// Deterministic adjoint: input bounds and a zeroed fixed-point volume, the
+// fixed-point brick kernel, then one conversion pass that adds the volume to
+// the float target.
+hipError_t launch_brick_backproject_fx(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                       int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                       const FxBuf &fb, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
+    const int64_t nv = (int64_t)g.M * g.M * g.M;
+    hipError_t e = launch_fx_prep(img, n * g.M * g.M, nullptr, 0, fb.maxbits, fb.fx, nv, st);
+    if (e != hipSuccess) return e;
+    e = run_brick_mode<kBBackproject, true>(g, rot, defocus, shift, n, nullptr, img, nullptr, accum, nullptr, scale,
+                                            ctf_power, ws, st, nullptr, &fb);
+    if (e != hipSuccess) return e;
+    return launch_fx_finish(accum, fb.fx, nv, fb.maxbits, scale, n, st);
+}
+
+hipError_t launch_brick_gradient_fx(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *vol, const float2 *x, float scale, float2 *accum,
+                                    double *loss, const FxBuf &fb, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;
+    const int64_t nv = (int64_t)g.M * g.M * g.M;
+    hipError_t e = launch_fx_prep(vol, nv, x, n * g.M * g.M, fb.maxbits, fb.fx, nv, st);
+    if (e != hipSuccess) return e;
+    e = run_brick_mode<kBGradient, true>(g, rot, defocus, shift, n, vol, x, nullptr, accum, loss, scale, 1, ws, st,
+                                         nullptr, &fb);
+    if (e != hipSuccess) return e;
+    return launch_fx_finish(accum, fb.fx, nv, fb.maxbits, scale, n, st);
+}
+
+hipError_t launch_brick_hvp_fx(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
+                               float scale, float2 *accum, const FxBuf &fb, void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;
+    const int64_t nv = (int64_t)g.M * g.M * g.M;
+    hipError_t e = launch_fx_prep(z, nv, nullptr, 0, fb.maxbits, fb.fx, nv, st);
+    if (e != hipSuccess) return e;
+    e = run_brick_mode<kBHvp, true>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st,
+                                    nullptr, &fb);
+    if (e != hipSuccess) return e;
+    return launch_fx_finish(accum, fb.fx, nv, fb.maxbits, scale, n, st);
 }
 
 }  // namespace csg

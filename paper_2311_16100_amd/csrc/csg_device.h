@@ -189,6 +189,47 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* >= 16 */) {
     return t;
 }
 
+// Fixed-point scale of the deterministic adjoint.  Every contribution w val to
+// a component of a voxel is rounded to an integer multiple of 1/S and the
+// multiples are summed as 64-bit integers: exact, hence independent of the
+// order of summation.  The bound: w <= 1 and |val| <= V, where V = |scale| (m0
+// + m1) with m0, m1 the largest |re| + |im| of the operator's inputs (|C| <= 1,
+// |T| = 1 and the trilinear weights of a gathered value sum to 1).  A voxel
+// receives from one image only the lattice pixels inside its 2x2x2
+// neighbourhood (at most 16; 32 is used as margin), so every partial sum over
+// n images stays below 32 n V.  S = 2^e is the largest power of two with
+// 32 n V S <= 2^61 (no 64-bit overflow) and V S <= 2^50 (fx_quant is exact).
+// ok = 0 when an input is not finite.
+struct FxScale {
+    double S, invS;
+    int ok;
+};
+__device__ __forceinline__ FxScale fx_scale(const unsigned *maxbits, float scale, int64_t n) {
+    const double m = (double)__uint_as_float(maxbits[0]) + (double)__uint_as_float(maxbits[1]);
+    const double V = fabs((double)scale) * m * (1.0 + 0x1p-20);
+    FxScale f;
+    f.S = 1.0;
+    f.invS = 1.0;
+    f.ok = isfinite(V) ? 1 : 0;
+    if (f.ok && V > 0.0) {
+        int kt, kv;
+        (void)frexp(32.0 * (double)n * V, &kt);  // 32 n V < 2^kt
+        (void)frexp(V, &kv);
+        const int e = min(61 - kt, 50 - kv);
+        f.S = ldexp(1.0, e);
+        f.invS = ldexp(1.0, -e);
+    }
+    return f;
+}
+
+// round(x S) as a two's-complement 64-bit integer, for |x S| <= 2^50: adding
+// 1.5 2^52 rounds the product to an integer (the spacing of doubles there is
+// 1), and the sum's bit pattern is that of 1.5 2^52 plus the integer.
+__device__ __forceinline__ unsigned long long fx_quant(float x, double S) {
+    const double q = fma((double)x, S, 0x1.8p52);
+    return (unsigned long long)__double_as_longlong(q) - 0x4338000000000000ull;
+}
+
 // Map a linear block id to a logical one so that the blocks placed on one XCD
 // (ids congruent modulo 8) take a contiguous range of logical ids; returns -1
 // for padding blocks.  nb_pad is the grid size rounded up to a multiple of 8.

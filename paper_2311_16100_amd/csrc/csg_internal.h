@@ -40,6 +40,21 @@ hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *de
 // allows the packed fixed-point accumulator
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
                             float scale, float2 *accum, void *ws, hipStream_t st, bool probe = false);
+// the deterministic adjoint (fixed point; trilinear grids): scratch of
+// 16 M^3 bytes (the 64-bit fixed-point volume, 16-byte aligned) and two words
+// (input bounds), both in device memory
+struct FxBuf {
+    unsigned long long *fx;
+    unsigned *maxbits;
+};
+hipError_t launch_brick_backproject_fx(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                       int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
+                                       const FxBuf &fb, void *ws, hipStream_t st);
+hipError_t launch_brick_gradient_fx(const Geom &g, const float *rot, const float *defocus, const float *shift,
+                                    int64_t n, const float2 *vol, const float2 *x, float scale, float2 *accum,
+                                    double *loss, const FxBuf &fb, void *ws, hipStream_t st);
+hipError_t launch_brick_hvp_fx(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
+                               float scale, float2 *accum, const FxBuf &fb, void *ws, hipStream_t st);
 
 // pixel-parallel kernels (pixel_kernels.hip)
 hipError_t launch_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
@@ -78,6 +93,12 @@ hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int6
 // 16-byte aligned, nvox even
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st);
+// fixed-point adjoint: bounds of a (and b, which may be NULL) into
+// maxbits[0..1] and a zeroed fx[0..2 nvox); then accum += fx / S
+hipError_t launch_fx_prep(const float2 *a, int64_t na, const float2 *b, int64_t nb, unsigned *maxbits,
+                          unsigned long long *fx, int64_t nvox, hipStream_t st);
+hipError_t launch_fx_finish(float2 *out, const unsigned long long *fx, int64_t nvox, const unsigned *maxbits,
+                            float scale, int64_t n, hipStream_t st);
 hipError_t launch_shell_sums(const float2 *u, const float2 *v, int M, double *out, hipStream_t st);
 hipError_t launch_alpha(const Geom &g, const float *defocus, int64_t n, int k2, double ratio, float lam,
                         double *alpha_out, hipStream_t st);

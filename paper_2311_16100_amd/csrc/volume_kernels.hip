@@ -451,4 +451,98 @@ hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, f
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic adjoint (fixed point, see FxScale)
+// ---------------------------------------------------------------------------
+
+// Largest |re| + |im| over n complex values, as float bits with the sign
+// cleared: for non-negative floats the bit patterns order like the values,
+// and a NaN orders above every finite value and infinity, so it is not lost.
+__device__ __forceinline__ unsigned absmax_bits(const float2 *p, int64_t n, int64_t tid, int64_t stride) {
+    unsigned m = 0u;
+    if (((uintptr_t)p & 15u) == 0) {
+        const float4 *q = (const float4 *)p;
+        const int64_t np = n / 2;
+        for (int64_t k = tid; k < np; k += stride) {
+            const float4 v = q[k];
+            m = max(m, __float_as_uint(fabsf(v.x) + fabsf(v.y)) & 0x7fffffffu);
+            m = max(m, __float_as_uint(fabsf(v.z) + fabsf(v.w)) & 0x7fffffffu);
+        }
+        if ((n & 1) && tid == 0) {
+            const float2 v = p[n - 1];
+            m = max(m, __float_as_uint(fabsf(v.x) + fabsf(v.y)) & 0x7fffffffu);
+        }
+    } else {
+        for (int64_t k = tid; k < n; k += stride) {
+            const float2 v = p[k];
+            m = max(m, __float_as_uint(fabsf(v.x) + fabsf(v.y)) & 0x7fffffffu);
+        }
+    }
+    return m;
+}
+
+__device__ __forceinline__ void block_max_to(unsigned m, unsigned *lds /* >= 16 */, unsigned *dst) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = 0u;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = max(t, lds[i]);
+        if (t) atomicMax(dst, t);
+    }
+    __syncthreads();
+}
+
+// maxbits[0] = bound of a[0..na), maxbits[1] = bound of b[0..nb) (b may be
+// NULL), both zero on entry; the fixed-point volume fx[0..nvox) is zeroed.
+__global__ __launch_bounds__(kBlock) void fx_prep_kernel(const float2 *a, int64_t na, const float2 *b, int64_t nb,
+                                                          unsigned *maxbits, ulonglong2 *fx, int64_t nvox) {
+    __shared__ unsigned red[16];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = tid; k < nvox; k += stride) fx[k] = make_ulonglong2(0ull, 0ull);
+    block_max_to(absmax_bits(a, na, tid, stride), red, maxbits);
+    if (b) block_max_to(absmax_bits(b, nb, tid, stride), red, maxbits + 1);
+}
+
+// out += fx / S per component, in double precision with one rounding to
+// float; every voxel becomes NaN when an input was not finite.
+__global__ __launch_bounds__(kBlock) void fx_finish_kernel(float2 *__restrict__ out,
+                                                            const ulonglong2 *__restrict__ fx, int64_t nvox,
+                                                            const unsigned *maxbits, float scale, int64_t n) {
+    const FxScale f = fx_scale(maxbits, scale, n);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
+        const ulonglong2 q = fx[k];
+        float2 o = out[k];
+        if (f.ok) {
+            o.x = (float)fma((double)(long long)q.x, f.invS, (double)o.x);
+            o.y = (float)fma((double)(long long)q.y, f.invS, (double)o.y);
+        } else {
+            o = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        }
+        out[k] = o;
+    }
+}
+
+hipError_t launch_fx_prep(const float2 *a, int64_t na, const float2 *b, int64_t nb, unsigned *maxbits,
+                          unsigned long long *fx, int64_t nvox, hipStream_t st) {
+    hipError_t e = launch_fill_f32((float *)maxbits, 2, 0.0f, st);  // zero bits
+    if (e != hipSuccess) return e;
+    int64_t units = na > nb ? na : nb;
+    if (nvox > units) units = nvox;
+    hipLaunchKernelGGL(fx_prep_kernel, dim3(reduce_blocks(units)), dim3(kBlock), 0, st, a, na, b, nb, maxbits,
+                       (ulonglong2 *)fx, nvox);
+    return hipGetLastError();
+}
+
+hipError_t launch_fx_finish(float2 *out, const unsigned long long *fx, int64_t nvox, const unsigned *maxbits,
+                            float scale, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(fx_finish_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, out, (const ulonglong2 *)fx,
+                       nvox, maxbits, scale, n);
+    return hipGetLastError();
+}
+
 }  // namespace csg

@@ -43,7 +43,14 @@ def test_workspace_sizes(b):
     g = b.Grid(256)
     vol = 256 ** 3 * 8
     assert b.workspace_bytes(g, 1024, b.CSG_WS_HUTCHINSON) >= 2 * vol
-    assert b.workspace_bytes(g, 1024, b.CSG_WS_GRADIENT_DETERMINISTIC) >= 1024 * 256 * 256 * 8
+    # deterministic adjoint: the 64-bit fixed-point volume on trilinear
+    # grids, one image per batch image (owner-computes kernel) on
+    # nearest-neighbour grids
+    for kind in (b.CSG_WS_GRADIENT_DETERMINISTIC, b.CSG_WS_BACKPROJECT_DETERMINISTIC):
+        assert b.workspace_bytes(g, 1024, kind) >= 2 * vol
+    nn = b.Grid(256, interp=0)
+    assert b.workspace_bytes(nn, 1024, b.CSG_WS_GRADIENT_DETERMINISTIC) >= 1024 * 256 * 256 * 8
+    assert b.workspace_bytes(nn, 1024, b.CSG_WS_BACKPROJECT_DETERMINISTIC) == 0
     assert b.workspace_bytes(g, 1024, b.CSG_WS_GRADIENT) > 0
     assert b.workspace_bytes(b.Grid(7), 1, b.CSG_WS_HUTCHINSON) == 0
 
