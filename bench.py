@@ -197,6 +197,12 @@ def main():
                             "frac": round(fa / HBM_PEAK_GBS, 4),
                             "kernels_avg_ms": {k: round(kern_fa[k][0] / kern_fa[k][1], 4) for k in kern_fa},
                             "bytes_per_image": round(16 * P + 24 * U)}
+    # the same bytes over the whole entry point's event-timed duration (for
+    # the gradient: the volume copy lam v, the image-bound pass of the
+    # fixed-point accumulator, cull, plan and the kernel)
+    if dominant in ms:
+        roofline["call_ms"] = round(ms[dominant], 4)
+        roofline["call_frac"] = round(per_image[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     tr = traffic_record(dominant, Bsz, M)
     if tr:
         # measured HBM bytes of one launch over the same average duration (GB/s)

@@ -101,14 +101,17 @@ int csg_project(const csg_grid *grid, const csg_optics *optics, const csg_poses 
  *   vol_accum += scale * sum_i P_i^T T_i^* C_i^p img_i,  p = ctf_power in {0,1,2}.
  *   img        device complex [n][M][M] (pixels outside the disk ignored)
  *   vol_accum  device complex [M^3], accumulated into
- *   deterministic 0: fast scatter (floating-point summation order varies
- *                 between runs); 1: bitwise reproducible.  On trilinear grids
- *                 every contribution is rounded to a multiple of 2^-e
- *                 (64-bit fixed point, with 2^e the largest power of two for
- *                 which 32 n |scale| max(|re| + |im|) of img stays below 2^61)
- *                 and the integers are summed exactly, so the order of
- *                 summation cannot matter; the rounding is far below float
- *                 precision.  A non-finite img value makes every voxel NaN.
+ *   deterministic 0: fast scatter (the floating-point summation order
+ *                 varies between runs; within a work item the sums are exact
+ *                 64-bit fixed point bounded by the largest |re| + |im| of
+ *                 img, so a non-finite img value gives NaN).
+ *                 1: bitwise reproducible.  On trilinear grids every
+ *                 contribution is rounded to a multiple of 2^-e (64-bit fixed
+ *                 point, with 2^e the largest power of two for which
+ *                 32 n |scale| max(|re| + |im|) of img stays below 2^61) and
+ *                 the integers are summed exactly, so the order of summation
+ *                 cannot matter; the rounding is far below float precision.
+ *                 A non-finite img value makes every voxel NaN.
  *                 Nearest-neighbour grids sum each voxel in a fixed order.
  *   workspace  device scratch of at least csg_workspace_bytes(grid, n,
  *              CSG_WS_BACKPROJECT or CSG_WS_BACKPROJECT_DETERMINISTIC) bytes

@@ -408,6 +408,36 @@ struct PackedScale {
     }
 };
 
+// Per-item fixed-point scale of the 64-bit LDS accumulator of the fast
+// adjoint modes.  A contribution is w val with w <= 1 and |val| <= V; an item
+// holds at most 128 images and a voxel receives at most 32 pixels of one
+// image (see FxScale), so every LDS sum stays below 4096 V.  S = 2^e is the
+// largest power of two with 4096 V S <= 2^61 and V S <= 2^50: the sums are
+// exact, each contribution is rounded by at most 2^-50 V (about 2^-26 of a
+// float ulp of V), and the flush converts each voxel's sum to float once.
+#ifndef CSG_LDS_FIXED
+#define CSG_LDS_FIXED 1
+#endif
+// ok = 0 when an input is not finite (the flush then writes NaN).
+struct ItemScale {
+    double S = 1.0, invS = 1.0;
+    int ok = 1;
+    static __device__ __forceinline__ ItemScale make(double V) {
+        static_assert(CHUNK_ADJ <= 128, "the LDS bound assumes at most 128 images per item");
+        ItemScale q;
+        q.ok = isfinite(V) ? 1 : 0;
+        if (q.ok && V > 0.0) {
+            int kt, kv;
+            (void)frexp(4096.0 * V, &kt);
+            (void)frexp(V, &kv);
+            const int e = min(61 - kt, 50 - kv);
+            q.S = ldexp(1.0, e);
+            q.invS = ldexp(1.0, -e);
+        }
+        return q;
+    }
+};
+
 #ifndef CSG_BRICK_WAVES
 #define CSG_BRICK_WAVES 6
 #endif
@@ -434,6 +464,17 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // a per-item power-of-two scale.  Only the probe HVP packs; the other
     // adjoint modes accumulate in double.
     constexpr bool PK_ALWAYS = MODE == kBHvpProbe;
+    // 64-bit fixed-point LDS accumulators: the deterministic modes (one
+    // launch-wide scale, FxScale) and the fast modes other than the packed
+    // probe (a scale per work item, ItemScale; the flush adds floats as
+    // before).  On gfx950 the LDS 64-bit integer atomic add is cheaper than
+    // the double one.
+    constexpr bool QLDS = FX || (CSG_LDS_FIXED && SCATTER && !PK_ALWAYS);
+    constexpr bool QITEM = QLDS && !FX;
+    // the item bound needs the largest staged volume value (gradient, HVP)
+    // and the images' bound from the set-up pass (backproject, gradient)
+    constexpr bool STAGE_MAX = PK_ALWAYS || (QITEM && GATHER);
+    constexpr bool IMG_BOUND = QITEM && READS_IMG;
     __shared__ float2 vh[GATHER ? XN : 1];
     __shared__ double acc_re[SCATTER ? XN : 1];
     __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN : 1];
@@ -443,7 +484,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // are zero in both)
     unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
-    __shared__ float s_wmax[kBT / 64];
+    __shared__ unsigned s_wmax[kBT / 64];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -464,6 +505,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     double lsum = 0.0;
     double fxS = 1.0;
     if (FX) fxS = fx_scale(a.fx_max, a.scale, a.n_total).S;
+    float img_bound = 0.f;
+    if (IMG_BOUND) img_bound = __uint_as_float(a.fx_max[0]);
 
     // work items are taken from the planned list (heaviest first) until it
     // is exhausted
@@ -514,14 +557,17 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
             }
-            if (PK_ALWAYS) {
+            if (STAGE_MAX) {
                 // bound on |z| over the staged brick (|re| + |im| >= modulus),
-                // per wave; combined after the next barrier
-                float zb = 0.f;
+                // per wave; combined after the next barrier.  The maximum is
+                // taken over the float bits with the sign cleared, which
+                // order like the values and keep a NaN.
+                unsigned zb = 0u;
 #pragma unroll
-                for (int k = 0; k < HPT; ++k) zb = fmaxf(zb, fabsf(hv[k].x) + fabsf(hv[k].y));
+                for (int k = 0; k < HPT; ++k)
+                    zb = max(zb, __float_as_uint(fabsf(hv[k].x) + fabsf(hv[k].y)) & 0x7fffffffu);
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) zb = fmaxf(zb, __shfl_xor(zb, off, 64));
+                for (int off = 32; off >= 1; off >>= 1) zb = max(zb, (unsigned)__shfl_xor((int)zb, off, 64));
                 if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = zb;
             }
         }
@@ -547,6 +593,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             }
         }
         PackedScale pk;  // set in the first window (after a barrier)
+        ItemScale qs;    // likewise
+        // modes without a gathered value: the bound is known before the item
+        // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2)
+        if (QITEM && !GATHER)
+            qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale) * (READS_IMG ? (double)img_bound : 1.0));
         // enumeration box (grid coordinates): the brick's pixels have floor(g)
         // in the brick
         float lo[3], hi[3];
@@ -566,12 +617,13 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             const int nw = min(WI, n_img - w0);
             // every wave has finished with the previous window's tables
             __syncthreads();
-            if (PK_ALWAYS && w0 == 0) {
-                float zb = 0.f;
+            if (STAGE_MAX && w0 == 0) {
+                unsigned zbits = 0u;
 #pragma unroll
-                for (int w = 0; w < kBT / 64; ++w) zb = fmaxf(zb, s_wmax[w]);
-                zb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(zb)));
-                pk = PackedScale::make(fabsf(a.scale) * zb);
+                for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
+                const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
+                if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
+                if (QITEM) qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + (double)img_bound));
             }
             // ---- the window's images (one thread each): constants, first row,
             // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
@@ -799,13 +851,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                         const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                                         const float w = wx[ax] * wy[ay] * wz[az];
                                         const int li = lb + az * XP + ay * XR + ax;
-                                        if (MODE == kBSqDiag) {
+                                        if (MODE == kBSqDiag && QLDS) {
+                                            atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
+                                        } else if (MODE == kBSqDiag) {
                                             atomicAdd(&acc_re[li], (double)(w * w * val.x));
                                         } else if (PK_ALWAYS) {
                                             atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
-                                        } else if (FX) {
-                                            atomicAdd(&acc_qre[li], fx_quant(w * val.x, fxS));
-                                            atomicAdd(&acc_qim[li], fx_quant(w * val.y, fxS));
+                                        } else if (QLDS) {
+                                            const double S = FX ? fxS : qs.S;
+                                            atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
+                                            atomicAdd(&acc_qim[li], fx_quant(w * val.y, S));
                                         } else {
                                             atomicAdd(&acc_re[li], (double)(w * val.x));
                                             atomicAdd(&acc_im[li], (double)(w * val.y));
@@ -837,6 +892,23 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                     const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
                     if (qr) atomicAdd(&a.fx[2 * gi], qr);
                     if (qi) atomicAdd(&a.fx[2 * gi + 1], qi);
+                    continue;
+                }
+                if (QITEM && MODE == kBSqDiag) {
+                    const long long qr = (long long)acc_qre[li];
+                    if (!qs.ok) atomicAdd(a.accum_real + gi, __builtin_nanf(""));
+                    else if (qr) atomicAdd(a.accum_real + gi, (float)((double)qr * qs.invS));
+                    continue;
+                }
+                if (QITEM) {
+                    const long long qr = (long long)acc_qre[li], qi = (long long)acc_qim[li];
+                    if (!qs.ok) {
+                        atomicAdd(&a.accum[gi].x, __builtin_nanf(""));
+                        atomicAdd(&a.accum[gi].y, __builtin_nanf(""));
+                    } else {
+                        if (qr) atomicAdd(&a.accum[gi].x, (float)((double)qr * qs.invS));
+                        if (qi) atomicAdd(&a.accum[gi].y, (float)((double)qi * qs.invS));
+                    }
                     continue;
                 }
                 if (PK_ALWAYS) {
@@ -948,6 +1020,16 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
     const int grid = (int)(resident_blocks<MODE, FX>() < max_items ? resident_blocks<MODE, FX>() : max_items);
+    // the fast backproject and gradient bound their LDS sums with the largest
+    // |re| + |im| of the images (one pass over them, into the work-list
+    // scalars)
+    constexpr bool img_bound = CSG_LDS_FIXED && !FX && (MODE == kBBackproject || MODE == kBGradient);
+    unsigned *img_bits = (unsigned *)(scalars + 2);
+    if (img_bound) {
+        hipError_t e = launch_fill_f32((float *)img_bits, 1, 0.0f, st);  // zero bits
+        if (e == hipSuccess) e = launch_img_absmax(g, img, n, img_bits, st);
+        if (e != hipSuccess) return e;
+    }
     for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
         const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
         const int stride = (int)ns;
@@ -985,6 +1067,8 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
             a.fx = fb->fx;
             a.fx_max = fb->maxbits;
             a.n_total = n;
+        } else if (img_bound) {
+            a.fx_max = img_bits;
         }
         // the probe HVP is timed with the HVP
         constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
@@ -1069,7 +1153,8 @@ hipError_t launch_brick_backproject_fx(const Geom &g, const float *rot, const fl
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
     const int64_t nv = (int64_t)g.M * g.M * g.M;
-    hipError_t e = launch_fx_prep(img, n * g.M * g.M, nullptr, 0, fb.maxbits, fb.fx, nv, st);
+    hipError_t e = launch_fx_prep(nullptr, 0, fb.maxbits, fb.fx, nv, st);
+    if (e == hipSuccess) e = launch_img_absmax(g, img, n, fb.maxbits, st);
     if (e != hipSuccess) return e;
     e = run_brick_mode<kBBackproject, true>(g, rot, defocus, shift, n, nullptr, img, nullptr, accum, nullptr, scale,
                                             ctf_power, ws, st, nullptr, &fb);
@@ -1083,7 +1168,8 @@ hipError_t launch_brick_gradient_fx(const Geom &g, const float *rot, const float
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;
     const int64_t nv = (int64_t)g.M * g.M * g.M;
-    hipError_t e = launch_fx_prep(vol, nv, x, n * g.M * g.M, fb.maxbits, fb.fx, nv, st);
+    hipError_t e = launch_fx_prep(vol, nv, fb.maxbits, fb.fx, nv, st);
+    if (e == hipSuccess) e = launch_img_absmax(g, x, n, fb.maxbits + 1, st);
     if (e != hipSuccess) return e;
     e = run_brick_mode<kBGradient, true>(g, rot, defocus, shift, n, vol, x, nullptr, accum, loss, scale, 1, ws, st,
                                          nullptr, &fb);
@@ -1096,7 +1182,7 @@ hipError_t launch_brick_hvp_fx(const Geom &g, const float *rot, const float *def
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;
     const int64_t nv = (int64_t)g.M * g.M * g.M;
-    hipError_t e = launch_fx_prep(z, nv, nullptr, 0, fb.maxbits, fb.fx, nv, st);
+    hipError_t e = launch_fx_prep(z, nv, fb.maxbits, fb.fx, nv, st);
     if (e != hipSuccess) return e;
     e = run_brick_mode<kBHvp, true>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st,
                                     nullptr, &fb);

@@ -93,10 +93,12 @@ hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int6
 // 16-byte aligned, nvox even
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st);
-// fixed-point adjoint: bounds of a (and b, which may be NULL) into
-// maxbits[0..1] and a zeroed fx[0..2 nvox); then accum += fx / S
-hipError_t launch_fx_prep(const float2 *a, int64_t na, const float2 *b, int64_t nb, unsigned *maxbits,
-                          unsigned long long *fx, int64_t nvox, hipStream_t st);
+// fixed-point adjoint: maxbits[0..1] zeroed, then the bound of a (may be
+// NULL) into maxbits[0] and a zeroed fx[0..2 nvox); img_absmax raises *dst
+// to the bound of the images' disk pixels; finish adds fx / S to accum
+hipError_t launch_fx_prep(const float2 *a, int64_t na, unsigned *maxbits, unsigned long long *fx, int64_t nvox,
+                          hipStream_t st);
+hipError_t launch_img_absmax(const Geom &g, const float2 *img, int64_t n, unsigned *dst, hipStream_t st);
 hipError_t launch_fx_finish(float2 *out, const unsigned long long *fx, int64_t nvox, const unsigned *maxbits,
                             float scale, int64_t n, hipStream_t st);
 hipError_t launch_shell_sums(const float2 *u, const float2 *v, int M, double *out, hipStream_t st);

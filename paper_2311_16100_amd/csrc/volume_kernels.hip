@@ -490,21 +490,122 @@ __device__ __forceinline__ void block_max_to(unsigned m, unsigned *lds /* >= 16 
     if (threadIdx.x == 0) {
         unsigned t = 0u;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = max(t, lds[i]);
-        if (t) atomicMax(dst, t);
+        // most blocks cannot raise the maximum: skip their atomics
+        if (t > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, t);
     }
     __syncthreads();
 }
 
-// maxbits[0] = bound of a[0..na), maxbits[1] = bound of b[0..nb) (b may be
-// NULL), both zero on entry; the fixed-point volume fx[0..nvox) is zeroed.
-__global__ __launch_bounds__(kBlock) void fx_prep_kernel(const float2 *a, int64_t na, const float2 *b, int64_t nb,
-                                                          unsigned *maxbits, ulonglong2 *fx, int64_t nvox) {
+// *maxbits = bound of a[0..na) (a may be NULL; *maxbits zero on entry); the
+// fixed-point volume fx[0..nvox) is zeroed.
+__global__ __launch_bounds__(kBlock) void fx_prep_kernel(const float2 *a, int64_t na, unsigned *maxbits,
+                                                          ulonglong2 *fx, int64_t nvox) {
     __shared__ unsigned red[16];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = tid; k < nvox; k += stride) fx[k] = make_ulonglong2(0ull, 0ull);
-    block_max_to(absmax_bits(a, na, tid, stride), red, maxbits);
-    if (b) block_max_to(absmax_bits(b, nb, tid, stride), red, maxbits + 1);
+    if (a) block_max_to(absmax_bits(a, na, tid, stride), red, maxbits);
+}
+
+// *dst = max(*dst, bound of the disk pixels of n images [n][M][M]): the
+// pixels the operators read.  One block per image; each wave takes every
+// fourth disk row, four rows per step with all their loads issued before the
+// first maximum (up to 16 loads in flight per lane).
+// floor(sqrt(k2max - ky^2)) for |ky| <= floor(sqrt(k2max)) (k2max < 2^20:
+// the float square root is off by at most one)
+__device__ __forceinline__ int disk_half_width(int k2max, int ky) {
+    const int rem = k2max - ky * ky;
+    int kxm = (int)sqrtf((float)rem);
+    kxm -= kxm * kxm > rem ? 1 : 0;
+    kxm += (kxm + 1) * (kxm + 1) <= rem ? 1 : 0;
+    return kxm;
+}
+
+__global__ __launch_bounds__(kBlock) void img_absmax_kernel(const float2 *__restrict__ img, int M, int half,
+                                                             int k2max, int kymax, unsigned *dst) {
+    __shared__ unsigned red[16];
+    constexpr int NW = kBlock / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const float2 *im = img + (int64_t)blockIdx.x * M * M + (int64_t)half * M + half;  // pixel (0, 0)
+    unsigned m = 0u;
+    for (int ky0 = -kymax + wv; ky0 <= kymax; ky0 += 4 * NW) {
+        // the loads are unconditional (addresses clamped into the row, rows
+        // past the disk replaced by its last row) so that all sixteen are
+        // issued before the first wait; the values outside are masked
+        float2 v[4][4];
+        bool in[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ky = ky0 + j * NW;
+            const bool row_in = ky <= kymax;
+            const int kyc = row_in ? ky : kymax;
+            const int kxm = disk_half_width(k2max, kyc);
+            const float2 *p = im + (int64_t)kyc * M;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int x = lane - kxm + 64 * k;
+                v[j][k] = p[min(x, kxm)];
+                in[j][k] = row_in && x <= kxm;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned bv = __float_as_uint(fabsf(v[j][k].x) + fabsf(v[j][k].y)) & 0x7fffffffu;
+                m = max(m, in[j][k] ? bv : 0u);
+            }
+    }
+    // rows longer than 256 pixels (M > 512)
+    for (int ky = -kymax + wv; ky <= kymax; ky += NW) {
+        const int kxm = disk_half_width(k2max, ky);
+        const float2 *p = im + (int64_t)ky * M;
+        for (int x = lane - kxm + 256; x <= kxm; x += 64) {
+            const float2 w = p[x];
+            m = max(m, __float_as_uint(fabsf(w.x) + fabsf(w.y)) & 0x7fffffffu);
+        }
+    }
+    block_max_to(m, red, dst);
+}
+
+// The same over 16-byte pairs of pixels (image base 16-byte aligned; M is
+// even, so a pair never straddles two rows): blockIdx.y is the image,
+// blockIdx.x a range of kImgPairs pairs, strided by the block size so that
+// each wave load covers 1 KB of consecutive pixels.  A pair with no pixel in
+// the disk loads the image's centre pair instead (always cached), so only
+// lines that hold disk pixels are fetched while every load stays
+// unconditional (all are issued before the first wait).
+constexpr int kImgPairs = 8;  // pairs per thread
+__global__ __launch_bounds__(kBlock) void img_absmax2_kernel(const float4 *__restrict__ img, int M, int half,
+                                                              int k2max, int pairs, unsigned *dst) {
+    __shared__ unsigned red[16];
+    const float4 *im = img + (int64_t)blockIdx.y * pairs;
+    const float invM = 1.0f / (float)M;
+    const int centre = (half * M + half) >> 1;
+    float4 v[kImgPairs];
+    int inside[kImgPairs];  // bit 0: first pixel, bit 1: second
+#pragma unroll
+    for (int u = 0; u < kImgPairs; ++u) {
+        const int q = (blockIdx.x * kImgPairs + u) * kBlock + threadIdx.x;
+        const int p = 2 * q;  // first pixel (p < M^2 <= 2^20: the float quotient is off by at most one)
+        int y = (int)((float)p * invM);
+        y += (y + 1) * M <= p ? 1 : 0;
+        y -= y * M > p ? 1 : 0;
+        const int kx = p - y * M - half, ky = y - half;
+        const int r2 = kx * kx + ky * ky;
+        const int in = (q < pairs ? 1 : 0) * ((r2 <= k2max ? 1 : 0) | (r2 + 2 * kx + 1 <= k2max ? 2 : 0));
+        inside[u] = in;
+        v[u] = im[in ? q : centre];
+    }
+    unsigned m = 0u;
+#pragma unroll
+    for (int u = 0; u < kImgPairs; ++u) {
+        const unsigned b0 = __float_as_uint(fabsf(v[u].x) + fabsf(v[u].y)) & 0x7fffffffu;
+        const unsigned b1 = __float_as_uint(fabsf(v[u].z) + fabsf(v[u].w)) & 0x7fffffffu;
+        m = max(m, (inside[u] & 1) ? b0 : 0u);
+        m = max(m, (inside[u] & 2) ? b1 : 0u);
+    }
+    block_max_to(m, red, dst);
 }
 
 // out += fx / S per component, in double precision with one rounding to
@@ -527,15 +628,41 @@ __global__ __launch_bounds__(kBlock) void fx_finish_kernel(float2 *__restrict__ 
     }
 }
 
-hipError_t launch_fx_prep(const float2 *a, int64_t na, const float2 *b, int64_t nb, unsigned *maxbits,
-                          unsigned long long *fx, int64_t nvox, hipStream_t st) {
+hipError_t launch_fx_prep(const float2 *a, int64_t na, unsigned *maxbits, unsigned long long *fx, int64_t nvox,
+                          hipStream_t st) {
     hipError_t e = launch_fill_f32((float *)maxbits, 2, 0.0f, st);  // zero bits
     if (e != hipSuccess) return e;
-    int64_t units = na > nb ? na : nb;
-    if (nvox > units) units = nvox;
-    hipLaunchKernelGGL(fx_prep_kernel, dim3(reduce_blocks(units)), dim3(kBlock), 0, st, a, na, b, nb, maxbits,
+    const int64_t units = na > nvox ? na : nvox;
+    if (units == 0) return hipSuccess;
+    hipLaunchKernelGGL(fx_prep_kernel, dim3(reduce_blocks(units)), dim3(kBlock), 0, st, a, na, maxbits,
                        (ulonglong2 *)fx, nvox);
     return hipGetLastError();
+}
+
+hipError_t launch_img_absmax(const Geom &g, const float2 *img, int64_t n, unsigned *dst, hipStream_t st) {
+    int kymax = (int)sqrt((double)g.k2max);
+    while ((kymax + 1) * (kymax + 1) <= g.k2max) ++kymax;
+    while (kymax > 0 && kymax * kymax > g.k2max) --kymax;
+    if (aligned(img, 16)) {
+        const int pairs = g.M * g.M / 2;
+        const unsigned bx = (unsigned)((pairs + kImgPairs * kBlock - 1) / (kImgPairs * kBlock));
+        for (int64_t i0 = 0; i0 < n; i0 += 65535) {
+            const int64_t cnt = n - i0 < 65535 ? n - i0 : 65535;
+            hipLaunchKernelGGL(img_absmax2_kernel, dim3(bx, (unsigned)cnt), dim3(kBlock), 0, st,
+                               (const float4 *)(img + i0 * (int64_t)g.M * g.M), g.M, g.half, g.k2max, pairs, dst);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)1 << 30) {  // one block per image
+        const int64_t cnt = n - i0 < ((int64_t)1 << 30) ? n - i0 : ((int64_t)1 << 30);
+        hipLaunchKernelGGL(img_absmax_kernel, dim3((unsigned)cnt), dim3(kBlock), 0, st,
+                           img + i0 * (int64_t)g.M * g.M, g.M, g.half, g.k2max, kymax, dst);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_fx_finish(float2 *out, const unsigned long long *fx, int64_t nvox, const unsigned *maxbits,

@@ -554,3 +554,22 @@ def test_in_plane_shift_parity(b, case):
         assert loss.item() == pytest.approx(want_f, rel=1e-5), det
     # without shifts the results differ (the shift is applied at all)
     assert rel(b.project(g, o, rot, df, v).cpu().numpy(), want) > 1e-2
+
+
+def test_non_finite_inputs_give_nan(b):
+    """The fast adjoint bounds its fixed-point LDS sums by the largest input
+    magnitude; a non-finite image value or volume value must surface as NaN,
+    not as a wrapped integer."""
+    grid_o, opt_o, P, vol, img = make_case(M=24, n=30, seed=17)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    bad = x.clone()
+    bad[3, 12, 12] = float("inf")
+    acc = b.backproject(g, o, rot, df, bad)
+    assert torch.isnan(torch.view_as_real(acc)).any()
+    vbad = v.clone()
+    vbad[12, 12, 12] = float("nan")
+    for out in (b.gradient(g, o, rot, df, vbad, x, 1.0, 0.0), b.hvp(g, o, rot, df, vbad, 1.0, 0.0)):
+        assert torch.isnan(torch.view_as_real(out)).any()
+    # finite inputs stay finite
+    assert torch.isfinite(torch.view_as_real(b.gradient(g, o, rot, df, v, x, 1.0, 0.0))).all()
