@@ -573,3 +573,22 @@ def test_non_finite_inputs_give_nan(b):
         assert torch.isnan(torch.view_as_real(out)).any()
     # finite inputs stay finite
     assert torch.isfinite(torch.view_as_real(b.gradient(g, o, rot, df, v, x, 1.0, 0.0))).all()
+
+
+@pytest.mark.parametrize("k", [-100, 100])
+def test_fast_adjoint_far_from_unit_scale(b, k):
+    """The per-item fixed-point scale follows the data: inputs scaled by 2^k
+    give outputs scaled by 2^k (to float rounding), for the adjoint, the
+    gradient and the HVP."""
+    grid_o, opt_o, P, vol, img = make_case(M=32, n=60, seed=18)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    f = float(2.0 ** k)
+    pairs = (
+        (b.backproject(g, o, rot, df, x, ctf_power=1), b.backproject(g, o, rot, df, x * f, ctf_power=1)),
+        (b.gradient(g, o, rot, df, v, x, 1.5, 0.0), b.gradient(g, o, rot, df, v * f, x * f, 1.5, 0.0)),
+        (b.hvp(g, o, rot, df, v, 1.5, 0.0), b.hvp(g, o, rot, df, v * f, 1.5, 0.0)),
+    )
+    for base, scaled in pairs:
+        want = base.cpu().numpy().astype(np.complex128) * f
+        assert rel(scaled.cpu().numpy().astype(np.complex128), want) <= 1e-6
