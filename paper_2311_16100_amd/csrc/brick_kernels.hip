@@ -9,14 +9,16 @@
 //   - stages the brick and the voxels one step above it on each axis (13^3
 //     complex values of the gathered volume) in LDS, so every trilinear
 //     gather is 8 LDS reads;
-//   - accumulates the adjoint into an LDS array of the same extent with
-//     double-precision LDS atomics (the probe HVP: packed fixed point, see
-//     PackedScale), and adds it to HBM once per voxel at the
-//     end with global atomics (the upper faces of the extent belong to the
-//     neighbouring bricks, which other blocks may be flushing at the same
-//     time).  On gfx950 the LDS double atomic add sustains about 20x the lane
-//     rate of the single-precision one, so the wider accumulator is also the
-//     faster one.
+//   - accumulates the adjoint into an LDS array of the same extent as 64-bit
+//     fixed-point integers, one per component (ItemScale; the deterministic
+//     mode: FxScale; the probe HVP packs both components into one, see
+//     PackedScale), and adds it to HBM once per voxel at the end with global
+//     atomics (the upper faces of the extent belong to the neighbouring
+//     bricks, which other blocks may be flushing at the same time).  On gfx950
+//     the LDS single-precision atomic add sustains about a twentieth of the
+//     lane rate of the 64-bit ones, and in these kernels the integer add is
+//     cheaper than the double one, so the wide integer accumulator is also
+//     the fastest.
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
@@ -372,14 +374,15 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // |val| <= V = |scale| max|z| over the staged brick (|C| <= 1 and the
 // trilinear weights sum to 1).  A voxel receives from one image at most
 // the pixels of the plane lattice inside its 2x2x2 neighbourhood, whose section
-// has diameter at most 2 sqrt(3): at most 16 pixels, each with weight <= 1.
+// has area at most 4 sqrt(2): at most 13 pixels (Pick's theorem; 16 is used),
+// each with weight <= 1.
 // Over an item of at most 128 images a component sum is therefore below
 // 2048 V = B, and S = 2^e with B S <= 2^30 keeps every sum (and every rounded
 // contribution) below 2^30.  The rounding error is at most 1/(2S) per
 // contribution, i.e. 2^-31 B (relative 5e-10 of B).  Because B is a worst
 // case, the result is about 1e-5 relative (measured), well below the noise of
 // a two-probe Hutchinson estimate; the gradient and the general HVP, whose
-// sums need float accuracy, keep the double accumulator.
+// sums need float accuracy, keep one 64-bit integer per component.
 struct PackedScale {
     float S = 1.f, invS = 1.f;
     static __device__ __forceinline__ PackedScale make(float V) {
@@ -461,8 +464,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     constexpr int CHUNK = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     // Packed accumulation (see PackedScale): both components of a contribution
     // go into one 64-bit integer LDS atomic, as 32-bit fixed-point numbers with
-    // a per-item power-of-two scale.  Only the probe HVP packs; the other
-    // adjoint modes accumulate in double.
+    // a per-item power-of-two scale.  Only the probe HVP packs.
     constexpr bool PK_ALWAYS = MODE == kBHvpProbe;
     // 64-bit fixed-point LDS accumulators: the deterministic modes (one
     // launch-wide scale, FxScale) and the fast modes other than the packed

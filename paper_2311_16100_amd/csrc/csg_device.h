@@ -196,8 +196,9 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* >= 16 */) {
 // + m1) with m0, m1 the largest |re| + |im| of the operator's inputs (|C| <= 1,
 // |T| = 1 and the trilinear weights of a gathered value sum to 1).  A voxel
 // receives from one image only the lattice pixels inside its 2x2x2
-// neighbourhood (at most 16; 32 is used as margin), so every partial sum over
-// n images stays below 32 n V.  S = 2^e is the largest power of two with
+// neighbourhood: a plane cuts that cube in area at most 4 sqrt(2), so by
+// Pick's theorem at most 13 pixels (32 is used as margin), and every partial
+// sum over n images stays below 32 n V.  S = 2^e is the largest power of two with
 // 32 n V S <= 2^61 (no 64-bit overflow) and V S <= 2^50 (fx_quant is exact).
 // ok = 0 when an input is not finite.
 struct FxScale {
