@@ -163,7 +163,9 @@ int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, voi
  * adjoint sums are kept in 32-bit fixed point per component with a scale
  * from a worst-case bound (the probe entries are +-1): the estimate matches
  * the one formed with csg_hvp to about 1e-5 relative, far below its own
- * sampling noise.
+ * sampling noise.  The probes are regenerated from their hash wherever they
+ * are read and never stored (on nearest-neighbour grids the pair is stored in
+ * the workspace).
  *   diag_out device float [M^3], overwritten.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_HUTCHINSON). */
 int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
@@ -264,7 +266,8 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
  *   CSG_WS_BACKPROJECT_DETERMINISTIC  csg_backproject, deterministic = 1
  *                                  (trilinear grids: adds the 64-bit
  *                                  fixed-point volume, 16 M^3 bytes)
- *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: two complex volumes
+ *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: one complex volume
+ *                                  (nearest-neighbour grids: two)
  *   CSG_WS_GRADIENT                csg_gradient / csg_hvp, deterministic = 0
  *   CSG_WS_GRADIENT_DETERMINISTIC  csg_gradient / csg_hvp, deterministic = 1
  *                                  (trilinear grids: the fixed-point volume;

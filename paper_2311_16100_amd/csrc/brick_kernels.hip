@@ -40,7 +40,8 @@
 //   kBBackproject  accum += scale C^p img
 //   kBGradient     r = C P v - x; loss (owner); accum += scale C r
 //   kBHvp          accum += scale C^2 P z
-//   kBHvpProbe     the same for a Rademacher probe pair z (Hutchinson): both
+//   kBHvpProbe     the same for a Rademacher probe pair z (Hutchinson),
+//                  generated from its hash while the brick is staged: both
 //                  components of a contribution go into one 64-bit integer LDS
 //                  atomic as fixed-point numbers (see PackedScale)
 //   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
@@ -126,6 +127,10 @@ struct BrickArgs {
     unsigned long long *fx;
     const unsigned *fx_max;
     int64_t n_total;
+    // probe HVP: the Rademacher pair z = z_a + i z_b (z_b = 0 without has_b),
+    // generated while the bricks are staged (rademacher_block)
+    uint64_t probe_seed, probe_a, probe_b;
+    int probe_has_b;
 };
 
 __device__ __forceinline__ void brick_origin(int b, int nbx, int o[3]) {
@@ -487,6 +492,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
     __shared__ unsigned s_wmax[kBT / 64];
+    // probe HVP: signs of the staged rows ([row][probe]; see the staging)
+    __shared__ uint32_t s_zmask[MODE == kBHvpProbe ? BX * BX : 1][2];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
     constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -542,6 +549,51 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             constexpr int HALO = BX * BX * BX;
             constexpr int HPT = (HALO + kBT - 1) / kBT;
             float2 hv[HPT];
+            if (MODE == kBHvpProbe) {
+                // the probe pair is generated, not loaded: one thread per row
+                // and probe of the extended brick forms the signs of the row's
+                // (at most 13, consecutive) voxels from the one or two Philox
+                // blocks they fall in, with the in-grid voxels marked in bits
+                // 16 and up; then every thread expands its voxels
+                if ((int)threadIdx.x < 2 * BX * BX) {
+                    const int row = threadIdx.x >> 1, p = threadIdx.x & 1;
+                    const int qy = o[1] + row % BX, qz = o[2] + row / BX;
+                    const int nx = min(BX, M - o[0]);
+                    uint32_t m = 0u;
+                    if (qy < M && qz < M && (p == 0 || a.probe_has_b)) {
+                        const int64_t g0 = ((int64_t)qz * M + qy) * M + o[0];
+                        const uint64_t probe = p ? a.probe_b : a.probe_a;
+                        const uint32_t b0 = (uint32_t)(g0 >> 7);
+                        const U4 r0 = rademacher_block(a.probe_seed, probe, b0);
+                        const U4 r1 = (uint32_t)((g0 + nx - 1) >> 7) != b0 ? rademacher_block(a.probe_seed, probe, b0 + 1)
+                                                                            : r0;
+                        // the 13 bits from bit (g0 mod 128) on, in the words
+                        // r0.x .. r0.w r1.x r1.y (a run of 13 spans at most
+                        // two consecutive words)
+                        const int start = (int)(g0 & 127), wi = start >> 5, sh = start & 31;
+                        const uint32_t lo = wi == 0 ? r0.x : wi == 1 ? r0.y : wi == 2 ? r0.z : r0.w;
+                        const uint32_t hi = wi == 0 ? r0.y : wi == 1 ? r0.z : wi == 2 ? r0.w : r1.x;
+                        const uint64_t two = ((uint64_t)hi << 32) | lo;
+                        m = (uint32_t)(two >> sh) & ((1u << nx) - 1u);
+                        m |= ((1u << nx) - 1u) << 16;
+                    }
+                    s_zmask[row][p] = m;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < HPT; ++k) {
+                    const int t = threadIdx.x + k * kBT;
+                    const int hx = t % BX, row = t / BX;
+                    hv[k] = make_float2(0.f, 0.f);
+                    if (t < HALO) {
+                        const uint32_t ma = s_zmask[row][0], mb = s_zmask[row][1];
+                        if ((ma >> (16 + hx)) & 1u) {
+                            hv[k].x = ((ma >> hx) & 1u) ? -1.f : 1.f;
+                            if (a.probe_has_b) hv[k].y = ((mb >> hx) & 1u) ? -1.f : 1.f;
+                        }
+                    }
+                }
+            } else {
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
                 int t = threadIdx.x + k * kBT;
@@ -552,6 +604,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
                 hv[k] = make_float2(0.f, 0.f);
                 if (t < HALO && qx < M && qy < M && qz < M) hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
+            }
             }
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
@@ -1001,11 +1054,17 @@ static int resident_blocks() {
     return cus * per;
 }
 
+// The Rademacher probe pair of the probe HVP mode (seed, pa, pb, has_b).
+struct ProbePair {
+    uint64_t seed, pa, pb;
+    int has_b;
+};
+
 template <int MODE, bool FX = false>
 static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                  const float2 *src, const float2 *img, float2 *out, float2 *accum, double *loss,
                                  float scale, int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr,
-                                 const FxBuf *fb = nullptr) {
+                                 const FxBuf *fb = nullptr, const ProbePair *probe = nullptr) {
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
@@ -1072,6 +1131,12 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         } else if (img_bound) {
             a.fx_max = img_bits;
         }
+        if (probe) {
+            a.probe_seed = probe->seed;
+            a.probe_a = probe->pa;
+            a.probe_b = probe->pb;
+            a.probe_has_b = probe->has_b;
+        }
         // the probe HVP is timed with the HVP
         constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
         hipEvent_t t0 = timing_begin(TMODE, st);
@@ -1137,13 +1202,20 @@ hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *de
 }
 
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
-                            float scale, float2 *accum, void *ws, hipStream_t st, bool probe) {
+                            float scale, float2 *accum, void *ws, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_hvp_atomic(g, rot, defocus, n, z, scale, accum, st);
-    if (probe)
-        return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws,
-                                          st);
     return run_brick_mode<kBHvp>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
+}
+
+hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,
+                                  uint64_t pa, uint64_t pb, int has_b, float scale, float2 *accum, void *ws,
+                                  hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;  // the pixel kernels read a stored probe
+    const ProbePair pp{seed, pa, pb, has_b};
+    return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, nullptr, nullptr, nullptr, accum, nullptr, scale, 2,
+                                      ws, st, nullptr, nullptr, &pp);
 }
 
 // Deterministic adjoint: input bounds and a zeroed fixed-point volume, the

@@ -167,6 +167,14 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 
 constexpr uint32_t kRademacherTag = 0x52414431u;  // counter word 3 of the probe stream
 
+// The 128 random bits of Rademacher probe `probe` for voxels 128 blk ..
+// 128 blk + 127: voxel k takes bit k mod 128 (word (k mod 128) / 32 of the
+// output, bit k mod 32 of that word); a set bit means -1, a clear one +1.
+__device__ __forceinline__ U4 rademacher_block(uint64_t seed, uint64_t probe, uint32_t blk) {
+    return philox4x32_10(U4{blk, (uint32_t)probe, (uint32_t)(probe >> 32), kRademacherTag}, (uint32_t)seed,
+                         (uint32_t)(seed >> 32));
+}
+
 // Wave-wide sum of a double (64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

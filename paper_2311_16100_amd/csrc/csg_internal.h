@@ -36,10 +36,14 @@ hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const floa
                                      float2 *accum, void *ws, hipStream_t st);
 hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,
                                 float *diag, void *ws, hipStream_t st);
-// probe: z is a Rademacher probe pair (entries 0 or +-1 per component), which
-// allows the packed fixed-point accumulator
 hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocus, int64_t n, const float2 *z,
-                            float scale, float2 *accum, void *ws, hipStream_t st, bool probe = false);
+                            float scale, float2 *accum, void *ws, hipStream_t st);
+// the same for the Rademacher probe pair (seed, pa, pb, has_b) of
+// launch_probe_init, generated while the bricks are staged; its entries are
+// 0 or +-1 per component, which allows the packed fixed-point accumulator
+hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,
+                                  uint64_t pa, uint64_t pb, int has_b, float scale, float2 *accum, void *ws,
+                                  hipStream_t st);
 // the deterministic adjoint (fixed point; trilinear grids): scratch of
 // 16 M^3 bytes (the 64-bit fixed-point volume, 16-byte aligned) and two words
 // (input bounds), both in device memory
@@ -84,15 +88,16 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_finish_loss(double *loss_out, const double *data, const double *norm2, float scale, float lam,
                               hipStream_t st);
 hipError_t launch_rademacher(float *z, int64_t nvox, uint64_t seed, uint64_t probe, hipStream_t st);
-hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
-                                  hipStream_t st);
-// first: the sum starts with this probe pair (diag is written, not read)
-hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,
-                            hipStream_t st);
-// z = Rademacher probe pair (as launch_rademacher_pair), hz = lam z; z and hz
-// 16-byte aligned, nvox even
+// Rademacher probe pair z = z_pa + i z_pb (z_pb = 0 without has_b; voxel k
+// takes bit k mod 128 of rademacher_block k / 128), never stored:
+// probe_init writes hz = lam z; zhz_hash adds w (Re z Re hz + Im z Im hz) to
+// diag (first: the sum starts with this pair, diag is written, not read).
+// probe_init also writes z where z is not NULL (the nearest-neighbour
+// kernels read it).  z and hz 16-byte aligned, nvox even.
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st);
+hipError_t launch_zhz_hash(float *diag, const float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb,
+                           int has_b, float w, bool first, hipStream_t st);
 // fixed-point adjoint: maxbits[0..1] zeroed, then the bound of a (may be
 // NULL) into maxbits[0] and a zeroed fx[0..2 nvox); img_absmax raises *dst
 // to the bound of the images' disk pixels; finish adds fx / S to accum

@@ -77,8 +77,7 @@ __global__ void finish_loss_kernel(double *loss_out, const double *data, const d
 // Philox block (k/128), using bits (k mod 128).
 __device__ __forceinline__ float4 rademacher4(uint64_t seed, uint64_t probe, int64_t k4) {
     const int64_t k = k4 * 4;
-    const U4 r = philox4x32_10(U4{(uint32_t)(k >> 7), (uint32_t)probe, (uint32_t)(probe >> 32), kRademacherTag},
-                               (uint32_t)seed, (uint32_t)(seed >> 32));
+    const U4 r = rademacher_block(seed, probe, (uint32_t)(k >> 7));
     const int bit = (int)(k & 127);
     const uint32_t word = (bit < 32) ? r.x : (bit < 64) ? r.y : (bit < 96) ? r.z : r.w;
     const uint32_t b = word >> (bit & 31);
@@ -101,68 +100,63 @@ __global__ __launch_bounds__(kBlock) void rademacher_kernel(float *__restrict__ 
     }
 }
 
-// Complex probe pair z = z_{pa} + i z_{pb} (z_{pb} = 0 when has_b == 0).
-__global__ __launch_bounds__(kBlock) void rademacher_pair_kernel(float2 *__restrict__ z, int64_t nvox, uint64_t seed,
-                                                                  uint64_t pa, uint64_t pb, int has_b) {
-    const int64_t n4 = (nvox + 3) / 4;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n4; t += stride) {
-        const float4 ra = rademacher4(seed, pa, t);
-        const float4 rb = has_b ? rademacher4(seed, pb, t) : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float va[4] = {ra.x, ra.y, ra.z, ra.w}, vb[4] = {rb.x, rb.y, rb.z, rb.w};
-        const int64_t k = t * 4;
-        for (int e = 0; e < 4; ++e)
-            if (k + e < nvox) z[k + e] = make_float2(va[e], vb[e]);
-    }
+// Start of the product of a probe pair z = z_pa + i z_pb: hz = lam z, and z
+// itself only where a kernel must read it (z may be NULL: the brick kernel
+// and the accumulation below regenerate it).  Voxel k takes bit k mod 128 of Philox block k / 128 (rademacher_block).
+// A wave covers 8192 consecutive voxels: each lane evaluates one Philox block
+// per probe into LDS, then the wave writes the voxels two per lane and store,
+// consecutive lanes at consecutive 16-byte addresses.  nvox is even and hz is
+// 16-byte aligned.
+constexpr int kProbeWaves = kBlock / 64;
+
+// the bits of probe pair (pa, pb) for the 8192 voxels of chunk c, into
+// words[probe][word][block of the chunk] of the calling wave
+__device__ __forceinline__ void probe_chunk_bits(uint32_t (*words)[4][64], int64_t c, int lane, uint64_t seed,
+                                                 uint64_t pa, uint64_t pb, int has_b) {
+    const uint32_t blk = (uint32_t)(c * 64 + lane);
+    const U4 ra = rademacher_block(seed, pa, blk);
+    const U4 rb = has_b ? rademacher_block(seed, pb, blk) : U4{0u, 0u, 0u, 0u};
+    words[0][0][lane] = ra.x;
+    words[0][1][lane] = ra.y;
+    words[0][2][lane] = ra.z;
+    words[0][3][lane] = ra.w;
+    words[1][0][lane] = rb.x;
+    words[1][1][lane] = rb.y;
+    words[1][2][lane] = rb.z;
+    words[1][3][lane] = rb.w;
+    // the words were written by this wave: its LDS accesses complete in
+    // order, and the barrier keeps the compiler from moving them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Probe pair and the start of its product in one pass: z = z_pa + i z_pb and
-// hz = lam z.  Voxel k takes bit k mod 128 of Philox block k / 128, as in
-// rademacher4.  A wave covers 8192 consecutive voxels: each lane evaluates one
-// Philox block (per probe) into LDS, then the wave writes the voxels two per
-// lane and store, consecutive lanes at consecutive 16-byte addresses.  nvox is
-// even and both pointers are 16-byte aligned.
-__global__ __launch_bounds__(kBlock) void probe_init_kernel(float4 *__restrict__ z, float4 *__restrict__ hz,
+// voxels 2 q and 2 q + 1 of chunk c (q = c 4096 + 64 j + lane) take bits
+// 2 lane and 2 lane + 1 of block c 64 + j: the pair (a0 + i b0, a1 + i b1)
+__device__ __forceinline__ float4 probe_pair_values(uint32_t (*words)[4][64], int j, int lane, int has_b) {
+    const int w = lane >> 4, sh = (2 * lane) & 31;
+    const uint32_t ba = words[0][w][j] >> sh, bb = words[1][w][j] >> sh;
+    const float a0 = (ba & 1u) ? -1.f : 1.f, a1 = (ba & 2u) ? -1.f : 1.f;
+    const float b0 = has_b ? ((bb & 1u) ? -1.f : 1.f) : 0.f;
+    const float b1 = has_b ? ((bb & 2u) ? -1.f : 1.f) : 0.f;
+    return make_float4(a0, b0, a1, b1);
+}
+
+__global__ __launch_bounds__(kBlock) void probe_init_kernel(float4 *__restrict__ z_out, float4 *__restrict__ hz,
                                                              int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb,
                                                              int has_b, float lam) {
-    constexpr int NW = kBlock / 64;
-    __shared__ uint32_t words[NW][2][4][64];  // [wave][probe][word][block of the chunk]
+    __shared__ uint32_t words[kProbeWaves][2][4][64];  // [wave][probe][word][block of the chunk]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nchunk = (nvox + 8191) / 8192;
     const int64_t npair = nvox / 2;
-    for (int64_t c = (int64_t)blockIdx.x * NW + wv; c < nchunk; c += (int64_t)gridDim.x * NW) {
-        const uint32_t blk = (uint32_t)(c * 64 + lane);
-        const U4 ra = philox4x32_10(U4{blk, (uint32_t)pa, (uint32_t)(pa >> 32), kRademacherTag}, (uint32_t)seed,
-                                    (uint32_t)(seed >> 32));
-        U4 rb = U4{0u, 0u, 0u, 0u};
-        if (has_b)
-            rb = philox4x32_10(U4{blk, (uint32_t)pb, (uint32_t)(pb >> 32), kRademacherTag}, (uint32_t)seed,
-                               (uint32_t)(seed >> 32));
-        words[wv][0][0][lane] = ra.x;
-        words[wv][0][1][lane] = ra.y;
-        words[wv][0][2][lane] = ra.z;
-        words[wv][0][3][lane] = ra.w;
-        words[wv][1][0][lane] = rb.x;
-        words[wv][1][1][lane] = rb.y;
-        words[wv][1][2][lane] = rb.z;
-        words[wv][1][3][lane] = rb.w;
-        // the words were written by this wave: its LDS accesses complete in
-        // order, and the barrier keeps the compiler from moving them
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // store j: voxels c 8192 + 128 j + 2 lane (+1), bits 2 lane (+1) of
-        // block c 64 + j
-        const int w = lane >> 4, sh = (2 * lane) & 31;
+    for (int64_t c = (int64_t)blockIdx.x * kProbeWaves + wv; c < nchunk; c += (int64_t)gridDim.x * kProbeWaves) {
+        probe_chunk_bits(words[wv], c, lane, seed, pa, pb, has_b);
         for (int j = 0; j < 64; ++j) {
             const int64_t q = c * 4096 + (int64_t)j * 64 + lane;
             if (q >= npair) break;
-            const uint32_t ba = words[wv][0][w][j] >> sh, bb = words[wv][1][w][j] >> sh;
-            const float a0 = (ba & 1u) ? -1.f : 1.f, a1 = (ba & 2u) ? -1.f : 1.f;
-            const float b0 = has_b ? ((bb & 1u) ? -1.f : 1.f) : 0.f;
-            const float b1 = has_b ? ((bb & 2u) ? -1.f : 1.f) : 0.f;
-            z[q] = make_float4(a0, b0, a1, b1);
-            hz[q] = make_float4(lam * a0, lam * b0, lam * a1, lam * b1);
+            const float4 z = probe_pair_values(words[wv], j, lane, has_b);
+            if (z_out) z_out[q] = z;
+            hz[q] = make_float4(lam * z.x, lam * z.y, lam * z.z, lam * z.w);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -170,26 +164,50 @@ __global__ __launch_bounds__(kBlock) void probe_init_kernel(float4 *__restrict__
     }
 }
 
-// diag += w * (Re z Re hz + Im z Im hz)
-__global__ __launch_bounds__(kBlock) void zhz_accum_kernel(float *__restrict__ diag, const float2 *__restrict__ z,
-                                                            const float2 *__restrict__ hz, int64_t nvox, float w) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvox; k += stride) {
-        const float2 a = z[k], b = hz[k];
-        diag[k] = fmaf(w, fmaf(a.x, b.x, a.y * b.y), diag[k]);
-    }
-}
-
-// The same over pairs of voxels; with `first` the sum starts here (diag is not
-// read).  16-byte aligned z and hz, 8-byte aligned diag, nvox even.
-__global__ __launch_bounds__(kBlock) void zhz_accum2_kernel(float2 *__restrict__ diag, const float4 *__restrict__ z,
-                                                             const float4 *__restrict__ hz, int64_t npair, float w,
-                                                             int first) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npair; k += stride) {
-        const float4 a = z[k], b = hz[k];
-        const float2 d = first ? make_float2(0.f, 0.f) : diag[k];
-        diag[k] = make_float2(fmaf(w, fmaf(a.x, b.x, a.y * b.y), d.x), fmaf(w, fmaf(a.z, b.z, a.w * b.w), d.y));
+// diag += w (Re z Re hz + Im z Im hz) with z regenerated as above; with
+// `first` the sum starts here (diag is not read).  nvox even, hz 16-byte
+// aligned; diag is written as float pairs when it is 8-byte aligned.
+__global__ __launch_bounds__(kBlock) void zhz_hash_kernel(float *__restrict__ diag, const float4 *__restrict__ hz,
+                                                           int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb,
+                                                           int has_b, float w, int first) {
+    __shared__ uint32_t words[kProbeWaves][2][4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nchunk = (nvox + 8191) / 8192;
+    const int64_t npair = nvox / 2;
+    const bool pairs = ((uintptr_t)diag & 7u) == 0;
+    for (int64_t c = (int64_t)blockIdx.x * kProbeWaves + wv; c < nchunk; c += (int64_t)gridDim.x * kProbeWaves) {
+        probe_chunk_bits(words[wv], c, lane, seed, pa, pb, has_b);
+        // eight pairs per step, their loads issued together (addresses
+        // clamped into the volume; pairs past its end are not stored)
+        constexpr int U = 8;
+        for (int j0 = 0; j0 < 64; j0 += U) {
+            float4 h[U];
+            float2 d[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = min(c * 4096 + (int64_t)(j0 + u) * 64 + lane, npair - 1);
+                h[u] = hz[q];
+                d[u] = make_float2(0.f, 0.f);
+                if (!first) d[u] = pairs ? reinterpret_cast<const float2 *>(diag)[q] : make_float2(diag[2 * q], diag[2 * q + 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = c * 4096 + (int64_t)(j0 + u) * 64 + lane;
+                if (q >= npair) break;
+                const float4 z = probe_pair_values(words[wv], j0 + u, lane, has_b);
+                const float s0 = fmaf(z.x, h[u].x, z.y * h[u].y), s1 = fmaf(z.z, h[u].z, z.w * h[u].w);
+                const float2 r = make_float2(fmaf(w, s0, d[u].x), fmaf(w, s1, d[u].y));
+                if (pairs) {
+                    reinterpret_cast<float2 *>(diag)[q] = r;
+                } else {
+                    diag[2 * q] = r.x;
+                    diag[2 * q + 1] = r.y;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -396,38 +414,25 @@ hipError_t launch_rademacher(float *z, int64_t nvox, uint64_t seed, uint64_t pro
     return hipGetLastError();
 }
 
-hipError_t launch_rademacher_pair(float2 *z, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(rademacher_pair_kernel, dim3(stream_blocks((nvox + 3) / 4)), dim3(kBlock), 0, st, z, nvox,
-                       seed, pa, pb, has_b);
-    return hipGetLastError();
-}
-
 hipError_t launch_probe_init(float2 *z, float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb, int has_b,
                              float lam, hipStream_t st) {
     // z and hz live in the (256-byte aligned) workspace and nvox = M^3 is even
-    if (nvox % 2 != 0 || !aligned(z, 16) || !aligned(hz, 16)) return hipErrorInvalidValue;
+    if (nvox % 2 != 0 || !aligned(hz, 16) || !aligned(z, 16)) return hipErrorInvalidValue;
     // one wave per 8192 voxels, four waves per block
-    int64_t blocks = ((nvox + 8191) / 8192 + kBlock / 64 - 1) / (kBlock / 64);
+    int64_t blocks = ((nvox + 8191) / 8192 + kProbeWaves - 1) / kProbeWaves;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(probe_init_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, (float4 *)z, (float4 *)hz, nvox,
                        seed, pa, pb, has_b, lam);
     return hipGetLastError();
 }
 
-hipError_t launch_zhz_accum(float *diag, const float2 *z, const float2 *hz, int64_t nvox, float w, bool first,
-                            hipStream_t st) {
-    if (nvox % 2 == 0 && aligned(diag, 8) && aligned(z, 16) && aligned(hz, 16)) {
-        const int64_t np = nvox / 2;
-        hipLaunchKernelGGL(zhz_accum2_kernel, dim3(stream_blocks(np)), dim3(kBlock), 0, st, (float2 *)diag,
-                           (const float4 *)z, (const float4 *)hz, np, w, first ? 1 : 0);
-        return hipGetLastError();
-    }
-    if (first) {
-        hipError_t e = launch_fill_f32(diag, nvox, 0.0f, st);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(zhz_accum_kernel, dim3(stream_blocks(nvox)), dim3(kBlock), 0, st, diag, z, hz, nvox, w);
+hipError_t launch_zhz_hash(float *diag, const float2 *hz, int64_t nvox, uint64_t seed, uint64_t pa, uint64_t pb,
+                           int has_b, float w, bool first, hipStream_t st) {
+    if (nvox % 2 != 0 || !aligned(hz, 16)) return hipErrorInvalidValue;
+    int64_t blocks = ((nvox + 8191) / 8192 + kProbeWaves - 1) / kProbeWaves;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zhz_hash_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, diag, (const float4 *)hz, nvox,
+                       seed, pa, pb, has_b, w, first ? 1 : 0);
     return hipGetLastError();
 }
 
