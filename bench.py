@@ -145,7 +145,8 @@ def main():
     # plain forward + adjoint of the batch
     y = torch.empty_like(x_b)
     acc = torch.zeros_like(v_true)
-    ws_bp = B.alloc_workspace(grid, Bsz, B.CSG_WS_BACKPROJECT, dev)
+    ws_bp = B.alloc_workspace(grid, Bsz, B.CSG_WS_BACKPROJECT_DETERMINISTIC if args.deterministic
+                              else B.CSG_WS_BACKPROJECT, dev)
     B.timing_enable(True)
     for k in B.KERNELS:
         B.timing_read(k)
