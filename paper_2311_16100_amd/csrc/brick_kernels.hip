@@ -479,9 +479,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     constexpr bool QLDS = FX || (CSG_LDS_FIXED && SCATTER && !PK_ALWAYS);
     constexpr bool QITEM = QLDS && !FX;
     // the item bound needs the largest staged volume value (gradient, HVP)
-    // and the images' bound from the set-up pass (backproject, gradient)
+    // and, where images are read (backproject, gradient), a bound on their
+    // values: a guess, checked against every value read; an item that meets
+    // a larger one is redone with its exact maximum (see the retry below)
     constexpr bool STAGE_MAX = PK_ALWAYS || (QITEM && GATHER);
-    constexpr bool IMG_BOUND = QITEM && READS_IMG;
+    constexpr bool XRETRY = QITEM && READS_IMG;
     __shared__ float2 vh[GATHER ? XN : 1];
     __shared__ double acc_re[SCATTER ? XN : 1];
     __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN : 1];
@@ -492,6 +494,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
     __shared__ unsigned s_wmax[kBT / 64];
+    __shared__ unsigned s_xmax[kBT / 64];
     // probe HVP: signs of the staged rows ([row][probe]; see the staging)
     __shared__ uint32_t s_zmask[MODE == kBHvpProbe ? BX * BX : 1][2];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
@@ -514,8 +517,37 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     double lsum = 0.0;
     double fxS = 1.0;
     if (FX) fxS = fx_scale(a.fx_max, a.scale, a.n_total).S;
-    float img_bound = 0.f;
-    if (IMG_BOUND) img_bound = __uint_as_float(a.fx_max[0]);
+    // the block's largest |re| + |im| of image values so far (float bits with
+    // the sign cleared, which order like the values and keep a NaN), started
+    // from a sample of disk pixels: per thread one of the 5 x 5 lowest
+    // frequencies (where the largest values of a Fourier-space image sit) of
+    // one image and one pixel spread over the disk of another
+    // (in LDS, to keep registers for the pixel loop: s_xseen is thread 0's,
+    // s_guess the item's guess, written by thread 0 and read after a barrier)
+    __shared__ unsigned s_xseen, s_guess;
+    if (XRETRY) {
+        int rr = (int)sqrtf(0.5f * (float)g.k2max);  // |kx|, |ky| <= rr lies in the disk
+        while (rr > 0 && 2 * rr * rr > g.k2max) --rr;
+        const int side = 2 * rr + 1, t = (int)threadIdx.x;
+        const int rc = min(rr, 2), sc = 2 * rc + 1;
+        const int cx = t % sc - rc, cy = (t / sc) % sc - rc;
+        const int kx = (t * 13 + (int)blockIdx.x) % side - rr, ky = (t * 7 + 3 * (int)blockIdx.x) % side - rr;
+        const int64_t i0 = ((int64_t)blockIdx.x * (kBT / (sc * sc) + 1) + t / (sc * sc)) % a.n;
+        const int64_t i1 = ((int64_t)blockIdx.x * kBT + t) % a.n;
+        const float2 u = a.img[(i0 * M + (cy + g.half)) * (int64_t)M + (cx + g.half)];
+        const float2 v = a.img[(i1 * M + (ky + g.half)) * (int64_t)M + (kx + g.half)];
+        unsigned b = max(__float_as_uint(fabsf(u.x) + fabsf(u.y)) & 0x7fffffffu,
+                         __float_as_uint(fabsf(v.x) + fabsf(v.y)) & 0x7fffffffu);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) b = max(b, (unsigned)__shfl_xor((int)b, off, 64));
+        if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned m = 0u;
+            for (int w = 0; w < kBT / 64; ++w) m = max(m, s_wmax[w]);
+            s_xseen = m;
+        }
+    }
 
     // work items are taken from the planned list (heaviest first) until it
     // is exhausted
@@ -649,10 +681,13 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         }
         PackedScale pk;  // set in the first window (after a barrier)
         ItemScale qs;    // likewise
-        // modes without a gathered value: the bound is known before the item
-        // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2)
-        if (QITEM && !GATHER)
-            qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale) * (READS_IMG ? (double)img_bound : 1.0));
+        // the image-value guess of the item: twice the block's maximum so far
+        // (the exponent raised by one, at most the largest float; a NaN or an
+        // infinity stays and gives a NaN flush)
+        if (XRETRY && threadIdx.x == 0) {
+            const unsigned xs = s_xseen;
+            s_guess = xs >= 0x7f800000u ? xs : min(xs + (1u << 23), 0x7f7fffffu);
+        }
         // enumeration box (grid coordinates): the brick's pixels have floor(g)
         // in the brick
         float lo[3], hi[3];
@@ -668,6 +703,13 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         const uint32_t MM = (uint32_t)M * (uint32_t)M;
         const uint32_t pix_off = (uint32_t)g.half * (uint32_t)M + (uint32_t)g.half;
 
+        for (int attempt = 0;; ++attempt) {
+        unsigned xmax_item = 0u;  // this thread's largest image value of the item
+        // modes without a gathered value: the bound is known before the item
+        // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2;
+        // backproject: |scale| times the image guess, set in the first window)
+        if (QITEM && !GATHER && !READS_IMG)
+            qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
         for (int w0 = 0; w0 < n_img; w0 += WI) {
             const int nw = min(WI, n_img - w0);
             // every wave has finished with the previous window's tables
@@ -678,8 +720,14 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
                 const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
                 if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
-                if (QITEM) qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + (double)img_bound));
+                if (QITEM) {
+                    const double xg = READS_IMG ? (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)) : 0.0;
+                    qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
+                }
             }
+            if (QITEM && !GATHER && READS_IMG && w0 == 0)
+                qs = ItemScale::make(fabs((double)a.scale) *
+                                     (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
             // ---- the window's images (one thread each): constants, first row,
             // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
             // MAXROWS - 1 of the window; those past its row count stay empty.
@@ -879,7 +927,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                     }
                                     if (a.out) a.out[j] = y;
                                     lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
-                                } else if (MODE == kBBackproject) {
+                                }
+                                if (XRETRY)
+                                    xmax_item = max(xmax_item, __float_as_uint(fabsf(xin[jj].x) + fabsf(xin[jj].y)) &
+                                                                   0x7fffffffu);
+                                if (MODE == kBBackproject) {
                                     const float2 x = cmul_conj(xin[jj], T);
                                     const float fct = a.scale * ctf_pow(C, a.ctf_power);
                                     val = make_float2(fct * x.x, fct * x.y);
@@ -931,6 +983,39 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
             }
         }
+        if (!XRETRY) break;
+        // the item's largest image value; above the guess, a fixed-point sum
+        // may have overflowed, and the item is redone with that maximum as
+        // its bound (which no value of the item can exceed, so once at most)
+        {
+            unsigned m = xmax_item;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+            if ((threadIdx.x & 63) == 0) s_xmax[threadIdx.x >> 6] = m;
+            const unsigned guess = __builtin_amdgcn_readfirstlane(s_guess);  // read before thread 0 may change it
+            __syncthreads();
+            unsigned im = 0u;
+#pragma unroll
+            for (int w = 0; w < kBT / 64; ++w) im = max(im, s_xmax[w]);
+            im = __builtin_amdgcn_readfirstlane(im);
+            if (threadIdx.x == 0) s_xseen = max(s_xseen, im);
+            if (im <= guess || attempt > 0) {
+                // the item's loss terms, added once the item is accepted
+                if (MODE == kBGradient && a.loss) {
+                    const double t = block_sum(lsum, red);
+                    if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
+                }
+                lsum = 0.0;
+                break;
+            }
+            if (threadIdx.x == 0) s_guess = im;  // read after the next window's barrier
+            lsum = 0.0;
+            for (int t = threadIdx.x; t < XN; t += kBT) {
+                acc_re[t] = 0.0;
+                acc_im[t] = 0.0;
+            }
+        }
+        }  // attempts
 
         if (SCATTER) {
             __syncthreads();
@@ -985,7 +1070,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         }
     }  // work items
 
-    if ((MODE == kBProject || MODE == kBGradient) && a.loss) {
+    // (the gradient with the retry adds its loss per item)
+    if ((MODE == kBProject || (MODE == kBGradient && !XRETRY)) && a.loss) {
         const double t = block_sum(lsum, red);
         if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
     }
@@ -1081,16 +1167,6 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
     const int grid = (int)(resident_blocks<MODE, FX>() < max_items ? resident_blocks<MODE, FX>() : max_items);
-    // the fast backproject and gradient bound their LDS sums with the largest
-    // |re| + |im| of the images (one pass over them, into the work-list
-    // scalars)
-    constexpr bool img_bound = CSG_LDS_FIXED && !FX && (MODE == kBBackproject || MODE == kBGradient);
-    unsigned *img_bits = (unsigned *)(scalars + 2);
-    if (img_bound) {
-        hipError_t e = launch_fill_f32((float *)img_bits, 1, 0.0f, st);  // zero bits
-        if (e == hipSuccess) e = launch_img_absmax(g, img, n, img_bits, st);
-        if (e != hipSuccess) return e;
-    }
     for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
         const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
         const int stride = (int)ns;
@@ -1128,8 +1204,6 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
             a.fx = fb->fx;
             a.fx_max = fb->maxbits;
             a.n_total = n;
-        } else if (img_bound) {
-            a.fx_max = img_bits;
         }
         if (probe) {
             a.probe_seed = probe->seed;
