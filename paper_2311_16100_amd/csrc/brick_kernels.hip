@@ -362,7 +362,7 @@ struct Win {
     static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
-    static constexpr int RUNCAP = MODE == kBProject ? 3072 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : 2048;
+    static constexpr int RUNCAP = MODE == kBProject ? 7168 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : 2048;
 };
 
 __device__ __forceinline__ double rint_scaled(float e) {
