@@ -597,8 +597,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                         const uint64_t probe = p ? a.probe_b : a.probe_a;
                         const uint32_t b0 = (uint32_t)(g0 >> 7);
                         const U4 r0 = rademacher_block(a.probe_seed, probe, b0);
-                        const U4 r1 = (uint32_t)((g0 + nx - 1) >> 7) != b0 ? rademacher_block(a.probe_seed, probe, b0 + 1)
-                                                                            : r0;
+                        const bool two = (uint32_t)((g0 + nx - 1) >> 7) != b0;
+                        const U4 r1 = two ? rademacher_block(a.probe_seed, probe, b0 + 1) : r0;
                         // the 13 bits from bit (g0 mod 128) on, in the words
                         // r0.x .. r0.w r1.x r1.y (a run of 13 spans at most
                         // two consecutive words)
@@ -704,317 +704,319 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         const uint32_t pix_off = (uint32_t)g.half * (uint32_t)M + (uint32_t)g.half;
 
         for (int attempt = 0;; ++attempt) {
-        unsigned xmax_item = 0u;  // this thread's largest image value of the item
-        // modes without a gathered value: the bound is known before the item
-        // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2;
-        // backproject: |scale| times the image guess, set in the first window)
-        if (QITEM && !GATHER && !READS_IMG)
-            qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
-        for (int w0 = 0; w0 < n_img; w0 += WI) {
-            const int nw = min(WI, n_img - w0);
-            // every wave has finished with the previous window's tables
-            __syncthreads();
-            if (STAGE_MAX && w0 == 0) {
-                unsigned zbits = 0u;
-#pragma unroll
-                for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
-                const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
-                if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
-                if (QITEM) {
-                    const double xg = READS_IMG ? (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)) : 0.0;
-                    qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
-                }
-            }
-            if (QITEM && !GATHER && READS_IMG && w0 == 0)
-                qs = ItemScale::make(fabs((double)a.scale) *
-                                     (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
-            // ---- the window's images (one thread each): constants, first row,
-            // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
-            // MAXROWS - 1 of the window; those past its row count stay empty.
-            const int t = (int)threadIdx.x;
-            if (t < nw) {
-                {
-                    ImgSlot &S = slot[t];
-                    const float *D = imgdat[w0 + t];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        S.E1[d] = rint_scaled(D[1 + d]);
-                        S.E2[d] = rint_scaled(D[4 + d]);
-                        S.E1i[d] = (int64_t)S.E1[d];
-                    }
-                    S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
-                    S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
-                    if (SHIFTED) {
-                        S.sx = D[IMGDAT - 2];
-                        S.sy = D[IMGDAT - 1];
-                    }
-                    // rows: range of e2 . (g - half) over the box
-                    float ylo = 0.f, yhi = 0.f;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const float u = D[4 + d] * (lo[d] - halff), w = D[4 + d] * (hi[d] - halff);
-                        ylo += fminf(u, w);
-                        yhi += fmaxf(u, w);
-                    }
-                    // range tests in floating point first, so only bounded values
-                    // are converted
-                    const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
-                    const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
-                    if (fl <= fh) {
-                        S.ky_lo = (short)(int)fl;
-                        S.nrows = (unsigned short)min((int)fh - (int)fl + 1, MAXROWS);
-                    } else {
-                        S.ky_lo = 0;
-                        S.nrows = 0;
-                    }
-                }
-            }
-
-            __syncthreads();
-            const int n_rows = nw * MAXROWS;
-            // ---- row intervals (kx range whose cells reach the box), runs per row
-            int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
-            int myruns = 0;
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int r = threadIdx.x + k * kBT;
-                rlen[k] = 0;
-                rkx0[k] = 0;
-                rky[k] = 0;
-                rsl[k] = 0;
-                const int s = r / MAXROWS;
-                const int q = r - s * MAXROWS;
-                if (r < n_rows && q < (int)slot[s].nrows) {
-                    const ImgSlot &S = slot[s];
-                    const int ky = S.ky_lo + q;
-                    const float *D = imgdat[w0 + s];
-                    const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
-                    int x0, x1;
-                    clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
-                    // the disk: |kx| <= floor(sqrt(k2max - ky^2))
-                    const int rem = g.k2max - ky * ky;
-                    int kxm = (int)sqrtf((float)max(rem, 0));
-                    while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
-                    while (kxm > 0 && kxm * kxm > rem) --kxm;
-                    x0 = max(x0, -kxm);
-                    x1 = min(x1, kxm);
-                    if (rem >= 0 && x1 >= x0) {
-                        rlen[k] = min(x1 - x0 + 1, MAXLEN);
-                        rkx0[k] = x0;
-                    }
-                    rky[k] = ky;
-                    rsl[k] = s;
-                }
-                myruns += (rlen[k] + RUN - 1) / RUN;
-            }
-            int T;
-            {
-                int p = block_exclusive_scan(myruns, wave_sums, &T);
-                T = __builtin_amdgcn_readfirstlane(T);
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int r = threadIdx.x + k * kBT;
-                    if (r < n_rows)
-                        seg[r] = make_int2(p | (rlen[k] << 16) | (rsl[k] << 24),
-                                           (rkx0[k] + 32768) | ((rky[k] + 32768) << 16));
-                    p += (rlen[k] + RUN - 1) / RUN;
-                }
-            }
-
-            for (int wbase = 0; wbase < T; wbase += RUNCAP) {
-                // ---- run -> row table of this pass (each thread fills the runs
-                // of its own rows, read back from their records)
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int r = threadIdx.x + k * kBT;
-                    if (r < n_rows) {
-                        const int x = seg[r].x;
-                        const int rs = x & 0xFFFF, nr = (((x >> 16) & 0xFF) + RUN - 1) / RUN;
-                        const int b0 = max(rs, wbase), b1 = min(rs + nr, wbase + RUNCAP);
-                        for (int q = b0; q < b1; ++q) run2row[q - wbase] = (unsigned short)r;
-                    }
-                }
+            unsigned xmax_item = 0u;  // this thread's largest image value of the item
+            // modes without a gathered value: the bound is known before the item
+            // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2;
+            // backproject: |scale| times the image guess, set in the first window)
+            if (QITEM && !GATHER && !READS_IMG)
+                qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
+            for (int w0 = 0; w0 < n_img; w0 += WI) {
+                const int nw = min(WI, n_img - w0);
+                // every wave has finished with the previous window's tables
                 __syncthreads();
-                const int wend = min(T, wbase + RUNCAP);
-                for (int u = wbase + threadIdx.x; u < wend; u += kBT) {
-                    const int2 rec = seg[run2row[u - wbase]];
-                    const int rs = rec.x & 0xFFFF;
-                    const int len = (rec.x >> 16) & 0xFF;
-                    const ImgSlot &I = slot[(unsigned)rec.x >> 24];
-                    const int kx0 = (rec.y & 0xFFFF) - 32768;
-                    const int ky = (int)((unsigned)rec.y >> 16) - 32768;
-                    const int j0 = (u - rs) * RUN;
-                    const int kxs = kx0 + j0;
-                    const int cnt = min(RUN, len - j0);
-                    const uint32_t jrun = I.img_base + pix_off + (uint32_t)(ky * M) + (uint32_t)kxs;
-                    // the run's image values are requested first, so that their
-                    // latency overlaps the sample-point arithmetic (every pixel of
-                    // a run lies in the disk, hence inside its image)
-                    float2 xin[RUN];
+                if (STAGE_MAX && w0 == 0) {
+                    unsigned zbits = 0u;
 #pragma unroll
-                    for (int jj = 0; jj < RUN; ++jj) {
-                        xin[jj] = make_float2(0.f, 0.f);
-                        if (READS_IMG && a.img && jj < cnt) xin[jj] = a.img[jrun + jj];
+                    for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
+                    const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
+                    if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
+                    if (QITEM) {
+                        const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
+                        const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
+                        qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
                     }
-                    // fixed-point sample point of the run's first pixel (exact)
-                    int64_t G[3];
+                }
+                if (QITEM && !GATHER && READS_IMG && w0 == 0)
+                    qs = ItemScale::make(fabs((double)a.scale) *
+                                         (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
+                // ---- the window's images (one thread each): constants, first row,
+                // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
+                // MAXROWS - 1 of the window; those past its row count stay empty.
+                const int t = (int)threadIdx.x;
+                if (t < nw) {
+                    {
+                        ImgSlot &S = slot[t];
+                        const float *D = imgdat[w0 + t];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double gd = fma((double)kxs, I.E1[d], fma((double)ky, I.E2[d], halfG));
-                        const double h = floor(gd * 0x1p-32);
-                        const uint32_t l32 = (uint32_t)fma(-h, 0x1p32, gd);
-                        G[d] = (int64_t)(((uint64_t)(uint32_t)(int)h << 32) | l32);
+                        for (int d = 0; d < 3; ++d) {
+                            S.E1[d] = rint_scaled(D[1 + d]);
+                            S.E2[d] = rint_scaled(D[4 + d]);
+                            S.E1i[d] = (int64_t)S.E1[d];
+                        }
+                        S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
+                        S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
+                        if (SHIFTED) {
+                            S.sx = D[IMGDAT - 2];
+                            S.sy = D[IMGDAT - 1];
+                        }
+                        // rows: range of e2 . (g - half) over the box
+                        float ylo = 0.f, yhi = 0.f;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const float u = D[4 + d] * (lo[d] - halff), w = D[4 + d] * (hi[d] - halff);
+                            ylo += fminf(u, w);
+                            yhi += fmaxf(u, w);
+                        }
+                        // range tests in floating point first, so only bounded values
+                        // are converted
+                        const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
+                        const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
+                        if (fl <= fh) {
+                            S.ky_lo = (short)(int)fl;
+                            S.nrows = (unsigned short)min((int)fh - (int)fl + 1, MAXROWS);
+                        } else {
+                            S.ky_lo = 0;
+                            S.nrows = 0;
+                        }
                     }
-                    const int64_t E1i[3] = {I.E1i[0], I.E1i[1], I.E1i[2]};
-                    const double ctfA = I.ctfA;
-                    const int ky2 = ky * ky;
+                }
+
+                __syncthreads();
+                const int n_rows = nw * MAXROWS;
+                // ---- row intervals (kx range whose cells reach the box), runs per row
+                int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
+                int myruns = 0;
 #pragma unroll
-                    for (int jj = 0; jj < RUN; ++jj) {
-                        if (jj < cnt) {
-                            int l[3];
-                            float t[3];
+                for (int k = 0; k < RPT; ++k) {
+                    const int r = threadIdx.x + k * kBT;
+                    rlen[k] = 0;
+                    rkx0[k] = 0;
+                    rky[k] = 0;
+                    rsl[k] = 0;
+                    const int s = r / MAXROWS;
+                    const int q = r - s * MAXROWS;
+                    if (r < n_rows && q < (int)slot[s].nrows) {
+                        const ImgSlot &S = slot[s];
+                        const int ky = S.ky_lo + q;
+                        const float *D = imgdat[w0 + s];
+                        const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
+                        int x0, x1;
+                        clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
+                        // the disk: |kx| <= floor(sqrt(k2max - ky^2))
+                        const int rem = g.k2max - ky * ky;
+                        int kxm = (int)sqrtf((float)max(rem, 0));
+                        while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
+                        while (kxm > 0 && kxm * kxm > rem) --kxm;
+                        x0 = max(x0, -kxm);
+                        x1 = min(x1, kxm);
+                        if (rem >= 0 && x1 >= x0) {
+                            rlen[k] = min(x1 - x0 + 1, MAXLEN);
+                            rkx0[k] = x0;
+                        }
+                        rky[k] = ky;
+                        rsl[k] = s;
+                    }
+                    myruns += (rlen[k] + RUN - 1) / RUN;
+                }
+                int T;
+                {
+                    int p = block_exclusive_scan(myruns, wave_sums, &T);
+                    T = __builtin_amdgcn_readfirstlane(T);
 #pragma unroll
-                            for (int d = 0; d < 3; ++d) {
-                                l[d] = (int)(G[d] >> 32) - o[d];  // base corner relative to the brick
-                                t[d] = (float)(uint32_t)G[d] * 0x1p-32f;
-                            }
-                            const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
-                                               (unsigned)l[2] < (unsigned)BS;
-                            if (owned) {
-                                const int kx = kxs + jj;
-                                float C = 1.0f;
-                                if (g.ctf_on) {
-                                    const double k2 = (double)(kx * kx + ky2);
-                                    const double turns = fma(fma(-ctfB, k2, ctfA), k2, g.phase0);
-                                    C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
+                    for (int k = 0; k < RPT; ++k) {
+                        const int r = threadIdx.x + k * kBT;
+                        if (r < n_rows)
+                            seg[r] = make_int2(p | (rlen[k] << 16) | (rsl[k] << 24),
+                                               (rkx0[k] + 32768) | ((rky[k] + 32768) << 16));
+                        p += (rlen[k] + RUN - 1) / RUN;
+                    }
+                }
+
+                for (int wbase = 0; wbase < T; wbase += RUNCAP) {
+                    // ---- run -> row table of this pass (each thread fills the runs
+                    // of its own rows, read back from their records)
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const int r = threadIdx.x + k * kBT;
+                        if (r < n_rows) {
+                            const int x = seg[r].x;
+                            const int rs = x & 0xFFFF, nr = (((x >> 16) & 0xFF) + RUN - 1) / RUN;
+                            const int b0 = max(rs, wbase), b1 = min(rs + nr, wbase + RUNCAP);
+                            for (int q = b0; q < b1; ++q) run2row[q - wbase] = (unsigned short)r;
+                        }
+                    }
+                    __syncthreads();
+                    const int wend = min(T, wbase + RUNCAP);
+                    for (int u = wbase + threadIdx.x; u < wend; u += kBT) {
+                        const int2 rec = seg[run2row[u - wbase]];
+                        const int rs = rec.x & 0xFFFF;
+                        const int len = (rec.x >> 16) & 0xFF;
+                        const ImgSlot &I = slot[(unsigned)rec.x >> 24];
+                        const int kx0 = (rec.y & 0xFFFF) - 32768;
+                        const int ky = (int)((unsigned)rec.y >> 16) - 32768;
+                        const int j0 = (u - rs) * RUN;
+                        const int kxs = kx0 + j0;
+                        const int cnt = min(RUN, len - j0);
+                        const uint32_t jrun = I.img_base + pix_off + (uint32_t)(ky * M) + (uint32_t)kxs;
+                        // the run's image values are requested first, so that their
+                        // latency overlaps the sample-point arithmetic (every pixel of
+                        // a run lies in the disk, hence inside its image)
+                        float2 xin[RUN];
+#pragma unroll
+                        for (int jj = 0; jj < RUN; ++jj) {
+                            xin[jj] = make_float2(0.f, 0.f);
+                            if (READS_IMG && a.img && jj < cnt) xin[jj] = a.img[jrun + jj];
+                        }
+                        // fixed-point sample point of the run's first pixel (exact)
+                        int64_t G[3];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double gd = fma((double)kxs, I.E1[d], fma((double)ky, I.E2[d], halfG));
+                            const double h = floor(gd * 0x1p-32);
+                            const uint32_t l32 = (uint32_t)fma(-h, 0x1p32, gd);
+                            G[d] = (int64_t)(((uint64_t)(uint32_t)(int)h << 32) | l32);
+                        }
+                        const int64_t E1i[3] = {I.E1i[0], I.E1i[1], I.E1i[2]};
+                        const double ctfA = I.ctfA;
+                        const int ky2 = ky * ky;
+#pragma unroll
+                        for (int jj = 0; jj < RUN; ++jj) {
+                            if (jj < cnt) {
+                                int l[3];
+                                float t[3];
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) {
+                                    l[d] = (int)(G[d] >> 32) - o[d];  // base corner relative to the brick
+                                    t[d] = (float)(uint32_t)G[d] * 0x1p-32f;
                                 }
-                                const uint32_t j = jrun + (uint32_t)jj;
-                                const float wx[2] = {1.0f - t[0], t[0]};
-                                const float wy[2] = {1.0f - t[1], t[1]};
-                                const float wz[2] = {1.0f - t[2], t[2]};
-                                float2 acc = make_float2(0.f, 0.f);
-                                // index of the base corner in the extended brick; the
-                                // eight corners lie in it
-                                const int lb = (l[2] * XR + l[1]) * XR + l[0];
-                                if (GATHER) {
-                                    // staged voxels outside the grid hold zeros, which
-                                    // drops those corners
-#pragma unroll
-                                    for (int c = 0; c < 8; ++c) {
-                                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                        const float w = wx[ax] * wy[ay] * wz[az];
-                                        const float2 v = vh[lb + az * XP + ay * XR + ax];
-                                        acc.x = fmaf(w, v.x, acc.x);
-                                        acc.y = fmaf(w, v.y, acc.y);
+                                const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
+                                                   (unsigned)l[2] < (unsigned)BS;
+                                if (owned) {
+                                    const int kx = kxs + jj;
+                                    float C = 1.0f;
+                                    if (g.ctf_on) {
+                                        const double k2 = (double)(kx * kx + ky2);
+                                        const double turns = fma(fma(-ctfB, k2, ctfA), k2, g.phase0);
+                                        C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
                                     }
-                                }
-                                // in-plane shift: T on the forward value, conj(T)
-                                // on the adjoint input
-                                float2 T = make_float2(1.f, 0.f);
-                                if (SHIFTED) {
-                                    const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
-                                                      (double)M;
-                                    const float fr = (float)(tt - rint(tt));
-                                    T = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
-                                    if (GATHER) acc = cmul(acc, T);
-                                }
-                                float2 val = make_float2(0.f, 0.f);
-                                if (MODE == kBProject) {
-                                    float2 y = make_float2(C * acc.x, C * acc.y);
-                                    if (a.img) {
-                                        y.x -= xin[jj].x;
-                                        y.y -= xin[jj].y;
-                                    }
-                                    if (a.out) a.out[j] = y;
-                                    lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
-                                }
-                                if (XRETRY)
-                                    xmax_item = max(xmax_item, __float_as_uint(fabsf(xin[jj].x) + fabsf(xin[jj].y)) &
-                                                                   0x7fffffffu);
-                                if (MODE == kBBackproject) {
-                                    const float2 x = cmul_conj(xin[jj], T);
-                                    const float fct = a.scale * ctf_pow(C, a.ctf_power);
-                                    val = make_float2(fct * x.x, fct * x.y);
-                                } else if (MODE == kBGradient) {
-                                    const float2 x = xin[jj];
-                                    const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
-                                    lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
-                                    const float fct = a.scale * C;
-                                    const float2 rt = cmul_conj(rr, T);
-                                    val = make_float2(fct * rt.x, fct * rt.y);
-                                } else if (is_hvp(MODE)) {
-                                    const float fct = a.scale * C * C;
-                                    val = make_float2(fct * acc.x, fct * acc.y);
-                                } else if (MODE == kBFeatures) {
-                                    val = make_float2(C * C, 1.0f);
-                                } else if (MODE == kBSqDiag) {
-                                    val = make_float2(a.scale * C * C, 0.0f);
-                                }
-                                if (SCATTER) {
-                                    // all eight corners; a corner beyond the grid edge
-                                    // lands in a slot that is never written back
+                                    const uint32_t j = jrun + (uint32_t)jj;
+                                    const float wx[2] = {1.0f - t[0], t[0]};
+                                    const float wy[2] = {1.0f - t[1], t[1]};
+                                    const float wz[2] = {1.0f - t[2], t[2]};
+                                    float2 acc = make_float2(0.f, 0.f);
+                                    // index of the base corner in the extended brick; the
+                                    // eight corners lie in it
+                                    const int lb = (l[2] * XR + l[1]) * XR + l[0];
+                                    if (GATHER) {
+                                        // staged voxels outside the grid hold zeros, which
+                                        // drops those corners
 #pragma unroll
-                                    for (int c = 0; c < 8; ++c) {
-                                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                        const float w = wx[ax] * wy[ay] * wz[az];
-                                        const int li = lb + az * XP + ay * XR + ax;
-                                        if (MODE == kBSqDiag && QLDS) {
-                                            atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
-                                        } else if (MODE == kBSqDiag) {
-                                            atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                                        } else if (PK_ALWAYS) {
-                                            atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
-                                        } else if (QLDS) {
-                                            const double S = FX ? fxS : qs.S;
-                                            atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
-                                            atomicAdd(&acc_qim[li], fx_quant(w * val.y, S));
-                                        } else {
-                                            atomicAdd(&acc_re[li], (double)(w * val.x));
-                                            atomicAdd(&acc_im[li], (double)(w * val.y));
+                                        for (int c = 0; c < 8; ++c) {
+                                            const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                            const float w = wx[ax] * wy[ay] * wz[az];
+                                            const float2 v = vh[lb + az * XP + ay * XR + ax];
+                                            acc.x = fmaf(w, v.x, acc.x);
+                                            acc.y = fmaf(w, v.y, acc.y);
+                                        }
+                                    }
+                                    // in-plane shift: T on the forward value, conj(T)
+                                    // on the adjoint input
+                                    float2 T = make_float2(1.f, 0.f);
+                                    if (SHIFTED) {
+                                        const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
+                                                          (double)M;
+                                        const float fr = (float)(tt - rint(tt));
+                                        T = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+                                        if (GATHER) acc = cmul(acc, T);
+                                    }
+                                    float2 val = make_float2(0.f, 0.f);
+                                    if (MODE == kBProject) {
+                                        float2 y = make_float2(C * acc.x, C * acc.y);
+                                        if (a.img) {
+                                            y.x -= xin[jj].x;
+                                            y.y -= xin[jj].y;
+                                        }
+                                        if (a.out) a.out[j] = y;
+                                        lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
+                                    }
+                                    if (XRETRY) {
+                                        const float xa = fabsf(xin[jj].x) + fabsf(xin[jj].y);
+                                        xmax_item = max(xmax_item, __float_as_uint(xa) & 0x7fffffffu);
+                                    }
+                                    if (MODE == kBBackproject) {
+                                        const float2 x = cmul_conj(xin[jj], T);
+                                        const float fct = a.scale * ctf_pow(C, a.ctf_power);
+                                        val = make_float2(fct * x.x, fct * x.y);
+                                    } else if (MODE == kBGradient) {
+                                        const float2 x = xin[jj];
+                                        const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
+                                        lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                                        const float fct = a.scale * C;
+                                        const float2 rt = cmul_conj(rr, T);
+                                        val = make_float2(fct * rt.x, fct * rt.y);
+                                    } else if (is_hvp(MODE)) {
+                                        const float fct = a.scale * C * C;
+                                        val = make_float2(fct * acc.x, fct * acc.y);
+                                    } else if (MODE == kBFeatures) {
+                                        val = make_float2(C * C, 1.0f);
+                                    } else if (MODE == kBSqDiag) {
+                                        val = make_float2(a.scale * C * C, 0.0f);
+                                    }
+                                    if (SCATTER) {
+                                        // all eight corners; a corner beyond the grid edge
+                                        // lands in a slot that is never written back
+#pragma unroll
+                                        for (int c = 0; c < 8; ++c) {
+                                            const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                            const float w = wx[ax] * wy[ay] * wz[az];
+                                            const int li = lb + az * XP + ay * XR + ax;
+                                            if (MODE == kBSqDiag && QLDS) {
+                                                atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
+                                            } else if (MODE == kBSqDiag) {
+                                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                                            } else if (PK_ALWAYS) {
+                                                atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
+                                            } else if (QLDS) {
+                                                const double S = FX ? fxS : qs.S;
+                                                atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
+                                                atomicAdd(&acc_qim[li], fx_quant(w * val.y, S));
+                                            } else {
+                                                atomicAdd(&acc_re[li], (double)(w * val.x));
+                                                atomicAdd(&acc_im[li], (double)(w * val.y));
+                                            }
                                         }
                                     }
                                 }
                             }
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) G[d] += E1i[d];
                         }
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) G[d] += E1i[d];
                     }
+                    __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
                 }
-                __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
             }
-        }
-        if (!XRETRY) break;
-        // the item's largest image value; above the guess, a fixed-point sum
-        // may have overflowed, and the item is redone with that maximum as
-        // its bound (which no value of the item can exceed, so once at most)
-        {
-            unsigned m = xmax_item;
+            if (!XRETRY) break;
+            // the item's largest image value; above the guess, a fixed-point sum
+            // may have overflowed, and the item is redone with that maximum as
+            // its bound (which no value of the item can exceed, so once at most)
+            {
+                unsigned m = xmax_item;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
-            if ((threadIdx.x & 63) == 0) s_xmax[threadIdx.x >> 6] = m;
-            const unsigned guess = __builtin_amdgcn_readfirstlane(s_guess);  // read before thread 0 may change it
-            __syncthreads();
-            unsigned im = 0u;
+                for (int off = 32; off >= 1; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+                if ((threadIdx.x & 63) == 0) s_xmax[threadIdx.x >> 6] = m;
+                const unsigned guess = __builtin_amdgcn_readfirstlane(s_guess);  // read before thread 0 may change it
+                __syncthreads();
+                unsigned im = 0u;
 #pragma unroll
-            for (int w = 0; w < kBT / 64; ++w) im = max(im, s_xmax[w]);
-            im = __builtin_amdgcn_readfirstlane(im);
-            if (threadIdx.x == 0) s_xseen = max(s_xseen, im);
-            if (im <= guess || attempt > 0) {
-                // the item's loss terms, added once the item is accepted
-                if (MODE == kBGradient && a.loss) {
-                    const double t = block_sum(lsum, red);
-                    if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
+                for (int w = 0; w < kBT / 64; ++w) im = max(im, s_xmax[w]);
+                im = __builtin_amdgcn_readfirstlane(im);
+                if (threadIdx.x == 0) s_xseen = max(s_xseen, im);
+                if (im <= guess || attempt > 0) {
+                    // the item's loss terms, added once the item is accepted
+                    if (MODE == kBGradient && a.loss) {
+                        const double t = block_sum(lsum, red);
+                        if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
+                    }
+                    lsum = 0.0;
+                    break;
                 }
+                if (threadIdx.x == 0) s_guess = im;  // read after the next window's barrier
                 lsum = 0.0;
-                break;
+                for (int t = threadIdx.x; t < XN; t += kBT) {
+                    acc_re[t] = 0.0;
+                    acc_im[t] = 0.0;
+                }
             }
-            if (threadIdx.x == 0) s_guess = im;  // read after the next window's barrier
-            lsum = 0.0;
-            for (int t = threadIdx.x; t < XN; t += kBT) {
-                acc_re[t] = 0.0;
-                acc_im[t] = 0.0;
-            }
-        }
         }  // attempts
 
         if (SCATTER) {
