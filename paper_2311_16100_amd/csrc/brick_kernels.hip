@@ -597,8 +597,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                         const uint64_t probe = p ? a.probe_b : a.probe_a;
                         const uint32_t b0 = (uint32_t)(g0 >> 7);
                         const U4 r0 = rademacher_block(a.probe_seed, probe, b0);
-                        const bool two = (uint32_t)((g0 + nx - 1) >> 7) != b0;
-                        const U4 r1 = two ? rademacher_block(a.probe_seed, probe, b0 + 1) : r0;
+                        const bool next_block = (uint32_t)((g0 + nx - 1) >> 7) != b0;
+                        const U4 r1 = next_block ? rademacher_block(a.probe_seed, probe, b0 + 1) : r0;
                         // the 13 bits from bit (g0 mod 128) on, in the words
                         // r0.x .. r0.w r1.x r1.y (a run of 13 spans at most
                         // two consecutive words)
