@@ -199,8 +199,7 @@ def main():
                             "kernels_avg_ms": {k: round(kern_fa[k][0] / kern_fa[k][1], 4) for k in kern_fa},
                             "bytes_per_image": round(16 * P + 24 * U)}
     # the same bytes over the whole entry point's event-timed duration (for
-    # the gradient: the volume copy lam v, the image-bound pass of the
-    # fixed-point accumulator, cull, plan and the kernel)
+    # the gradient: the volume copy lam v, cull, plan and the kernel)
     if dominant in ms:
         roofline["call_ms"] = round(ms[dominant], 4)
         roofline["call_frac"] = round(per_image[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
