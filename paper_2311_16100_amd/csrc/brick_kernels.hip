@@ -2,17 +2,19 @@
 //
 // The volume is cut into 12^3 bricks.  A cull kernel lists, per brick and in
 // image order, the images whose slice plane reaches the brick; a plan kernel
-// turns the lists into work items (one brick and up to 64 of its images for
-// the forward mode, 128 for the adjoint modes), ordered by size, largest
-// first.  One wave of resident blocks takes the items from that list with an
-// atomic counter.  For each item the block
+// turns the lists into work items (one brick and chunks of its images),
+// ordered by size, largest first.  One wave of resident blocks takes the items from
+// that list with an atomic counter.  For each item the block takes the
+// brick's images in chunks (64 for the forward mode, 128 for the adjoint
+// modes; up to eight chunks per item for the gradient and HVP) and
 //   - stages the brick and the voxels one step above it on each axis (13^3
-//     complex values of the gathered volume) in LDS, so every trilinear
+//     complex values of the gathered volume) in LDS once, so every trilinear
 //     gather is 8 LDS reads;
 //   - accumulates the adjoint into an LDS array of the same extent as 64-bit
 //     fixed-point integers, one per component (ItemScale; the deterministic
 //     mode: FxScale; the probe HVP packs both components into one, see
-//     PackedScale), and adds it to HBM once per voxel at the end with global
+//     PackedScale: flushed after every chunk), and adds it to HBM once per
+//     voxel at the end with global
 //     atomics (the upper faces of the extent belong to the neighbouring
 //     bricks, which other blocks may be flushing at the same time).  On gfx950
 //     the LDS single-precision atomic add sustains about a twentieth of the
@@ -100,6 +102,11 @@ constexpr float kClipEps = 1e-2f;
 enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5,
                  kBHvpProbe = 6 };
 constexpr bool is_hvp(int mode) { return mode == kBHvp || mode == kBHvpProbe; }
+// the most chunks of a brick's images per work item (staged and flushed once
+// for all of them): eight for the gradient and HVP modes (two blocks per CU),
+// two for the modes with three blocks per CU (measured: a whole brick per
+// item leaves those with a long tail); the plan lowers it for small batches
+constexpr int max_chunks_per_item(int mode) { return (mode == kBGradient || is_hvp(mode)) ? 8 : 2; }
 
 struct BrickArgs {
     Geom g;
@@ -119,9 +126,10 @@ struct BrickArgs {
     const int *lists;   // [nb][stride]
     int stride;
     int nbx, nb;
-    const int2 *items;  // work items, heaviest first: (brick | chunk << 20, images of the brick)
+    const int2 *items;  // work items, heaviest first: (brick | first chunk << 20, images of the brick)
     const int *n_items; // number of work items
     int *next_item;     // work counter (zero at launch)
+    const int *per_item; // chunks of images per work item
     // deterministic adjoint (fixed point, see FxScale): the 64-bit volume
     // [M^3][re, im], the input bounds and the images of the whole launch
     unsigned long long *fx;
@@ -226,28 +234,48 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wave_sums, int *
 }
 
 // ---------------------------------------------------------------------------
-// Plan: one work item per brick and chunk of `chunk` images of its list,
-// ordered by the number of images, largest first (the full chunks of the
-// heavily crossed central bricks, then the partial chunks by size), so that
-// the long items start first.  Each wave counts into its own histogram copy
-// (fewer colliding LDS atomics).  Resets the work counter.  One block.
+// Plan: one work item per brick and run of up to `per` consecutive chunks of
+// `chunk` images of its list (the block that takes the item stages the brick
+// once for all of them), ordered by the number of images, largest first, so
+// that the long items start first: the key is ceil(images / per), at most
+// `chunk`.  `per` is the largest value up to `max_per` that leaves at least
+// `min_items` items (about ceil(chunks / per) of them), so that small batches
+// keep every resident block busy; it is stored in *per_out for the kernel.
+// Each wave counts into its own histogram copy (fewer colliding LDS atomics).
+// Resets the work counter.  One block.
 // ---------------------------------------------------------------------------
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanWaves = kPlanThreads / 64;
 constexpr int kMaxChunk = 128;
 static_assert(CHUNK_ADJ <= kMaxChunk && CHUNK_FWD <= kMaxChunk, "plan histogram too small");
 
-__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int2 *items,
-                                                                   int *n_items, int *next_item) {
+__global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *counts, int nb, int chunk, int max_per,
+                                                                   int min_items, int2 *items, int *n_items,
+                                                                   int *next_item, int *per_out) {
     __shared__ int hist[kPlanWaves][kMaxChunk + 1];
     __shared__ int base[kMaxChunk + 1];
+    __shared__ int s_chunks;
     const int wv = threadIdx.x >> 6;
+    // the batch's chunks, then chunks per item
+    if (threadIdx.x == 0) s_chunks = 0;
+    __syncthreads();
+    {
+        int nc = 0;
+        for (int b = threadIdx.x; b < nb; b += kPlanThreads) nc += (counts[b] + chunk - 1) / chunk;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nc += __shfl_xor(nc, off, 64);
+        if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&s_chunks, nc);
+    }
+    __syncthreads();
+    const int per = max(1, min(max_per, s_chunks / max(min_items, 1)));
+    if (threadIdx.x == 0) *per_out = per;
+    const int span = chunk * per;  // images of a full item
     for (int k = threadIdx.x; k < kPlanWaves * (kMaxChunk + 1); k += kPlanThreads) (&hist[0][0])[k] = 0;
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
-        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        const int c = counts[b], full = c / span, rem = c - full * span;
         if (full) atomicAdd(&hist[wv][chunk], full);
-        if (rem) atomicAdd(&hist[wv][rem], 1);
+        if (rem) atomicAdd(&hist[wv][(rem + per - 1) / per], 1);
     }
     __syncthreads();
     // bucket starts (largest key first), then per-wave cursors inside each
@@ -292,13 +320,14 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
         }
     }
     __syncthreads();
+    // item record: (brick | first chunk << 20, images of the brick)
     for (int b = threadIdx.x; b < nb; b += kPlanThreads) {
-        const int c = counts[b], full = c / chunk, rem = c - full * chunk;
+        const int c = counts[b], full = c / span, rem = c - full * span;
         if (full) {
             const int p = atomicAdd(&hist[wv][chunk], full);
-            for (int k = 0; k < full; ++k) items[p + k] = make_int2(b | (k << 20), c);
+            for (int k = 0; k < full; ++k) items[p + k] = make_int2(b | ((k * per) << 20), c);
         }
-        if (rem) items[atomicAdd(&hist[wv][rem], 1)] = make_int2(b | (full << 20), c);
+        if (rem) items[atomicAdd(&hist[wv][(rem + per - 1) / per], 1)] = make_int2(b | ((full * per) << 20), c);
     }
 }
 
@@ -381,7 +410,8 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // the pixels of the plane lattice inside its 2x2x2 neighbourhood, whose section
 // has area at most 4 sqrt(2): at most 13 pixels (Pick's theorem; 16 is used),
 // each with weight <= 1.
-// Over an item of at most 128 images a component sum is therefore below
+// Over a chunk of at most 128 images (the probe mode flushes after each) a
+// component sum is therefore below
 // 2048 V = B, and S = 2^e with B S <= 2^30 keeps every sum (and every rounded
 // contribution) below 2^30.  The rounding error is at most 1/(2S) per
 // contribution, i.e. 2^-31 B (relative 5e-10 of B).  Because B is a worst
@@ -418,11 +448,12 @@ struct PackedScale {
 
 // Per-item fixed-point scale of the 64-bit LDS accumulator of the fast
 // adjoint modes.  A contribution is w val with w <= 1 and |val| <= V; an item
-// holds at most 128 images and a voxel receives at most 32 pixels of one
-// image (see FxScale), so every LDS sum stays below 4096 V.  S = 2^e is the
-// largest power of two with 4096 V S <= 2^61 and V S <= 2^50: the sums are
-// exact, each contribution is rounded by at most 2^-50 V (about 2^-26 of a
-// float ulp of V), and the flush converts each voxel's sum to float once.
+// holds at most one sub-batch of 2048 images and a voxel receives
+// at most 32 pixels of one image (see FxScale), so every LDS sum stays below
+// 2^16 V.  S = 2^e is the largest power of two with 2^16 V S <= 2^61 and
+// V S <= 2^50: the sums are exact, each contribution is rounded by at most
+// 2^-46 V (about 2^-22 of a float ulp of V), and the flush converts each
+// voxel's sum to float once.
 #ifndef CSG_LDS_FIXED
 #define CSG_LDS_FIXED 1
 #endif
@@ -431,12 +462,12 @@ struct ItemScale {
     double S = 1.0, invS = 1.0;
     int ok = 1;
     static __device__ __forceinline__ ItemScale make(double V) {
-        static_assert(CHUNK_ADJ <= 128, "the LDS bound assumes at most 128 images per item");
+        static_assert(kBrickSubBatch <= 2048, "the LDS bound assumes at most 2048 images per item");
         ItemScale q;
         q.ok = isfinite(V) ? 1 : 0;
         if (q.ok && V > 0.0) {
             int kt, kv;
-            (void)frexp(4096.0 * V, &kt);
+            (void)frexp(65536.0 * V, &kt);
             (void)frexp(V, &kv);
             const int e = min(61 - kt, 50 - kv);
             q.S = ldexp(1.0, e);
@@ -514,6 +545,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     const Geom &g = a.g;
     const int M = g.M;
     const int total = *a.n_items;
+    const int per_item = *a.per_item;  // chunks per work item (from the plan)
     double lsum = 0.0;
     double fxS = 1.0;
     if (FX) fxS = fx_scale(a.fx_max, a.scale, a.n_total).S;
@@ -559,22 +591,23 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         // uniform values read from LDS are moved to scalar registers
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= total) break;
+        // an item is a brick and up to per_item chunks of CHUNK of its images:
+        // images first0 .. last - 1 of its list
         const int2 rec = a.items[item];
-        const int code = rec.x;
-        const int brick = code & 0xFFFFF;
-        const int first = (code >> 20) * CHUNK;
+        const int brick = rec.x & 0xFFFFF;
         const int count = rec.y;
-        const int n_img = min(CHUNK, count - first);
+        const int first0 = (rec.x >> 20) * CHUNK;
+        const int last = min(count, first0 + per_item * CHUNK);
         int o[3];
         brick_origin(brick, a.nbx, o);
 
-        const int *list = a.lists + (int64_t)brick * a.stride + first;
-        // the item's images are staged in LDS by threads t < n_img; their
-        // loads are issued together with the halo loads so that the
+        const int *list = a.lists + (int64_t)brick * a.stride;
+        // a chunk's images are staged in LDS by threads t < n_img; the first
+        // chunk's loads are issued together with the halo loads so that the
         // latencies overlap
-        const bool holds_img = (int)threadIdx.x < n_img;
+        const bool holds_img = (int)threadIdx.x < min(CHUNK, last - first0);
         int my_ii = 0;
-        if (holds_img) my_ii = list[threadIdx.x];
+        if (holds_img) my_ii = list[first0 + threadIdx.x];
         if (GATHER) {
             // the extended brick of the gathered volume; every load is issued
             // before the first LDS store
@@ -658,19 +691,21 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = zb;
             }
         }
-        if (holds_img) {
+        // one image of a chunk into LDS (thread t: the chunk's image t)
+        auto stage_image = [&](int ii) {
             float e[9];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) e[d] = a.rot[(int64_t)my_ii * 9 + d];
-            e[6] = a.defocus[my_ii];
+            for (int d = 0; d < 6; ++d) e[d] = a.rot[(int64_t)ii * 9 + d];
+            e[6] = a.defocus[ii];
             if (SHIFTED) {
-                e[7] = a.shift[2 * my_ii];
-                e[8] = a.shift[2 * my_ii + 1];
+                e[7] = a.shift[2 * ii];
+                e[8] = a.shift[2 * ii + 1];
             }
-            imgdat[threadIdx.x][0] = __int_as_float(my_ii);
+            imgdat[threadIdx.x][0] = __int_as_float(ii);
 #pragma unroll
             for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
-        }
+        };
+        if (holds_img) stage_image(my_ii);
         if (SCATTER && PK_ALWAYS) {
             for (int t = threadIdx.x; t < XN; t += kBT) acc_pk[t] = 0ull;
         } else if (SCATTER) {
@@ -703,6 +738,62 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         const uint32_t MM = (uint32_t)M * (uint32_t)M;
         const uint32_t pix_off = (uint32_t)g.half * (uint32_t)M + (uint32_t)g.half;
 
+        // flush: every voxel of the extended brick that lies in the grid is
+        // added to HBM with global atomics (voxels that received nothing are
+        // skipped); the probe mode flushes after every chunk and clears its
+        // packed sums as it goes
+        auto flush_voxels = [&]() {
+            constexpr int NV = BX * BX * BX;
+            for (int t = threadIdx.x; t < NV; t += kBT) {
+                const int tx = t % BX, ty = (t / BX) % BX, tz = t / (BX * BX);
+                const int li = (tz * XR + ty) * XR + tx;
+                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) {
+                    if (PK_ALWAYS) acc_pk[li] = 0ull;  // cleared for the next chunk
+                    continue;
+                }
+                const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
+                if (FX) {
+                    const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
+                    if (qr) atomicAdd(&a.fx[2 * gi], qr);
+                    if (qi) atomicAdd(&a.fx[2 * gi + 1], qi);
+                    continue;
+                }
+                if (QITEM && MODE == kBSqDiag) {
+                    const long long qr = (long long)acc_qre[li];
+                    if (!qs.ok) atomicAdd(a.accum_real + gi, __builtin_nanf(""));
+                    else if (qr) atomicAdd(a.accum_real + gi, (float)((double)qr * qs.invS));
+                    continue;
+                }
+                if (QITEM) {
+                    const long long qr = (long long)acc_qre[li], qi = (long long)acc_qim[li];
+                    if (!qs.ok) {
+                        atomicAdd(&a.accum[gi].x, __builtin_nanf(""));
+                        atomicAdd(&a.accum[gi].y, __builtin_nanf(""));
+                    } else {
+                        if (qr) atomicAdd(&a.accum[gi].x, (float)((double)qr * qs.invS));
+                        if (qi) atomicAdd(&a.accum[gi].y, (float)((double)qi * qs.invS));
+                    }
+                    continue;
+                }
+                if (PK_ALWAYS) {
+                    float re, im;
+                    pk.unpack(acc_pk[li], re, im);
+                    acc_pk[li] = 0ull;  // cleared for the next chunk
+                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
+                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
+                    continue;
+                }
+                const float re = (float)acc_re[li];
+                if (MODE == kBSqDiag) {
+                    if (re != 0.f) atomicAdd(a.accum_real + gi, re);
+                } else {
+                    const float im = (float)acc_im[li];
+                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
+                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
+                }
+            }
+        };
+
         for (int attempt = 0;; ++attempt) {
             unsigned xmax_item = 0u;  // this thread's largest image value of the item
             // modes without a gathered value: the bound is known before the item
@@ -710,281 +801,292 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             // backproject: |scale| times the image guess, set in the first window)
             if (QITEM && !GATHER && !READS_IMG)
                 qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
-            for (int w0 = 0; w0 < n_img; w0 += WI) {
-                const int nw = min(WI, n_img - w0);
-                // every wave has finished with the previous window's tables
-                __syncthreads();
-                if (STAGE_MAX && w0 == 0) {
-                    unsigned zbits = 0u;
-#pragma unroll
-                    for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
-                    const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
-                    if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
-                    if (QITEM) {
-                        const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
-                        const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
-                        qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
-                    }
-                }
-                if (QITEM && !GATHER && READS_IMG && w0 == 0)
-                    qs = ItemScale::make(fabs((double)a.scale) *
-                                         (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
-                // ---- the window's images (one thread each): constants, first row,
-                // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
-                // MAXROWS - 1 of the window; those past its row count stay empty.
-                const int t = (int)threadIdx.x;
-                if (t < nw) {
-                    {
-                        ImgSlot &S = slot[t];
-                        const float *D = imgdat[w0 + t];
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            S.E1[d] = rint_scaled(D[1 + d]);
-                            S.E2[d] = rint_scaled(D[4 + d]);
-                            S.E1i[d] = (int64_t)S.E1[d];
-                        }
-                        S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
-                        S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
-                        if (SHIFTED) {
-                            S.sx = D[IMGDAT - 2];
-                            S.sy = D[IMGDAT - 1];
-                        }
-                        // rows: range of e2 . (g - half) over the box
-                        float ylo = 0.f, yhi = 0.f;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const float u = D[4 + d] * (lo[d] - halff), w = D[4 + d] * (hi[d] - halff);
-                            ylo += fminf(u, w);
-                            yhi += fmaxf(u, w);
-                        }
-                        // range tests in floating point first, so only bounded values
-                        // are converted
-                        const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
-                        const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
-                        if (fl <= fh) {
-                            S.ky_lo = (short)(int)fl;
-                            S.nrows = (unsigned short)min((int)fh - (int)fl + 1, MAXROWS);
-                        } else {
-                            S.ky_lo = 0;
-                            S.nrows = 0;
-                        }
-                    }
-                }
-
-                __syncthreads();
-                const int n_rows = nw * MAXROWS;
-                // ---- row intervals (kx range whose cells reach the box), runs per row
-                int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
-                int myruns = 0;
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int r = threadIdx.x + k * kBT;
-                    rlen[k] = 0;
-                    rkx0[k] = 0;
-                    rky[k] = 0;
-                    rsl[k] = 0;
-                    const int s = r / MAXROWS;
-                    const int q = r - s * MAXROWS;
-                    if (r < n_rows && q < (int)slot[s].nrows) {
-                        const ImgSlot &S = slot[s];
-                        const int ky = S.ky_lo + q;
-                        const float *D = imgdat[w0 + s];
-                        const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
-                        int x0, x1;
-                        clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
-                        // the disk: |kx| <= floor(sqrt(k2max - ky^2))
-                        const int rem = g.k2max - ky * ky;
-                        int kxm = (int)sqrtf((float)max(rem, 0));
-                        while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
-                        while (kxm > 0 && kxm * kxm > rem) --kxm;
-                        x0 = max(x0, -kxm);
-                        x1 = min(x1, kxm);
-                        if (rem >= 0 && x1 >= x0) {
-                            rlen[k] = min(x1 - x0 + 1, MAXLEN);
-                            rkx0[k] = x0;
-                        }
-                        rky[k] = ky;
-                        rsl[k] = s;
-                    }
-                    myruns += (rlen[k] + RUN - 1) / RUN;
-                }
-                int T;
-                {
-                    int p = block_exclusive_scan(myruns, wave_sums, &T);
-                    T = __builtin_amdgcn_readfirstlane(T);
-#pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const int r = threadIdx.x + k * kBT;
-                        if (r < n_rows)
-                            seg[r] = make_int2(p | (rlen[k] << 16) | (rsl[k] << 24),
-                                               (rkx0[k] + 32768) | ((rky[k] + 32768) << 16));
-                        p += (rlen[k] + RUN - 1) / RUN;
-                    }
-                }
-
-                for (int wbase = 0; wbase < T; wbase += RUNCAP) {
-                    // ---- run -> row table of this pass (each thread fills the runs
-                    // of its own rows, read back from their records)
-#pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const int r = threadIdx.x + k * kBT;
-                        if (r < n_rows) {
-                            const int x = seg[r].x;
-                            const int rs = x & 0xFFFF, nr = (((x >> 16) & 0xFF) + RUN - 1) / RUN;
-                            const int b0 = max(rs, wbase), b1 = min(rs + nr, wbase + RUNCAP);
-                            for (int q = b0; q < b1; ++q) run2row[q - wbase] = (unsigned short)r;
-                        }
-                    }
+            for (int first = first0; first < last; first += CHUNK) {
+                const int n_img = min(CHUNK, last - first);
+                if (first > first0 || attempt > 0) {
+                    // the chunk's images (the first chunk's were staged with the
+                    // brick); every wave is done with the previous chunk's
                     __syncthreads();
-                    const int wend = min(T, wbase + RUNCAP);
-                    for (int u = wbase + threadIdx.x; u < wend; u += kBT) {
-                        const int2 rec = seg[run2row[u - wbase]];
-                        const int rs = rec.x & 0xFFFF;
-                        const int len = (rec.x >> 16) & 0xFF;
-                        const ImgSlot &I = slot[(unsigned)rec.x >> 24];
-                        const int kx0 = (rec.y & 0xFFFF) - 32768;
-                        const int ky = (int)((unsigned)rec.y >> 16) - 32768;
-                        const int j0 = (u - rs) * RUN;
-                        const int kxs = kx0 + j0;
-                        const int cnt = min(RUN, len - j0);
-                        const uint32_t jrun = I.img_base + pix_off + (uint32_t)(ky * M) + (uint32_t)kxs;
-                        // the run's image values are requested first, so that their
-                        // latency overlaps the sample-point arithmetic (every pixel of
-                        // a run lies in the disk, hence inside its image)
-                        float2 xin[RUN];
+                    if ((int)threadIdx.x < n_img) stage_image(list[first + threadIdx.x]);
+                }
+                for (int w0 = 0; w0 < n_img; w0 += WI) {
+                    const int nw = min(WI, n_img - w0);
+                    // every wave has finished with the previous window's tables
+                    __syncthreads();
+                    if (STAGE_MAX && w0 == 0) {
+                        unsigned zbits = 0u;
 #pragma unroll
-                        for (int jj = 0; jj < RUN; ++jj) {
-                            xin[jj] = make_float2(0.f, 0.f);
-                            if (READS_IMG && a.img && jj < cnt) xin[jj] = a.img[jrun + jj];
+                        for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
+                        const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
+                        if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
+                        if (QITEM) {
+                            const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
+                            const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
+                            qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
                         }
-                        // fixed-point sample point of the run's first pixel (exact)
-                        int64_t G[3];
+                    }
+                    if (QITEM && !GATHER && READS_IMG && w0 == 0)
+                        qs = ItemScale::make(fabs((double)a.scale) *
+                                             (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
+                    // ---- the window's images (one thread each): constants, first row,
+                    // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
+                    // MAXROWS - 1 of the window; those past its row count stay empty.
+                    const int t = (int)threadIdx.x;
+                    if (t < nw) {
+                        {
+                            ImgSlot &S = slot[t];
+                            const float *D = imgdat[w0 + t];
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const double gd = fma((double)kxs, I.E1[d], fma((double)ky, I.E2[d], halfG));
-                            const double h = floor(gd * 0x1p-32);
-                            const uint32_t l32 = (uint32_t)fma(-h, 0x1p32, gd);
-                            G[d] = (int64_t)(((uint64_t)(uint32_t)(int)h << 32) | l32);
+                            for (int d = 0; d < 3; ++d) {
+                                S.E1[d] = rint_scaled(D[1 + d]);
+                                S.E2[d] = rint_scaled(D[4 + d]);
+                                S.E1i[d] = (int64_t)S.E1[d];
+                            }
+                            S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
+                            S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
+                            if (SHIFTED) {
+                                S.sx = D[IMGDAT - 2];
+                                S.sy = D[IMGDAT - 1];
+                            }
+                            // rows: range of e2 . (g - half) over the box
+                            float ylo = 0.f, yhi = 0.f;
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                const float u = D[4 + d] * (lo[d] - halff), w = D[4 + d] * (hi[d] - halff);
+                                ylo += fminf(u, w);
+                                yhi += fmaxf(u, w);
+                            }
+                            // range tests in floating point first, so only bounded values
+                            // are converted
+                            const float fl = fmaxf(ceilf(ylo - kClipEps), (float)-kymax);
+                            const float fh = fminf(floorf(yhi + kClipEps), (float)kymax);
+                            if (fl <= fh) {
+                                S.ky_lo = (short)(int)fl;
+                                S.nrows = (unsigned short)min((int)fh - (int)fl + 1, MAXROWS);
+                            } else {
+                                S.ky_lo = 0;
+                                S.nrows = 0;
+                            }
                         }
-                        const int64_t E1i[3] = {I.E1i[0], I.E1i[1], I.E1i[2]};
-                        const double ctfA = I.ctfA;
-                        const int ky2 = ky * ky;
+                    }
+
+                    __syncthreads();
+                    const int n_rows = nw * MAXROWS;
+                    // ---- row intervals (kx range whose cells reach the box), runs per row
+                    int rlen[RPT], rkx0[RPT], rky[RPT], rsl[RPT];
+                    int myruns = 0;
 #pragma unroll
-                        for (int jj = 0; jj < RUN; ++jj) {
-                            if (jj < cnt) {
-                                int l[3];
-                                float t[3];
+                    for (int k = 0; k < RPT; ++k) {
+                        const int r = threadIdx.x + k * kBT;
+                        rlen[k] = 0;
+                        rkx0[k] = 0;
+                        rky[k] = 0;
+                        rsl[k] = 0;
+                        const int s = r / MAXROWS;
+                        const int q = r - s * MAXROWS;
+                        if (r < n_rows && q < (int)slot[s].nrows) {
+                            const ImgSlot &S = slot[s];
+                            const int ky = S.ky_lo + q;
+                            const float *D = imgdat[w0 + s];
+                            const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
+                            int x0, x1;
+                            clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
+                            // the disk: |kx| <= floor(sqrt(k2max - ky^2))
+                            const int rem = g.k2max - ky * ky;
+                            int kxm = (int)sqrtf((float)max(rem, 0));
+                            while ((kxm + 1) * (kxm + 1) <= rem) ++kxm;
+                            while (kxm > 0 && kxm * kxm > rem) --kxm;
+                            x0 = max(x0, -kxm);
+                            x1 = min(x1, kxm);
+                            if (rem >= 0 && x1 >= x0) {
+                                rlen[k] = min(x1 - x0 + 1, MAXLEN);
+                                rkx0[k] = x0;
+                            }
+                            rky[k] = ky;
+                            rsl[k] = s;
+                        }
+                        myruns += (rlen[k] + RUN - 1) / RUN;
+                    }
+                    int T;
+                    {
+                        int p = block_exclusive_scan(myruns, wave_sums, &T);
+                        T = __builtin_amdgcn_readfirstlane(T);
 #pragma unroll
-                                for (int d = 0; d < 3; ++d) {
-                                    l[d] = (int)(G[d] >> 32) - o[d];  // base corner relative to the brick
-                                    t[d] = (float)(uint32_t)G[d] * 0x1p-32f;
-                                }
-                                const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
-                                                   (unsigned)l[2] < (unsigned)BS;
-                                if (owned) {
-                                    const int kx = kxs + jj;
-                                    float C = 1.0f;
-                                    if (g.ctf_on) {
-                                        const double k2 = (double)(kx * kx + ky2);
-                                        const double turns = fma(fma(-ctfB, k2, ctfA), k2, g.phase0);
-                                        C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
+                        for (int k = 0; k < RPT; ++k) {
+                            const int r = threadIdx.x + k * kBT;
+                            if (r < n_rows)
+                                seg[r] = make_int2(p | (rlen[k] << 16) | (rsl[k] << 24),
+                                                   (rkx0[k] + 32768) | ((rky[k] + 32768) << 16));
+                            p += (rlen[k] + RUN - 1) / RUN;
+                        }
+                    }
+
+                    for (int wbase = 0; wbase < T; wbase += RUNCAP) {
+                        // ---- run -> row table of this pass (each thread fills the runs
+                        // of its own rows, read back from their records)
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) {
+                            const int r = threadIdx.x + k * kBT;
+                            if (r < n_rows) {
+                                const int x = seg[r].x;
+                                const int rs = x & 0xFFFF, nr = (((x >> 16) & 0xFF) + RUN - 1) / RUN;
+                                const int b0 = max(rs, wbase), b1 = min(rs + nr, wbase + RUNCAP);
+                                for (int q = b0; q < b1; ++q) run2row[q - wbase] = (unsigned short)r;
+                            }
+                        }
+                        __syncthreads();
+                        const int wend = min(T, wbase + RUNCAP);
+                        for (int u = wbase + threadIdx.x; u < wend; u += kBT) {
+                            const int2 rec = seg[run2row[u - wbase]];
+                            const int rs = rec.x & 0xFFFF;
+                            const int len = (rec.x >> 16) & 0xFF;
+                            const ImgSlot &I = slot[(unsigned)rec.x >> 24];
+                            const int kx0 = (rec.y & 0xFFFF) - 32768;
+                            const int ky = (int)((unsigned)rec.y >> 16) - 32768;
+                            const int j0 = (u - rs) * RUN;
+                            const int kxs = kx0 + j0;
+                            const int cnt = min(RUN, len - j0);
+                            const uint32_t jrun = I.img_base + pix_off + (uint32_t)(ky * M) + (uint32_t)kxs;
+                            // the run's image values are requested first, so that their
+                            // latency overlaps the sample-point arithmetic (every pixel of
+                            // a run lies in the disk, hence inside its image)
+                            float2 xin[RUN];
+#pragma unroll
+                            for (int jj = 0; jj < RUN; ++jj) {
+                                xin[jj] = make_float2(0.f, 0.f);
+                                if (READS_IMG && a.img && jj < cnt) xin[jj] = a.img[jrun + jj];
+                            }
+                            // fixed-point sample point of the run's first pixel (exact)
+                            int64_t G[3];
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                const double gd = fma((double)kxs, I.E1[d], fma((double)ky, I.E2[d], halfG));
+                                const double h = floor(gd * 0x1p-32);
+                                const uint32_t l32 = (uint32_t)fma(-h, 0x1p32, gd);
+                                G[d] = (int64_t)(((uint64_t)(uint32_t)(int)h << 32) | l32);
+                            }
+                            const int64_t E1i[3] = {I.E1i[0], I.E1i[1], I.E1i[2]};
+                            const double ctfA = I.ctfA;
+                            const int ky2 = ky * ky;
+#pragma unroll
+                            for (int jj = 0; jj < RUN; ++jj) {
+                                if (jj < cnt) {
+                                    int l[3];
+                                    float t[3];
+#pragma unroll
+                                    for (int d = 0; d < 3; ++d) {
+                                        l[d] = (int)(G[d] >> 32) - o[d];  // base corner relative to the brick
+                                        t[d] = (float)(uint32_t)G[d] * 0x1p-32f;
                                     }
-                                    const uint32_t j = jrun + (uint32_t)jj;
-                                    const float wx[2] = {1.0f - t[0], t[0]};
-                                    const float wy[2] = {1.0f - t[1], t[1]};
-                                    const float wz[2] = {1.0f - t[2], t[2]};
-                                    float2 acc = make_float2(0.f, 0.f);
-                                    // index of the base corner in the extended brick; the
-                                    // eight corners lie in it
-                                    const int lb = (l[2] * XR + l[1]) * XR + l[0];
-                                    if (GATHER) {
-                                        // staged voxels outside the grid hold zeros, which
-                                        // drops those corners
-#pragma unroll
-                                        for (int c = 0; c < 8; ++c) {
-                                            const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                            const float w = wx[ax] * wy[ay] * wz[az];
-                                            const float2 v = vh[lb + az * XP + ay * XR + ax];
-                                            acc.x = fmaf(w, v.x, acc.x);
-                                            acc.y = fmaf(w, v.y, acc.y);
+                                    const bool owned = (unsigned)l[0] < (unsigned)BS && (unsigned)l[1] < (unsigned)BS &&
+                                                       (unsigned)l[2] < (unsigned)BS;
+                                    if (owned) {
+                                        const int kx = kxs + jj;
+                                        float C = 1.0f;
+                                        if (g.ctf_on) {
+                                            const double k2 = (double)(kx * kx + ky2);
+                                            const double turns = fma(fma(-ctfB, k2, ctfA), k2, g.phase0);
+                                            C = -__builtin_amdgcn_sinf((float)(turns - rint(turns)));
                                         }
-                                    }
-                                    // in-plane shift: T on the forward value, conj(T)
-                                    // on the adjoint input
-                                    float2 T = make_float2(1.f, 0.f);
-                                    if (SHIFTED) {
-                                        const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
-                                                          (double)M;
-                                        const float fr = (float)(tt - rint(tt));
-                                        T = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
-                                        if (GATHER) acc = cmul(acc, T);
-                                    }
-                                    float2 val = make_float2(0.f, 0.f);
-                                    if (MODE == kBProject) {
-                                        float2 y = make_float2(C * acc.x, C * acc.y);
-                                        if (a.img) {
-                                            y.x -= xin[jj].x;
-                                            y.y -= xin[jj].y;
-                                        }
-                                        if (a.out) a.out[j] = y;
-                                        lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
-                                    }
-                                    if (XRETRY) {
-                                        const float xa = fabsf(xin[jj].x) + fabsf(xin[jj].y);
-                                        xmax_item = max(xmax_item, __float_as_uint(xa) & 0x7fffffffu);
-                                    }
-                                    if (MODE == kBBackproject) {
-                                        const float2 x = cmul_conj(xin[jj], T);
-                                        const float fct = a.scale * ctf_pow(C, a.ctf_power);
-                                        val = make_float2(fct * x.x, fct * x.y);
-                                    } else if (MODE == kBGradient) {
-                                        const float2 x = xin[jj];
-                                        const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
-                                        lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
-                                        const float fct = a.scale * C;
-                                        const float2 rt = cmul_conj(rr, T);
-                                        val = make_float2(fct * rt.x, fct * rt.y);
-                                    } else if (is_hvp(MODE)) {
-                                        const float fct = a.scale * C * C;
-                                        val = make_float2(fct * acc.x, fct * acc.y);
-                                    } else if (MODE == kBFeatures) {
-                                        val = make_float2(C * C, 1.0f);
-                                    } else if (MODE == kBSqDiag) {
-                                        val = make_float2(a.scale * C * C, 0.0f);
-                                    }
-                                    if (SCATTER) {
-                                        // all eight corners; a corner beyond the grid edge
-                                        // lands in a slot that is never written back
+                                        const uint32_t j = jrun + (uint32_t)jj;
+                                        const float wx[2] = {1.0f - t[0], t[0]};
+                                        const float wy[2] = {1.0f - t[1], t[1]};
+                                        const float wz[2] = {1.0f - t[2], t[2]};
+                                        float2 acc = make_float2(0.f, 0.f);
+                                        // index of the base corner in the extended brick; the
+                                        // eight corners lie in it
+                                        const int lb = (l[2] * XR + l[1]) * XR + l[0];
+                                        if (GATHER) {
+                                            // staged voxels outside the grid hold zeros, which
+                                            // drops those corners
 #pragma unroll
-                                        for (int c = 0; c < 8; ++c) {
-                                            const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                            const float w = wx[ax] * wy[ay] * wz[az];
-                                            const int li = lb + az * XP + ay * XR + ax;
-                                            if (MODE == kBSqDiag && QLDS) {
-                                                atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
-                                            } else if (MODE == kBSqDiag) {
-                                                atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                                            } else if (PK_ALWAYS) {
-                                                atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
-                                            } else if (QLDS) {
-                                                const double S = FX ? fxS : qs.S;
-                                                atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
-                                                atomicAdd(&acc_qim[li], fx_quant(w * val.y, S));
-                                            } else {
-                                                atomicAdd(&acc_re[li], (double)(w * val.x));
-                                                atomicAdd(&acc_im[li], (double)(w * val.y));
+                                            for (int c = 0; c < 8; ++c) {
+                                                const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                const float w = wx[ax] * wy[ay] * wz[az];
+                                                const float2 v = vh[lb + az * XP + ay * XR + ax];
+                                                acc.x = fmaf(w, v.x, acc.x);
+                                                acc.y = fmaf(w, v.y, acc.y);
+                                            }
+                                        }
+                                        // in-plane shift: T on the forward value, conj(T)
+                                        // on the adjoint input
+                                        float2 T = make_float2(1.f, 0.f);
+                                        if (SHIFTED) {
+                                            const double tt = -((double)kx * (double)I.sx + (double)ky * (double)I.sy) /
+                                                              (double)M;
+                                            const float fr = (float)(tt - rint(tt));
+                                            T = make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+                                            if (GATHER) acc = cmul(acc, T);
+                                        }
+                                        float2 val = make_float2(0.f, 0.f);
+                                        if (MODE == kBProject) {
+                                            float2 y = make_float2(C * acc.x, C * acc.y);
+                                            if (a.img) {
+                                                y.x -= xin[jj].x;
+                                                y.y -= xin[jj].y;
+                                            }
+                                            if (a.out) a.out[j] = y;
+                                            lsum += 0.5 * ((double)y.x * y.x + (double)y.y * y.y);
+                                        }
+                                        if (XRETRY) {
+                                            const float xa = fabsf(xin[jj].x) + fabsf(xin[jj].y);
+                                            xmax_item = max(xmax_item, __float_as_uint(xa) & 0x7fffffffu);
+                                        }
+                                        if (MODE == kBBackproject) {
+                                            const float2 x = cmul_conj(xin[jj], T);
+                                            const float fct = a.scale * ctf_pow(C, a.ctf_power);
+                                            val = make_float2(fct * x.x, fct * x.y);
+                                        } else if (MODE == kBGradient) {
+                                            const float2 x = xin[jj];
+                                            const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
+                                            lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
+                                            const float fct = a.scale * C;
+                                            const float2 rt = cmul_conj(rr, T);
+                                            val = make_float2(fct * rt.x, fct * rt.y);
+                                        } else if (is_hvp(MODE)) {
+                                            const float fct = a.scale * C * C;
+                                            val = make_float2(fct * acc.x, fct * acc.y);
+                                        } else if (MODE == kBFeatures) {
+                                            val = make_float2(C * C, 1.0f);
+                                        } else if (MODE == kBSqDiag) {
+                                            val = make_float2(a.scale * C * C, 0.0f);
+                                        }
+                                        if (SCATTER) {
+                                            // all eight corners; a corner beyond the grid edge
+                                            // lands in a slot that is never written back
+#pragma unroll
+                                            for (int c = 0; c < 8; ++c) {
+                                                const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                const float w = wx[ax] * wy[ay] * wz[az];
+                                                const int li = lb + az * XP + ay * XR + ax;
+                                                if (MODE == kBSqDiag && QLDS) {
+                                                    atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
+                                                } else if (MODE == kBSqDiag) {
+                                                    atomicAdd(&acc_re[li], (double)(w * w * val.x));
+                                                } else if (PK_ALWAYS) {
+                                                    atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
+                                                } else if (QLDS) {
+                                                    const double S = FX ? fxS : qs.S;
+                                                    atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
+                                                    atomicAdd(&acc_qim[li], fx_quant(w * val.y, S));
+                                                } else {
+                                                    atomicAdd(&acc_re[li], (double)(w * val.x));
+                                                    atomicAdd(&acc_im[li], (double)(w * val.y));
+                                                }
                                             }
                                         }
                                     }
                                 }
-                            }
 #pragma unroll
-                            for (int d = 0; d < 3; ++d) G[d] += E1i[d];
+                                for (int d = 0; d < 3; ++d) G[d] += E1i[d];
+                            }
                         }
+                        __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
                     }
-                    __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
                 }
-            }
+                // the probe mode's packed sums hold one chunk (see PackedScale)
+                if (PK_ALWAYS) flush_voxels();
+            }  // chunks
             if (!XRETRY) break;
             // the item's largest image value; above the guess, a fixed-point sum
             // may have overflowed, and the item is redone with that maximum as
@@ -1019,56 +1121,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             }
         }  // attempts
 
-        if (SCATTER) {
+        if (SCATTER && !PK_ALWAYS) {
             __syncthreads();
-            // flush: every voxel of the extended brick that lies in the grid is
-            // added with global atomics (voxels that received nothing are
-            // skipped)
-            constexpr int NV = BX * BX * BX;
-            for (int t = threadIdx.x; t < NV; t += kBT) {
-                const int tx = t % BX, ty = (t / BX) % BX, tz = t / (BX * BX);
-                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
-                const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
-                const int li = (tz * XR + ty) * XR + tx;
-                if (FX) {
-                    const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
-                    if (qr) atomicAdd(&a.fx[2 * gi], qr);
-                    if (qi) atomicAdd(&a.fx[2 * gi + 1], qi);
-                    continue;
-                }
-                if (QITEM && MODE == kBSqDiag) {
-                    const long long qr = (long long)acc_qre[li];
-                    if (!qs.ok) atomicAdd(a.accum_real + gi, __builtin_nanf(""));
-                    else if (qr) atomicAdd(a.accum_real + gi, (float)((double)qr * qs.invS));
-                    continue;
-                }
-                if (QITEM) {
-                    const long long qr = (long long)acc_qre[li], qi = (long long)acc_qim[li];
-                    if (!qs.ok) {
-                        atomicAdd(&a.accum[gi].x, __builtin_nanf(""));
-                        atomicAdd(&a.accum[gi].y, __builtin_nanf(""));
-                    } else {
-                        if (qr) atomicAdd(&a.accum[gi].x, (float)((double)qr * qs.invS));
-                        if (qi) atomicAdd(&a.accum[gi].y, (float)((double)qi * qs.invS));
-                    }
-                    continue;
-                }
-                if (PK_ALWAYS) {
-                    float re, im;
-                    pk.unpack(acc_pk[li], re, im);
-                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
-                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
-                    continue;
-                }
-                const float re = (float)acc_re[li];
-                if (MODE == kBSqDiag) {
-                    if (re != 0.f) atomicAdd(a.accum_real + gi, re);
-                } else {
-                    const float im = (float)acc_im[li];
-                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
-                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
-                }
-            }
+            flush_voxels();
         }
     }  // work items
 
@@ -1115,7 +1170,7 @@ int brick_count(int M) {
 
 // Workspace of the brick kernels for a batch of n images (256-byte aligned
 // regions): per-brick image counts, per-brick image lists of one sub-batch,
-// the work items of one launch, and the two work-list scalars.
+// the work items of one launch, and the three work-list scalars.
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 static size_t brick_items_cap(int M, int64_t sub) {
@@ -1164,7 +1219,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     w += align256((size_t)nb * (size_t)sub * 4);
     int2 *items = (int2 *)w;
     w += align256(brick_items_cap(M, sub) * 8);
-    int *scalars = (int *)w;  // [0] number of work items, [1] work counter
+    int *scalars = (int *)w;  // [0] number of work items, [1] work counter, [2] chunks per item
     const int64_t img_stride = (int64_t)M * M;
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
@@ -1176,8 +1231,9 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
                            st, g, rot + s0 * 9, ns, nbx, nb, counts, lists, stride);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(brick_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, counts, nb, chunk, items, scalars,
-                           scalars + 1);
+        // at least two items per resident block
+        hipLaunchKernelGGL(brick_plan_kernel, dim3(1), dim3(kPlanThreads), 0, st, counts, nb, chunk,
+                           max_chunks_per_item(MODE), 2 * grid, items, scalars, scalars + 1, scalars + 2);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         BrickArgs a{};
@@ -1202,6 +1258,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         a.items = items;
         a.n_items = scalars;
         a.next_item = scalars + 1;
+        a.per_item = scalars + 2;
         if (FX) {
             a.fx = fb->fx;
             a.fx_max = fb->maxbits;
