@@ -333,9 +333,8 @@ __global__ __launch_bounds__(kPlanThreads) void brick_plan_kernel(const int *cou
 
 // Interval of kx for which the sample point of row ky lies in the box
 // [lo, hi) (grid coordinates) on every axis, widened by kClipEps.
-// inv_e1 = 1 / e1 per axis (formed once per image).
-__device__ __forceinline__ void clip_row(const float e1[3], const float inv_e1[3], const float e2[3], float half, int ky,
-                                         const float lo[3], const float hi[3], int &kx0, int &kx1) {
+__device__ __forceinline__ void clip_row(const float e1[3], const float e2[3], float half, int ky, const float lo[3],
+                                         const float hi[3], int &kx0, int &kx1) {
     float a = -1e30f, b = 1e30f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -346,7 +345,7 @@ __device__ __forceinline__ void clip_row(const float e1[3], const float inv_e1[3
                 b = -1e30f;
             }
         } else {
-            const float inv = inv_e1[d];
+            const float inv = 1.0f / e1[d];
             const float t0 = (lo[d] - c) * inv, t1 = (hi[d] - c) * inv;
             a = fmaxf(a, fminf(t0, t1));
             b = fminf(b, fmaxf(t0, t1));
@@ -373,7 +372,6 @@ struct ImgSlot {
     short ky_lo;       // first row that can reach the box
     unsigned short nrows; // rows that can reach the box (at most MAXROWS)
     float sx, sy;      // in-plane shift (pixels)
-    float inv_e1[3];   // 1 / e1 (0 where |e1| < 1e-7), for the row clipping
 };
 
 // rows of one image that reach a brick's box (side BS): the box's extent
@@ -843,7 +841,6 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                 S.E1[d] = rint_scaled(D[1 + d]);
                                 S.E2[d] = rint_scaled(D[4 + d]);
                                 S.E1i[d] = (int64_t)S.E1[d];
-                                S.inv_e1[d] = fabsf(D[1 + d]) < 1e-7f ? 0.0f : 1.0f / D[1 + d];
                             }
                             S.ctfA = g.ctf_a * (double)D[7] * g.inv_s2;
                             S.img_base = (uint32_t)__float_as_int(D[0]) * MM;
@@ -892,9 +889,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                             const int ky = S.ky_lo + q;
                             const float *D = imgdat[w0 + s];
                             const float e1f[3] = {D[1], D[2], D[3]}, e2f[3] = {D[4], D[5], D[6]};
-                            const float inv1[3] = {S.inv_e1[0], S.inv_e1[1], S.inv_e1[2]};
                             int x0, x1;
-                            clip_row(e1f, inv1, e2f, halff, ky, lo, hi, x0, x1);
+                            clip_row(e1f, e2f, halff, ky, lo, hi, x0, x1);
                             // the disk: |kx| <= floor(sqrt(k2max - ky^2))
                             const int rem = g.k2max - ky * ky;
                             int kxm = (int)sqrtf((float)max(rem, 0));
