@@ -109,7 +109,7 @@ def main():
         calls.setdefault(name, []).append((s, e))
 
     for _ in range(args.warmup):
-        run.iteration(rot_b, df_b, x_b)
+        run.iteration(rot_b, df_b, x_b, next_poses=(rot_b, df_b))
     torch.cuda.synchronize()
     calls.clear()
     # HIP events around every brick-kernel launch of the timed steps, on the
@@ -119,7 +119,7 @@ def main():
         B.timing_read(k)
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        run.iteration(rot_b, df_b, x_b)
+        run.iteration(rot_b, df_b, x_b, next_poses=(rot_b, df_b))
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
     B.timing_enable(False)

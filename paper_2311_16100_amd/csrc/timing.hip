@@ -24,8 +24,10 @@ hipEvent_t take_event() {
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache write-back and invalidate)
+    // when the event is recorded, which would stall and cool the next launch
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -249,13 +249,32 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     t_log = t0
     it = 0
     eta_cap = eta0
+
+    def poses_of(idx):
+        return ds.rot[idx].contiguous(), ds.defocus[idx].contiguous()
+
+    # the poses of the current and the next batch: the next ones let the
+    # Hutchinson arm compute its next probe product during the line search
+    cur = None
+    perm_next = None
     for epoch in range(max_epochs):
         if decay_epochs and epoch > 0 and epoch % decay_epochs == 0:
             eta_cap *= 0.5
             run.state.eta = min(run.state.eta, eta_cap)
-        perm = torch.from_numpy(synth.epoch_permutation(ds.N, seed, epoch)).to(dev)
+        perm = perm_next if perm_next is not None else torch.from_numpy(
+            synth.epoch_permutation(ds.N, seed, epoch)).to(dev)
+        perm_next = None
         for s in range(0, ds.N - batch + 1, batch):
             idx = perm[s:s + batch]
+            if cur is None:
+                cur = poses_of(idx)
+            if s + 2 * batch <= ds.N:
+                nxt = poses_of(perm[s + batch:s + 2 * batch])
+            elif epoch + 1 < max_epochs:
+                perm_next = torch.from_numpy(synth.epoch_permutation(ds.N, seed, epoch + 1)).to(dev)
+                nxt = poses_of(perm_next[:batch])
+            else:
+                nxt = None
             if ds.streamed:
                 torch.cuda.synchronize()
                 tg = time.perf_counter()
@@ -264,7 +283,8 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
                 res.gen_seconds += time.perf_counter() - tg
             else:
                 xb = ds.images(idx)
-            res.halvings += run.iteration(ds.rot[idx].contiguous(), ds.defocus[idx].contiguous(), xb)
+            res.halvings += run.iteration(cur[0], cur[1], xb, next_poses=nxt)
+            cur = nxt
             del xb
             it += 1
             if progress and time.perf_counter() - t_log > 30.0:

@@ -7,6 +7,10 @@ arithmetic step (gradient, Hessian-vector probes, the running mean and
 exponential average of the diagonal, thresholding, the step, the line-search
 losses) runs in the library's kernels.  The only host work is the line
 search's decision, which needs one read-back of four device scalars per trial.
+The Hutchinson probe product of the next batch does not depend on v (the
+Hessian of the least-squares loss is constant), so when the caller names the
+next batch's poses it is queued behind that read-back and the device keeps
+working while the host decides.
 
 Arms (same loop, same step-size rule):
   "hutchinson"  D estimated on the fly from Rademacher probes (Algorithm 1)
@@ -65,20 +69,33 @@ class Alg1Runner:
         self.g = torch.empty_like(v0)
         self.v_new = torch.empty_like(v0)
         self.zHz = torch.empty((M, M, M), dtype=torch.float32, device=dev) if arm == "hutchinson" else None
+        self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" else None
+        self._queued = None  # (rot, defocus, k) of the probe product already in zHz_next
         # scalars: [0] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data term of f(v')
         self.sc = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.sc_host = torch.zeros(4, dtype=torch.float64, pin_memory=True)
+        self.sc_ready = torch.cuda.Event()
         self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
                                          else B.CSG_WS_GRADIENT, dev)
         self.ws_hutch = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev) if arm == "hutchinson" else None
         self.ws_proj = B.alloc_workspace(grid, batch, B.CSG_WS_PROJECT, dev)
 
-    def iteration(self, rot_I, df_I, x_I) -> int:
+    def iteration(self, rot_I, df_I, x_I, next_poses=None) -> int:
+        """One iteration on the batch (rot_I, df_I, x_I).  `next_poses` =
+        (rot, defocus) of the next call's batch, if known: the Hutchinson arm
+        then computes that batch's probe product during this line search, and
+        the next call uses it when it is given the same two tensors."""
         st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
         st.k += 1
         if self.arm == "hutchinson":
-            # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
-            B.hutchinson_diag(g, o, rot_I, df_I, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
-                              probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
+            q = self._queued
+            if q is not None and q[0] is rot_I and q[1] is df_I and q[2] == st.k:
+                self.zHz, self.zHz_next = self.zHz_next, self.zHz
+            else:
+                # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
+                B.hutchinson_diag(g, o, rot_I, df_I, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
+                                  probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
+            self._queued = None
         B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g, loss_out=self.sc[0:1],
                    deterministic=cfg.deterministic, workspace=self.ws_grad)
         eta = st.eta
@@ -88,11 +105,19 @@ class Alg1Runner:
             B.precond_sgd_step(st.v, self.g, st.D, st.D_avg, self.zHz if first else None, st.k, cfg.beta,
                                self.alpha if st.D is not None else 0.0, eta, v_out=self.v_new,
                                stats_out=self.sc[1:3])
-            first = False
             self.sc[3:4].zero_()
             B.project(g, o, rot_I, df_I, self.v_new, subtract=x_I, out=None, loss=self.sc[3:4], want_out=False,
                       workspace=self.ws_proj)
-            f0, gn, vn2, l1 = self.sc.tolist()
+            self.sc_host.copy_(self.sc, non_blocking=True)
+            self.sc_ready.record()
+            if first and next_poses is not None and self.arm == "hutchinson":
+                rn, dn = next_poses
+                B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
+                                  probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)
+                self._queued = (rn, dn, st.k + 1)
+            first = False
+            self.sc_ready.synchronize()
+            f0, gn, vn2, l1 = self.sc_host.tolist()
             f1 = self.scale * l1 + 0.5 * self.lam * vn2
             if f1 <= f0 - cfg.c * eta * gn:
                 break

@@ -1,0 +1,134 @@
+"""Algorithm 1 (Sec. 3.4) on the GPU against the oracle's step-by-step
+iteration: the same minibatches, probes and threshold on both sides, and per
+iteration the number of halvings of the line search (eq. (stochastic armijo))
+and the step size equal, and the iterate close.
+
+Arms: plain SGD (D-hat = 1), a fixed diagonal, and the Hutchinson estimate
+(running mean, exponential average and threshold of Algorithm 1), the last
+also with each iteration's probe product queued during the previous line
+search (the runner's `next_poses`), which must not change the trajectory.
+The tolerance on the iterate is 1e-4: every iteration applies float32
+operators (each within 1e-5..1e-4 of the oracle) and carries the previous
+iteration's difference forward.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+M, N, BATCH, ITERS = 16, 128, 32, 4
+SEED, PROBE_SEED, N_PROBE = 81, 5, 2
+LAM, BETA, C = 1e-3, 0.9, 0.1
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128).reshape(-1)
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2311_16100_amd import binding
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    binding.lib()
+    grid_o, opt_o = oracle.Grid(M), oracle.Optics()
+    P = oracle.Poses(synth.uniform_rotations(N, SEED), synth.defocus_values(N, 1.0, 3.0, SEED))
+    v_true = synth.blob_volume(M, 6, SEED)
+    # data: the oracle's projections of a blob volume plus a little noise,
+    # rounded to complex64 (the values both sides read)
+    x = oracle.project(grid_o, opt_o, P, v_true) + 0.05 * synth.random_complex((N, M, M), SEED, stream=3)
+    x = x.astype(np.complex64)
+    alpha = float(oracle.alpha_threshold(grid_o, opt_o, P.defocus, LAM))
+    perm = synth.epoch_permutation(N, SEED, 0)
+    batches = [perm[k * BATCH:(k + 1) * BATCH] for k in range(ITERS)]
+    return binding, grid_o, opt_o, P, x, alpha, batches
+
+
+def run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
+    scale = N / BATCH
+    nv = M ** 3
+    if arm == "hutchinson":
+        st = oracle.Alg1State(v=np.zeros(nv, np.complex128), D=np.ones(nv), D_avg=np.zeros(nv), eta=1.0)
+    else:
+        st = oracle.Alg1State(v=np.zeros(nv, np.complex128), D=None, D_avg=None, eta=1.0)
+    out = []
+    for k, I in enumerate(batches):
+        pI = P.subset(I)
+        zHz = None
+        if arm == "hutchinson":
+            zHz = oracle.hutchinson_diag(grid_o, opt_o, pI, N_PROBE, PROBE_SEED, scale, LAM, probe0=k * N_PROBE)
+        h = oracle.alg1_iteration(grid_o, opt_o, pI, x[I], st, scale, LAM, alpha if arm == "hutchinson" else 0.0,
+                                  BETA, C, zHz=zHz, D_hat_fixed=D_fixed)
+        out.append((h, st.eta, st.v.copy()))
+    return out
+
+
+def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False):
+    from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+    g = b.Grid(M)
+    o = b.Optics()
+    dev = torch.device("cuda:0")
+    rot_d = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)
+    df_d = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)
+    x_d = torch.from_numpy(x).to(dev)
+    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED)
+    kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
+    Df = None if D_fixed is None else torch.from_numpy(D_fixed.astype(np.float32).reshape(M, M, M)).to(dev)
+    v0 = torch.zeros((M, M, M), dtype=torch.complex64, device=dev)
+    run = Alg1Runner(g, o, kind, N / BATCH, LAM, alpha if arm != "plain" else 0.0, cfg, v0, D_fixed=Df,
+                     batch=BATCH)
+    poses = []
+    for I in batches:
+        idx = torch.from_numpy(I).to(dev)
+        poses.append((rot_d[idx].contiguous(), df_d[idx].contiguous()))
+    out = []
+    for k, I in enumerate(batches):
+        nxt = None
+        if queue and k + 1 < len(batches):
+            # a copy of the next poses when checking that a mismatch is ignored
+            nxt = tuple(t.clone() for t in poses[k + 1]) if mismatch else poses[k + 1]
+        idx = torch.from_numpy(I).to(dev)
+        h = run.iteration(poses[k][0], poses[k][1], x_d[idx].contiguous(), next_poses=nxt)
+        out.append((h, run.state.eta, run.state.v.reshape(-1).cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("arm,queue", [("plain", False), ("fixed", False), ("hutchinson", False),
+                                       ("hutchinson", True)], ids=["plain", "fixed", "hutchinson", "queued"])
+def test_trajectory_matches_oracle(setup, arm, queue):
+    b, grid_o, opt_o, P, x, alpha, batches = setup
+    D_fixed = None
+    if arm == "fixed":
+        # the exact diagonal, thresholded on the oracle's side so that both
+        # sides use the same D-hat
+        D_fixed = np.maximum(oracle.exact_diag(grid_o, opt_o, P, 1.0, LAM).reshape(-1), alpha)
+        D_fixed = D_fixed.astype(np.float32).astype(np.float64)
+    want = run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed)
+    got = run_gpu(b, P, x, alpha, batches, arm, D_fixed, queue=queue)
+    errs = []
+    for k, ((hw, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
+        assert hg == hw, (arm, k, hg, hw)
+        assert eg == ew, (arm, k)
+        errs.append(rel(vg, vw))
+    print("[alg1] %s%s halvings %s rel err per iteration %s" % (
+        arm, " (queued probes)" if queue else "", [w[0] for w in want], ["%.1e" % e for e in errs]))
+    assert max(errs) <= 1e-4
+    # the iterate moved: the comparison is not between two zero volumes
+    assert np.linalg.norm(want[-1][2]) > 0
+
+
+def test_queued_probe_for_other_tensors_is_recomputed(setup):
+    """next_poses that are not the tensors of the next call (a copy) leave
+    the queued product unused: the trajectory equals the one computed in
+    place."""
+    b, grid_o, opt_o, P, x, alpha, batches = setup
+    a = run_gpu(b, P, x, alpha, batches, "hutchinson")
+    m = run_gpu(b, P, x, alpha, batches, "hutchinson", queue=True, mismatch=True)
+    for (ha, ea, va), (hm, em, vm) in zip(a, m):
+        assert ha == hm and ea == em
+        assert rel(vm, va) <= 1e-5
