@@ -183,7 +183,8 @@ def main():
     achieved = per_image[dominant] * Bsz / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "brick_kernel<%s>" % dominant, "kernel_avg_ms": round(avg_ms, 4), "launches": launches,
+                "kernel": "brick_kernel<%s%s>" % (dominant, ", fixed point" if args.deterministic else ""),
+                "kernel_avg_ms": round(avg_ms, 4), "launches": launches,
                 "bytes_per_image": round(per_image[dominant]), "P": P, "U": round(U),
                 "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items()}}
     # the separate forward + adjoint pair: disk-pixel write 8P and gather 8U
@@ -203,7 +204,7 @@ def main():
     if dominant in ms:
         roofline["call_ms"] = round(ms[dominant], 4)
         roofline["call_frac"] = round(per_image[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    tr = traffic_record(dominant, Bsz, M)
+    tr = traffic_record(dominant, Bsz, M, args.deterministic)
     if tr:
         # measured HBM bytes of one launch over the same average duration (GB/s)
         roofline["traffic"] = round(tr["hbm_bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
@@ -263,11 +264,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_record(kernel, images, M):
+def traffic_record(kernel, images, M, deterministic=False):
     """HBM bytes per launch of `kernel` from the committed PMC summary
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel), or None when
-    there is none for this kernel and workload or the kernel sources changed
-    since the counters were taken."""
+    there is none for this kernel, mode (fast or fixed-point deterministic;
+    a record without the field was taken on the fast path) and workload, or
+    the kernel sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_SUMMARY) as fh:
             line = next(l for l in fh if l.startswith("traffic-record:"))
@@ -275,6 +277,8 @@ def traffic_record(kernel, images, M):
         return None
     rec = json.loads(line.split(":", 1)[1])
     if rec.get("kernel") != kernel or rec.get("images") != images or rec.get("M") != M:
+        return None
+    if bool(rec.get("deterministic", False)) != bool(deterministic):
         return None
     if rec.get("sources_sha256") != kernel_sources_sha256():
         return None
