@@ -13,7 +13,10 @@ image read 8P, gather 8U, scatter read-modify-write 16U; P disk pixels, U
 distinct voxels an image's stencils touch) over its average launch duration
 from HIP events recorded around each launch on its stream; `traffic` is the
 measured HBM rate of the same launches from the committed counter summary,
-when it was taken on the current kernel sources.  `fwd_adj_roofline` is the
+when it was taken on the current kernel sources and mode; `compulsory` gives
+the bytes any implementation must move once per launch (for the gradient the
+disk pixels of the batch, one volume read and one read-modify-write of the
+accumulator) and their rate against the peak.  `fwd_adj_roofline` is the
 same figure for the separate forward and adjoint kernels together (16P + 24U
 bytes per image over the sum of their average durations).
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
@@ -187,6 +190,16 @@ def main():
                 "kernel_avg_ms": round(avg_ms, 4), "launches": launches,
                 "bytes_per_image": round(per_image[dominant]), "P": P, "U": round(U),
                 "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items()}}
+    # compulsory bytes of one launch: what any implementation must move once
+    # (the batch's disk pixels, plus one read of the volume and one
+    # read-modify-write of the accumulator for the gradient; one
+    # read-modify-write of the packed accumulator for the probe product; one
+    # volume read for the loss-only forward)
+    nvox = M ** 3
+    compulsory = {"gradient": 8 * P * Bsz + 24 * nvox, "hvp": 16 * nvox, "project": 8 * P * Bsz + 8 * nvox}
+    cb = compulsory[dominant]
+    roofline["compulsory"] = {"bytes_per_launch": cb,
+                              "frac": round(cb / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     # the separate forward + adjoint pair: disk-pixel write 8P and gather 8U
     # (project), image read 8P and read-modify-write 16U (backproject), over
     # the two kernels' average durations (the zero fill outside the disk is a
