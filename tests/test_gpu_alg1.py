@@ -6,7 +6,8 @@ and the step size equal, and the iterate close.
 Arms: plain SGD (D-hat = 1), a fixed diagonal, and the Hutchinson estimate
 (running mean, exponential average and threshold of Algorithm 1), the last
 also with each iteration's probe product queued during the previous line
-search (the runner's `next_poses`), which must not change the trajectory.
+search (the runner's `next_poses`), which must not change the trajectory,
+and with the deterministic (fixed-point) gradient.
 The tolerance on the iterate is 1e-4: every iteration applies float32
 operators (each within 1e-5..1e-4 of the oracle) and carries the previous
 iteration's difference forward.
@@ -68,7 +69,7 @@ def run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
     return out
 
 
-def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False):
+def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False):
     from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
     g = b.Grid(M)
     o = b.Optics()
@@ -76,7 +77,7 @@ def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=Fa
     rot_d = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)
     df_d = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)
     x_d = torch.from_numpy(x).to(dev)
-    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED)
+    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED, deterministic=deterministic)
     kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
     Df = None if D_fixed is None else torch.from_numpy(D_fixed.astype(np.float32).reshape(M, M, M)).to(dev)
     v0 = torch.zeros((M, M, M), dtype=torch.complex64, device=dev)
@@ -98,9 +99,11 @@ def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=Fa
     return out
 
 
-@pytest.mark.parametrize("arm,queue", [("plain", False), ("fixed", False), ("hutchinson", False),
-                                       ("hutchinson", True)], ids=["plain", "fixed", "hutchinson", "queued"])
-def test_trajectory_matches_oracle(setup, arm, queue):
+@pytest.mark.parametrize("arm,queue,det", [("plain", False, False), ("fixed", False, False),
+                                           ("hutchinson", False, False), ("hutchinson", True, False),
+                                           ("hutchinson", True, True)],
+                         ids=["plain", "fixed", "hutchinson", "queued", "queued-deterministic"])
+def test_trajectory_matches_oracle(setup, arm, queue, det):
     b, grid_o, opt_o, P, x, alpha, batches = setup
     D_fixed = None
     if arm == "fixed":
@@ -109,14 +112,15 @@ def test_trajectory_matches_oracle(setup, arm, queue):
         D_fixed = np.maximum(oracle.exact_diag(grid_o, opt_o, P, 1.0, LAM).reshape(-1), alpha)
         D_fixed = D_fixed.astype(np.float32).astype(np.float64)
     want = run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed)
-    got = run_gpu(b, P, x, alpha, batches, arm, D_fixed, queue=queue)
+    got = run_gpu(b, P, x, alpha, batches, arm, D_fixed, queue=queue, deterministic=det)
     errs = []
     for k, ((hw, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
         assert hg == hw, (arm, k, hg, hw)
         assert eg == ew, (arm, k)
         errs.append(rel(vg, vw))
-    print("[alg1] %s%s halvings %s rel err per iteration %s" % (
-        arm, " (queued probes)" if queue else "", [w[0] for w in want], ["%.1e" % e for e in errs]))
+    print("[alg1] %s%s%s halvings %s rel err per iteration %s" % (
+        arm, " (queued probes)" if queue else "", " (deterministic gradient)" if det else "",
+        [w[0] for w in want], ["%.1e" % e for e in errs]))
     assert max(errs) <= 1e-4
     # the iterate moved: the comparison is not between two zero volumes
     assert np.linalg.norm(want[-1][2]) > 0
