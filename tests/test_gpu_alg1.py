@@ -10,8 +10,12 @@ search (the runner's `next_poses`), which must not change the trajectory,
 and with the deterministic (fixed-point) gradient.
 The tolerance on the iterate is 1e-4: every iteration applies float32
 operators (each within 1e-5..1e-4 of the oracle) and carries the previous
-iteration's difference forward.
+iteration's difference forward.  Sizes: 16^3 (one brick and a 4-voxel tail
+per axis) and 40^3 (three bricks and a 4-voxel tail), with line-search
+decisions whose margins in the oracle are at least a quarter of the loss.
 """
+from collections import namedtuple
+
 import numpy as np
 import pytest
 import torch
@@ -21,8 +25,10 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-M, N, BATCH, ITERS = 16, 128, 32, 4
-SEED, PROBE_SEED, N_PROBE = 81, 5, 2
+Case = namedtuple("Case", "M N BATCH ITERS SEED BLOBS")
+SMALL = Case(16, 128, 32, 4, 81, 6)
+BRICKS = Case(40, 240, 80, 3, 82, 8)
+PROBE_SEED, N_PROBE = 5, 2
 LAM, BETA, C = 1e-3, 0.9, 0.1
 
 
@@ -32,27 +38,33 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.fixture(scope="module")
-def setup():
+_CACHE = {}
+
+
+def make(case):
+    if case in _CACHE:
+        return _CACHE[case]
     from paper_2311_16100_amd import binding
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     binding.lib()
+    M, N = case.M, case.N
     grid_o, opt_o = oracle.Grid(M), oracle.Optics()
-    P = oracle.Poses(synth.uniform_rotations(N, SEED), synth.defocus_values(N, 1.0, 3.0, SEED))
-    v_true = synth.blob_volume(M, 6, SEED)
+    P = oracle.Poses(synth.uniform_rotations(N, case.SEED), synth.defocus_values(N, 1.0, 3.0, case.SEED))
+    v_true = synth.blob_volume(M, case.BLOBS, case.SEED)
     # data: the oracle's projections of a blob volume plus a little noise,
     # rounded to complex64 (the values both sides read)
-    x = oracle.project(grid_o, opt_o, P, v_true) + 0.05 * synth.random_complex((N, M, M), SEED, stream=3)
+    x = oracle.project(grid_o, opt_o, P, v_true) + 0.05 * synth.random_complex((N, M, M), case.SEED, stream=3)
     x = x.astype(np.complex64)
     alpha = float(oracle.alpha_threshold(grid_o, opt_o, P.defocus, LAM))
-    perm = synth.epoch_permutation(N, SEED, 0)
-    batches = [perm[k * BATCH:(k + 1) * BATCH] for k in range(ITERS)]
-    return binding, grid_o, opt_o, P, x, alpha, batches
+    perm = synth.epoch_permutation(N, case.SEED, 0)
+    batches = [perm[k * case.BATCH:(k + 1) * case.BATCH] for k in range(case.ITERS)]
+    _CACHE[case] = (binding, grid_o, opt_o, P, x, alpha, batches)
+    return _CACHE[case]
 
 
-def run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
-    scale = N / BATCH
-    nv = M ** 3
+def run_oracle(case, grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
+    scale = case.N / case.BATCH
+    nv = case.M ** 3
     if arm == "hutchinson":
         st = oracle.Alg1State(v=np.zeros(nv, np.complex128), D=np.ones(nv), D_avg=np.zeros(nv), eta=1.0)
     else:
@@ -69,8 +81,9 @@ def run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
     return out
 
 
-def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False):
+def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False):
     from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+    M = case.M
     g = b.Grid(M)
     o = b.Optics()
     dev = torch.device("cuda:0")
@@ -81,8 +94,8 @@ def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=Fa
     kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
     Df = None if D_fixed is None else torch.from_numpy(D_fixed.astype(np.float32).reshape(M, M, M)).to(dev)
     v0 = torch.zeros((M, M, M), dtype=torch.complex64, device=dev)
-    run = Alg1Runner(g, o, kind, N / BATCH, LAM, alpha if arm != "plain" else 0.0, cfg, v0, D_fixed=Df,
-                     batch=BATCH)
+    run = Alg1Runner(g, o, kind, case.N / case.BATCH, LAM, alpha if arm != "plain" else 0.0, cfg, v0, D_fixed=Df,
+                     batch=case.BATCH)
     poses = []
     for I in batches:
         idx = torch.from_numpy(I).to(dev)
@@ -99,40 +112,41 @@ def run_gpu(b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=Fa
     return out
 
 
-@pytest.mark.parametrize("arm,queue,det", [("plain", False, False), ("fixed", False, False),
-                                           ("hutchinson", False, False), ("hutchinson", True, False),
-                                           ("hutchinson", True, True)],
-                         ids=["plain", "fixed", "hutchinson", "queued", "queued-deterministic"])
-def test_trajectory_matches_oracle(setup, arm, queue, det):
-    b, grid_o, opt_o, P, x, alpha, batches = setup
+@pytest.mark.parametrize("case,arm,queue,det", [
+    (SMALL, "plain", False, False), (SMALL, "fixed", False, False), (SMALL, "hutchinson", False, False),
+    (SMALL, "hutchinson", True, False), (SMALL, "hutchinson", True, True),
+    (BRICKS, "plain", False, False), (BRICKS, "hutchinson", True, False)],
+    ids=["plain", "fixed", "hutchinson", "queued", "queued-deterministic", "M40-plain", "M40-queued"])
+def test_trajectory_matches_oracle(case, arm, queue, det):
+    b, grid_o, opt_o, P, x, alpha, batches = make(case)
     D_fixed = None
     if arm == "fixed":
         # the exact diagonal, thresholded on the oracle's side so that both
         # sides use the same D-hat
         D_fixed = np.maximum(oracle.exact_diag(grid_o, opt_o, P, 1.0, LAM).reshape(-1), alpha)
         D_fixed = D_fixed.astype(np.float32).astype(np.float64)
-    want = run_oracle(grid_o, opt_o, P, x, alpha, batches, arm, D_fixed)
-    got = run_gpu(b, P, x, alpha, batches, arm, D_fixed, queue=queue, deterministic=det)
+    want = run_oracle(case, grid_o, opt_o, P, x, alpha, batches, arm, D_fixed)
+    got = run_gpu(case, b, P, x, alpha, batches, arm, D_fixed, queue=queue, deterministic=det)
     errs = []
     for k, ((hw, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
         assert hg == hw, (arm, k, hg, hw)
         assert eg == ew, (arm, k)
         errs.append(rel(vg, vw))
-    print("[alg1] %s%s%s halvings %s rel err per iteration %s" % (
-        arm, " (queued probes)" if queue else "", " (deterministic gradient)" if det else "",
+    print("[alg1] M=%d %s%s%s halvings %s rel err per iteration %s" % (
+        case.M, arm, " (queued probes)" if queue else "", " (deterministic gradient)" if det else "",
         [w[0] for w in want], ["%.1e" % e for e in errs]))
     assert max(errs) <= 1e-4
     # the iterate moved: the comparison is not between two zero volumes
     assert np.linalg.norm(want[-1][2]) > 0
 
 
-def test_queued_probe_for_other_tensors_is_recomputed(setup):
+def test_queued_probe_for_other_tensors_is_recomputed():
     """next_poses that are not the tensors of the next call (a copy) leave
     the queued product unused: the trajectory equals the one computed in
     place."""
-    b, grid_o, opt_o, P, x, alpha, batches = setup
-    a = run_gpu(b, P, x, alpha, batches, "hutchinson")
-    m = run_gpu(b, P, x, alpha, batches, "hutchinson", queue=True, mismatch=True)
+    b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
+    a = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson")
+    m = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", queue=True, mismatch=True)
     for (ha, ea, va), (hm, em, vm) in zip(a, m):
         assert ha == hm and ea == em
         assert rel(vm, va) <= 1e-5
