@@ -295,12 +295,15 @@ int csg_shell_sums(const csg_grid *grid, const float *u, const float *v, double 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support, not part of the method).  While
  * enabled, every launch of a brick-binned operator kernel is bracketed by two
- * HIP events recorded on the stream the kernel is launched on.
+ * HIP events recorded on the stream the kernel is launched on (timing-only
+ * events, without the system-scope cache write-back on record).
  * csg_timing_read waits for the recorded events of one kernel, returns the
  * summed duration (ms) and the number of launches recorded since the last
  * read of that kernel, and forgets them.  At most 8192 launches per kernel
  * are kept between reads; later ones are not recorded.  Launches of the
- * nearest-neighbour and deterministic paths (other kernels) are not timed.
+ * nearest-neighbour path (other kernels) are not timed; the fixed-point
+ * brick kernels of the deterministic mode are timed under the same index as
+ * the fast ones.
  * Results of the operators do not depend on the setting.
  *   kernel: CSG_KERNEL_PROJECT     forward projection (csg_project)
  *           CSG_KERNEL_BACKPROJECT adjoint (csg_backproject, fast mode)
