@@ -226,14 +226,16 @@ def high_band_mask(M: int, r_max: float, device) -> torch.Tensor:
 def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
             eval_every: int = 5, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
             seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball",
-            deterministic: bool = False, progress=None) -> RunResult:
+            deterministic: bool = False, progress=None, queue_probes: bool = True) -> RunResult:
     """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
     the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target.
     `decay_epochs` > 0 halves the step-size cap every that many epochs
     (identically in every arm).  Wall time counts iterations and error
     evaluations; for a streamed data set the regeneration of each batch's
     images is timed apart (`gen_seconds`) and not counted.
-    `deterministic` selects the bitwise-reproducible adjoint."""
+    `deterministic` selects the bitwise-reproducible adjoint.  With
+    `queue_probes` the runner is told the next batch's poses (the Hutchinson
+    arm then computes its next probe product during the line search)."""
     dev = ds.device
     scale = ds.N / batch
     alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
@@ -268,7 +270,9 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
             idx = perm[s:s + batch]
             if cur is None:
                 cur = poses_of(idx)
-            if s + 2 * batch <= ds.N:
+            if not queue_probes:
+                nxt = None
+            elif s + 2 * batch <= ds.N:
                 nxt = poses_of(perm[s + batch:s + 2 * batch])
             elif epoch + 1 < max_epochs:
                 perm_next = torch.from_numpy(synth.epoch_permutation(ds.N, seed, epoch + 1)).to(dev)

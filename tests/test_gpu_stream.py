@@ -44,3 +44,17 @@ def test_deterministic_arm_is_reproducible(E):
     # Armijo losses are double-precision sums whose order may vary
     ea, eb = [e[2] for e in a.errors], [e[2] for e in b.errors]
     assert len(ea) == len(eb) and max(abs(x - y) / y for x, y in zip(ea, eb)) < 1e-5
+
+
+def test_queued_probes_leave_the_run_unchanged(E):
+    """The look-ahead over batches (across the epoch boundary too: 31 batches
+    of 32 per epoch) feeds the same poses and images as the plain loop."""
+    ds = E.make_dataset(32, 1000, 20, 14, float("inf"))
+    v_star, _, _ = E.ground_truth(ds)
+    a = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9)
+    b = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9, queue_probes=False)
+    assert a.iterations == b.iterations == 62
+    # float atomics differ between the runs; a batch whose images and poses
+    # did not belong together would move the errors far beyond this
+    ea, eb = [e[2] for e in a.errors], [e[2] for e in b.errors]
+    assert len(ea) == len(eb) and max(abs(x - y) / y for x, y in zip(ea, eb)) < 1e-3
