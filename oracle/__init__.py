@@ -292,6 +292,7 @@ class Alg1State:
     D_avg: np.ndarray | None
     eta: float
     k: int = 0
+    capped: int = 0  # iterations whose line search stopped at max_halvings
 
 
 def precond_update(D, D_avg, zHz, k: int, beta: float, alpha: float):
@@ -321,7 +322,15 @@ def alg1_iteration(grid, optics, poses_I, x_I, state: Alg1State, scale: float, l
     """One iteration k of Algorithm 1 on the minibatch (poses_I, x_I).
     zHz: the probe sample z (.) H_I z for this iteration (None: no update of D,
     e.g. plain SGD or a fixed preconditioner).  D_hat_fixed overrides D-hat
-    (learned or precomputed preconditioner).  Returns the number of halvings."""
+    (learned or precomputed preconditioner).  Returns the number of halvings.
+
+    The line search of eq. (stochastic armijo) halves eta until the
+    sufficient-decrease test holds.  The paper's loop has no bound; here it
+    stops after max_halvings halvings and keeps the last (tiny) trial step,
+    counting the iteration in state.capped: in floating point the test can
+    fail on rounding alone once the decrease is below the resolution of the
+    minibatch loss.  A loss or gradient norm that is not finite raises
+    FloatingPointError (no step is taken)."""
     state.k += 1
     k = state.k
     if D_hat_fixed is not None:
@@ -341,12 +350,15 @@ def alg1_iteration(grid, optics, poses_I, x_I, state: Alg1State, scale: float, l
     while True:
         v_new, gn = precond_step(state.v, g, D_hat, eta)
         f1 = loss(grid, optics, poses_I, v_new, x_I, scale, lam)
+        if not (np.isfinite(f0) and np.isfinite(f1) and np.isfinite(gn)):
+            raise FloatingPointError("Armijo line search: f(v) = %r, f(v') = %r, |g|^2_D^-1 = %r" % (f0, f1, gn))
         if f1 <= f0 - c * eta * gn:
+            break
+        if halvings >= max_halvings:
+            state.capped += 1
             break
         eta /= 2.0
         halvings += 1
-        if halvings > max_halvings:
-            raise RuntimeError("Armijo line search did not terminate")
     state.v = v_new
     state.eta = eta
     return halvings

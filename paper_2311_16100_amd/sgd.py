@@ -16,9 +16,15 @@ Arms (same loop, same step-size rule):
   "hutchinson"  D estimated on the fly from Rademacher probes (Algorithm 1)
   "fixed"       a given diagonal D held fixed (precomputed / learned / exact)
   "plain"       D_hat = 1 (no preconditioner)
+
+Line search bounds (the same rule as the oracle's iteration): after
+max_halvings failed halvings the last trial step is kept and the iteration
+is counted in `capped`; a loss or gradient norm that is not finite raises
+CsgError before any step is taken.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import torch
@@ -119,6 +125,10 @@ class Alg1Runner:
             self.sc_ready.synchronize()
             f0, gn, vn2, l1 = self.sc_host.tolist()
             f1 = self.scale * l1 + 0.5 * self.lam * vn2
+            if not (math.isfinite(f0) and math.isfinite(f1) and math.isfinite(gn)):
+                # v is left as it was (the trial went to v_new)
+                raise B.CsgError("Armijo line search at iteration %d: f(v) = %r, f(v') = %r, |g|^2_D^-1 = %r "
+                                 "(non-finite input or preconditioner)" % (st.k, f0, f1, gn))
             if f1 <= f0 - cfg.c * eta * gn:
                 break
             if halvings >= cfg.max_halvings:

@@ -150,3 +150,114 @@ def test_queued_probe_for_other_tensors_is_recomputed():
     for (ha, ea, va), (hm, em, vm) in zip(a, m):
         assert ha == hm and ea == em
         assert rel(vm, va) <= 1e-5
+
+
+def _c1_problem():
+    """The small workload (32^3 volume of 20 blobs, N = 1000 Haar-uniform
+    poses, defocus 1-3 um, 300 kV / Cs 2.7 mm / A 0.1, SNR 0.1) as both sides
+    read it: complex64 images = the oracle's noise-free projections plus
+    complex Gaussian noise keyed by (seed, image), lambda = sigma^2 / tau^2."""
+    W = synth.WORKLOADS["small_32"]
+    M, N = W.M, W.N
+    g, o = oracle.Grid(M), oracle.Optics()
+    P = oracle.Poses(synth.uniform_rotations(N, W.seed), synth.defocus_values(N, *W.defocus_um, W.seed))
+    v_true = synth.blob_volume(M, W.n_blobs, W.seed)
+    y = oracle.project(g, o, P, v_true)
+    ax = np.arange(M) - M // 2
+    disk = (ax[:, None] ** 2 + ax[None, :] ** 2) <= g.rmax ** 2
+    sigma2 = float(np.mean(np.abs(y[:1024][:, disk]) ** 2)) / W.snr
+    x = (y + synth.complex_noise((N, M, M), sigma2, W.seed) * disk).astype(np.complex64)
+    lam = sigma2 / float(np.mean(np.abs(v_true[synth.ball_mask(M, g.rmax)]) ** 2))
+    return W, g, o, P, x, lam
+
+
+def test_small_workload_trajectory_matches_oracle():
+    """Algorithm 1 on the small workload as specified (batch 32, 50
+    Rademacher probes per iteration, SNR 0.1): ten iterations of the
+    Hutchinson arm with queued probe products against the oracle's
+    iteration.  The oracle's line-search decisions here have margins of at
+    least 4% of the loss."""
+    from paper_2311_16100_amd import binding as b
+    from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+    W, g_o, o_o, P, x, lam = _c1_problem()
+    M, N, Bsz, n_probe, iters = W.M, W.N, W.batch, W.n_probe, 10
+    alpha = float(oracle.alpha_threshold(g_o, o_o, P.defocus, lam))
+    scale = N / Bsz
+    perm = synth.epoch_permutation(N, W.seed, 0)
+    batches = [perm[k * Bsz:(k + 1) * Bsz] for k in range(iters)]
+    st = oracle.Alg1State(v=np.zeros(M ** 3, np.complex128), D=np.ones(M ** 3), D_avg=np.zeros(M ** 3), eta=1.0)
+    want = []
+    for k, I in enumerate(batches):
+        pI = P.subset(I)
+        zHz = oracle.hutchinson_diag(g_o, o_o, pI, n_probe, PROBE_SEED, scale, lam, probe0=k * n_probe)
+        h = oracle.alg1_iteration(g_o, o_o, pI, x[I], st, scale, lam, alpha, BETA, C, zHz=zHz)
+        want.append((h, st.eta, st.v.copy()))
+    dev = torch.device("cuda:0")
+    rot_d = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)
+    df_d = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)
+    x_d = torch.from_numpy(x).to(dev)
+    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=n_probe, probe_seed=PROBE_SEED)
+    run = Alg1Runner(b.Grid(M), b.Optics(), "hutchinson", scale, lam, alpha, cfg,
+                     torch.zeros((M, M, M), dtype=torch.complex64, device=dev), batch=Bsz)
+    poses = [(rot_d[torch.from_numpy(I).to(dev)].contiguous(), df_d[torch.from_numpy(I).to(dev)].contiguous())
+             for I in batches]
+    errs = []
+    for k, I in enumerate(batches):
+        nxt = poses[k + 1] if k + 1 < iters else None
+        h = run.iteration(poses[k][0], poses[k][1], x_d[torch.from_numpy(I).to(dev)].contiguous(), next_poses=nxt)
+        assert h == want[k][0], (k, h, want[k][0])
+        assert run.state.eta == want[k][1]
+        errs.append(rel(run.state.v.reshape(-1).cpu().numpy(), want[k][2]))
+    print("[alg1] small workload: halvings %s, rel err per iteration %s" % (
+        [w[0] for w in want], ["%.1e" % e for e in errs]))
+    assert max(errs) <= 1e-4
+    assert run.state.capped == 0 and st.capped == 0
+
+
+def test_line_search_cap_matches_oracle():
+    """The line search's bound: with c = 1e9 the sufficient-decrease test
+    fails at every trial by a margin of the order of the loss, so both sides
+    halve 30 times, keep the last trial step (eta = 2^-30) and count the
+    iteration as capped."""
+    from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+    b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
+    M = SMALL.M
+    scale = SMALL.N / SMALL.BATCH
+    I = batches[0]
+    st = oracle.Alg1State(v=np.zeros(M ** 3, np.complex128), D=None, D_avg=None, eta=1.0)
+    hw = oracle.alg1_iteration(grid_o, opt_o, P.subset(I), x[I], st, scale, LAM, 0.0, BETA, 1e9)
+    assert hw == 30 and st.capped == 1
+    dev = torch.device("cuda:0")
+    idx = torch.from_numpy(I).to(dev)
+    rot = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)[idx].contiguous()
+    df = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)[idx].contiguous()
+    cfg = Alg1Config(beta=BETA, c=1e9, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED)
+    run = Alg1Runner(b.Grid(M), b.Optics(), "plain", scale, LAM, 0.0, cfg,
+                     torch.zeros((M, M, M), dtype=torch.complex64, device=dev), batch=SMALL.BATCH)
+    hg = run.iteration(rot, df, torch.from_numpy(x[I]).to(dev).contiguous())
+    assert hg == 30 and run.state.capped == 1
+    assert run.state.eta == st.eta == 2.0 ** -30
+    assert rel(run.state.v.reshape(-1).cpu().numpy(), st.v) <= 1e-4
+
+
+def test_non_finite_image_raises():
+    """A NaN pixel in the batch makes the loss non-finite: the runner raises
+    CsgError instead of taking a NaN step, and v is unchanged."""
+    from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
+    b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
+    M = SMALL.M
+    dev = torch.device("cuda:0")
+    I = batches[0]
+    idx = torch.from_numpy(I).to(dev)
+    rot = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)[idx].contiguous()
+    df = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)[idx].contiguous()
+    xb = x[I].copy()
+    xb[3, M // 2 + 1, M // 2 + 2] = np.nan
+    xd = torch.from_numpy(xb).to(dev).contiguous()
+    for arm in ("plain", "hutchinson"):
+        cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED)
+        run = Alg1Runner(b.Grid(M), b.Optics(), arm, SMALL.N / SMALL.BATCH, LAM, alpha if arm != "plain" else 0.0,
+                         cfg, torch.zeros((M, M, M), dtype=torch.complex64, device=dev), batch=SMALL.BATCH)
+        with pytest.raises(b.CsgError, match="non-finite"):
+            run.iteration(rot, df, xd)
+        assert torch.count_nonzero(run.state.v).item() == 0

@@ -241,24 +241,164 @@ def test_fsc_identities(orc):
     assert np.all(np.abs(f[3:]) < 0.5)
 
 
+def _shell_counts_integer(M, R):
+    """(P_x(R), P_v(R)) by integer arithmetic alone: round(|k|) = R exactly
+    when (2R - 1)^2 <= 4|k|^2 < (2R + 1)^2 (|k|^2 is an integer, so |k| is
+    never a half-integer and the rounding has no ties)."""
+    ax = np.arange(M, dtype=np.int64) - M // 2
+    k2_2 = ax[:, None] ** 2 + ax[None, :] ** 2
+    k2_3 = k2_2[None, :, :] + (ax ** 2)[:, None, None]
+    lo, hi = (2 * R - 1) ** 2 if R > 0 else -1, (2 * R + 1) ** 2
+    px = int(np.count_nonzero(4 * k2_2 < hi) - np.count_nonzero(4 * k2_2 < lo))
+    pv = int(np.count_nonzero(4 * k2_3 < hi) - np.count_nonzero(4 * k2_3 < lo))
+    return px, pv
+
+
+# P_x(R) / P_v(R) at R = M/2 - 1, the shell of eq. (thresh value) for the
+# workloads' grids, as exact integer ratios (enumerated independently of the
+# oracle when the workloads were specified).
+SHELL_RATIOS = {32: 0.03204, 64: 0.01581, 128: 0.00745, 256: 0.00412}
+
+
 def test_threshold_shell_counts(orc):
     # P_x(R), P_v(R) of eq. (thresh value): unit-thick shells round(|k|) = R.
-    # Summed over R <= Rm they count the lattice points of the disk / ball of
-    # radius Rm + 1/2 (Gauss circle problem: area pi r^2 and volume 4/3 pi r^3
-    # up to a boundary term); a single shell fluctuates by several percent, so
-    # its ratio is only required to be near 2 pi R / (4 pi R^2) = 1/(2R).
-    for M in (32, 64, 128, 256):
-        Rm = M // 2 - 2
-        cx = sum(orc.shell_counts(M, R)[0] for R in range(Rm + 1)) if M <= 64 else None
-        if cx is not None:
-            r = Rm + 0.5
-            cv = sum(orc.shell_counts(M, R)[1] for R in range(Rm + 1))
-            assert cx == pytest.approx(math.pi * r * r, rel=0.02)
-            assert cv == pytest.approx(4.0 / 3.0 * math.pi * r ** 3, rel=0.02)
+    # Exact against an integer count, for every shell of small grids and the
+    # threshold shell of the workload grids; the ratios reproduce the
+    # enumerated values to their printed digits.  A floor(|k|) shell
+    # definition is 6% off at M = 32, so it fails here.
+    for M in (8, 16, 32):
+        for R in range(M // 2):
+            assert orc.shell_counts(M, R) == _shell_counts_integer(M, R)
+    for M, ratio in SHELL_RATIOS.items():
         R = M // 2 - 1
         px, pv = orc.shell_counts(M, R)
-        assert px / pv == pytest.approx(1.0 / (2 * R), rel=0.15)
+        assert (px, pv) == _shell_counts_integer(M, R)
+        assert px / pv == pytest.approx(ratio, abs=5e-6)
+    # Summed over R <= Rm the shells count the lattice points of the disk /
+    # ball of radius Rm + 1/2 (Gauss circle problem: area pi r^2 and volume
+    # 4/3 pi r^3 up to a boundary term).
+    for M in (32, 64):
+        Rm = M // 2 - 2
+        cx = sum(orc.shell_counts(M, R)[0] for R in range(Rm + 1))
+        cv = sum(orc.shell_counts(M, R)[1] for R in range(Rm + 1))
+        r = Rm + 0.5
+        assert cx == pytest.approx(math.pi * r * r, rel=0.02)
+        assert cv == pytest.approx(4.0 / 3.0 * math.pi * r ** 3, rel=0.02)
     # alpha: with no CTF it is P_x/P_v * N + lambda
     grid = orc.Grid(32)
     px, pv = orc.shell_counts(32, 15)
     assert orc.alpha_threshold(grid, orc.NO_CTF, np.zeros(50), 0.5) == pytest.approx(px / pv * 50 + 0.5)
+
+
+def test_shell_pin_rejects_floor_shells():
+    # the pin above is sensitive to the shell definition: floor(|k|) = R
+    # shells give ratios 1-6% away from the enumerated ones
+    for M, ratio in SHELL_RATIOS.items():
+        R = M // 2 - 1
+        ax = np.arange(M) - M // 2
+        r2 = np.floor(np.sqrt(ax[:, None] ** 2 + ax[None, :] ** 2))
+        r3 = np.floor(np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2))
+        wrong = np.sum(r2 == R) / np.sum(r3 == R)
+        assert abs(wrong - ratio) > 5e-6
+
+
+def _ema_closed_form(samples, beta):
+    """D^(k) of Algorithm 1 written out: with D^(0) = 1 and m_j the mean of
+    the first j probe samples, D^(k) = beta^k + (1 - beta) sum_j beta^(k-j) m_j."""
+    k = len(samples)
+    means = [np.mean(samples[:j], axis=0) for j in range(1, k + 1)]
+    D = beta ** k * np.ones_like(samples[0])
+    for j, m in enumerate(means, start=1):
+        D = D + (1.0 - beta) * beta ** (k - j) * m
+    return D
+
+
+def _running_mean_ok(update, beta=0.9, k_max=7, n=257, seed=5):
+    rng = np.random.default_rng(seed)
+    samples = [rng.uniform(0.1, 50.0, n) for _ in range(k_max)]
+    D, D_avg = np.ones(n), np.zeros(n)
+    for k in range(1, k_max + 1):
+        D, D_avg, _ = update(D, D_avg, samples[k - 1], k, beta, 0.0)
+        if not np.allclose(D_avg, np.mean(samples[:k], axis=0), rtol=1e-13, atol=0):
+            return False
+        if not np.allclose(D, _ema_closed_form(samples[:k], beta), rtol=1e-13, atol=0):
+            return False
+    return True
+
+
+def test_running_mean_and_ema_closed_form(orc):
+    # Algorithm 1's running-mean line: after k probe samples D_avg is their
+    # plain mean, and D follows the exponential average from D^(0) = 1 in the
+    # closed form above.  Checked on precond_update and through
+    # alg1_iteration (which must call it with the iteration counter k).
+    assert _running_mean_ok(orc.precond_update)
+    M, N = 8, 6
+    grid, opt = orc.Grid(M), orc.Optics()
+    poses = orc.Poses(synth.uniform_rotations(N, seed=72), synth.defocus_values(N, 1.0, 3.0, seed=72))
+    x = synth.random_complex((N, M, M), seed=73).astype(np.complex128)
+    st = orc.Alg1State(v=np.zeros(M ** 3, np.complex128), D=np.ones(M ** 3), D_avg=np.zeros(M ** 3), eta=1.0)
+    rng = np.random.default_rng(74)
+    samples = []
+    for _ in range(5):
+        s = rng.uniform(1.0, 20.0, M ** 3)
+        samples.append(s)
+        orc.alg1_iteration(grid, opt, poses, x, st, 1.0, 0.1, 0.5, 0.9, 0.1, zHz=s)
+        assert np.allclose(st.D_avg, np.mean(samples, axis=0), rtol=1e-13, atol=0)
+        assert np.allclose(st.D, _ema_closed_form(samples, 0.9), rtol=1e-13, atol=0)
+
+
+def test_running_mean_pin_rejects_garbled_update(orc):
+    # the printed eq. (hutch update), D_avg = (1/k) z (.) Hz (no running sum),
+    # and an update that forgets the (k-1)/k factor both fail the pin
+    def garbled(D, D_avg, zHz, k, beta, alpha):
+        D_avg = zHz / k
+        D = beta * D + (1.0 - beta) * D_avg
+        return D, D_avg, np.maximum(np.abs(D), alpha)
+
+    def no_decay(D, D_avg, zHz, k, beta, alpha):
+        D_avg = D_avg + zHz / k
+        D = beta * D + (1.0 - beta) * D_avg
+        return D, D_avg, np.maximum(np.abs(D), alpha)
+
+    def ema_of_sample(D, D_avg, zHz, k, beta, alpha):
+        D_avg = (k - 1) / k * D_avg + zHz / k
+        D = beta * D + (1.0 - beta) * zHz
+        return D, D_avg, np.maximum(np.abs(D), alpha)
+
+    for wrong in (garbled, no_decay, ema_of_sample):
+        assert not _running_mean_ok(wrong)
+
+
+def test_alg1_line_search_cap_keeps_last_step(orc):
+    # With c = 2 the sufficient-decrease test of eq. (stochastic armijo) fails
+    # for every eta > 0 on a convex quadratic (the decrease is at most eta
+    # |g|^2_D^-1 to first order), so the line search runs into its bound:
+    # after 30 halvings the last trial step, eta = 2^-30 eta0, is kept and the
+    # iteration is counted as capped.
+    M, N = 8, 6
+    grid, opt = orc.Grid(M), orc.Optics()
+    poses = orc.Poses(synth.uniform_rotations(N, seed=75), synth.defocus_values(N, 1.0, 3.0, seed=75))
+    x = synth.random_complex((N, M, M), seed=76).astype(np.complex128)
+    v0 = synth.random_complex(M ** 3, seed=77).astype(np.complex128)
+    st = orc.Alg1State(v=v0.copy(), D=None, D_avg=None, eta=1.0)
+    g = orc.gradient(grid, opt, poses, v0, x, 1.0, 0.1).reshape(-1)
+    h = orc.alg1_iteration(grid, opt, poses, x, st, 1.0, 0.1, 0.0, 0.9, 2.0)
+    assert h == 30 and st.capped == 1
+    assert st.eta == 2.0 ** -30
+    assert np.array_equal(st.v, v0 - 2.0 ** -30 * g)
+    # the next iteration starts from the reduced step (eta is never raised)
+    h = orc.alg1_iteration(grid, opt, poses, x, st, 1.0, 0.1, 0.0, 0.9, 0.1)
+    assert h == 0 and st.eta == 2.0 ** -30 and st.capped == 1
+
+
+def test_alg1_non_finite_raises(orc):
+    M, N = 8, 6
+    grid, opt = orc.Grid(M), orc.Optics()
+    poses = orc.Poses(synth.uniform_rotations(N, seed=78), synth.defocus_values(N, 1.0, 3.0, seed=78))
+    x = synth.random_complex((N, M, M), seed=79).astype(np.complex128)
+    x[2, M // 2, M // 2 + 1] = np.nan
+    v0 = np.zeros(M ** 3, np.complex128)
+    st = orc.Alg1State(v=v0.copy(), D=None, D_avg=None, eta=1.0)
+    with pytest.raises(FloatingPointError):
+        orc.alg1_iteration(grid, opt, poses, x, st, 1.0, 0.1, 0.0, 0.9, 0.1)
+    assert np.array_equal(st.v, v0)

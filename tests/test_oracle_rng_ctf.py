@@ -108,3 +108,26 @@ def test_ctf_spherical_aberration_only(orc):
         s2 = k2 / (M * M)
         want = math.sin(0.5 * math.pi * 2.7e7 * lam ** 3 * s2 * s2)
         assert orc.ctf(opt, M, 0.0, k2) == pytest.approx(want, abs=1e-12)
+
+
+def test_ctf_against_wave_aberration_in_angles(orc):
+    # The phase written from the classical wave aberration instead of spatial
+    # frequencies: a ray scattered by the angle theta = lambda s has the path
+    # difference W(theta) = Cs theta^4 / 4 - df theta^2 / 2 (df > 0 meaning
+    # underfocus here), and the phase is chi = -(2 pi / lambda) W.  Worked
+    # example at 300 kV (lambda = 0.0196875 A), Cs = 2.7 mm, df = 0, s = 1/4 A^-1:
+    #   theta = 4.9219e-3 rad, W = 6.75e6 A * theta^4 = 3.9612e-3 A,
+    #   chi = -1.26420 rad, C = -(sqrt(0.99) sin chi + 0.1 cos chi) = 0.91840.
+    # A wrong power of lambda or of s, or a wrong factor on the Cs term, moves
+    # these values by far more than the tolerances.
+    opt = orc.Optics()
+    lam = orc.wavelength_A(300.0)
+    assert lam == pytest.approx(0.0196875, abs=2e-7)
+    M = 128
+    assert orc.ctf(opt, M, 0.0, (0.25 * M) ** 2) == pytest.approx(0.91840, abs=2e-5)
+    for df, s in ((0.0, 0.25), (0.0, 0.4), (15000.0, 0.25), (15000.0, 0.4), (32000.0, 0.11)):
+        theta = lam * s
+        W = 2.7e7 * theta ** 4 / 4.0 - df * theta ** 2 / 2.0
+        chi = -2.0 * math.pi * W / lam
+        want = -(math.sqrt(1.0 - 0.01) * math.sin(chi) + 0.1 * math.cos(chi))
+        assert orc.ctf(opt, M, df, (s * M) ** 2) == pytest.approx(want, abs=1e-9)
