@@ -12,6 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcryosgd.so")
 OBJDIR = os.path.join(HERE, "_build")
+# throughput probes (measurement support), a library of their own
+MB_LIB = os.path.join(HERE, "libcsg_microbench.so")
+MB_SOURCE = "microbench.hip"
 
 SOURCES = ["api.hip", "pixel_kernels.hip", "brick_kernels.hip", "voxel_kernels.hip", "volume_kernels.hip",
            "mlp_kernels.hip", "timing.hip"]
@@ -54,8 +57,15 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    mb_obj = _compile(MB_SOURCE)
+    tmp = MB_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, mb_obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, MB_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MB_LIB)
     return LIB
 
 

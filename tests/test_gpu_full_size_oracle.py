@@ -1,0 +1,144 @@
+"""The benchmark's launch against the FP64 oracle, element by element: a
+256^3 volume of 1000 blobs and a batch of 1024 images of 256 x 256 (the
+high-resolution workload's poses and defocus), whole batch, in the launch
+configuration the benchmark times (one call over the 1024 images).
+
+Every entry point of the timed step is compared with the oracle on the same
+float32 inputs: the forward projection, the adjoint (fast and
+deterministic), the fused gradient and loss (fast and deterministic), the
+Hessian-vector product (fast and deterministic) and the Hutchinson probe
+product.  Two bounds per output, both written here:
+  relative L2        <= 1e-5 (project) / 1e-4 (adjoint modes)
+  per element  max|got - want| <= 1e-5 / 1e-4 times max|want|
+The oracle's C loops run over chunks of the batch in threads (the ctypes
+calls release the interpreter lock); the chunks' volumes are summed in chunk
+order.  That is only a split of the sum over images of the definitions.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+M, N_IMG, SEED = 256, 1024, 3000
+THREADS = 8
+
+
+def close(got, want, l2, elem, what=""):
+    got = np.asarray(got, dtype=np.complex128).reshape(-1)
+    want = np.asarray(want, dtype=np.complex128).reshape(-1)
+    d = np.abs(got - want)
+    e_l2 = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    e_max = float(d.max() / np.abs(want).max())
+    print("[full] %s: relative L2 %.2e, max element error / max %.2e" % (what, e_l2, e_max))
+    assert e_l2 <= l2 and e_max <= elem, (what, e_l2, e_max)
+
+
+def _chunks(n):
+    step = (n + THREADS - 1) // THREADS
+    return [list(range(s, min(n, s + step))) for s in range(0, n, step)]
+
+
+def o_project(grid, opt, P, vol):
+    parts = _chunks(P.n)
+    with ThreadPoolExecutor(THREADS) as ex:
+        outs = list(ex.map(lambda idx: oracle.project(grid, opt, P.subset(idx), vol), parts))
+    return np.concatenate(outs)
+
+
+def o_backproject(grid, opt, P, img, power, scale):
+    parts = _chunks(P.n)
+    with ThreadPoolExecutor(THREADS) as ex:
+        vols = list(ex.map(lambda idx: oracle.backproject(grid, opt, P.subset(idx), img[idx], ctf_power=power,
+                                                          scale=scale), parts))
+    acc = vols[0]
+    for v in vols[1:]:
+        acc = acc + v
+    return acc
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2311_16100_amd import binding as b
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    b.lib()
+    grid = oracle.Grid(M)
+    P = oracle.Poses(synth.uniform_rotations(N_IMG, SEED), synth.defocus_values(N_IMG, 1.0, 3.0, SEED))
+    vol = synth.blob_volume(M, 1000, SEED)
+    dev = torch.device("cuda:0")
+    rot = torch.from_numpy(P.rot).to(dev)
+    df = torch.from_numpy(P.defocus).to(dev)
+    v = torch.from_numpy(vol).to(dev)
+    ax = np.arange(M) - M // 2
+    disk = (ax[:, None] ** 2 + ax[None, :] ** 2) <= grid.rmax ** 2
+    return b, grid, P, vol, rot, df, v, disk
+
+
+def test_full_batch_project(full):
+    b, grid, P, vol, rot, df, v, disk = full
+    got = b.project(b.Grid(M), b.Optics(), rot, df, v).cpu().numpy()
+    want = o_project(grid, oracle.Optics(), P, vol)
+    close(got, want, 1e-5, 1e-5, "project")
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["fast", "deterministic"])
+def test_full_batch_backproject(full, det):
+    b, grid, P, vol, rot, df, v, disk = full
+    x = synth.random_complex((N_IMG, M, M), 5, stream=13)
+    acc = torch.zeros((M, M, M), dtype=torch.complex64, device="cuda")
+    b.backproject(b.Grid(M), b.Optics(), rot, df, torch.from_numpy(x).cuda(), ctf_power=1, scale=1.0, accum=acc,
+                  deterministic=det)
+    want = o_backproject(grid, oracle.Optics(), P, x, 1, 1.0)
+    close(acc.cpu().numpy(), want, 1e-4, 1e-4, "backproject (%s)" % ("deterministic" if det else "fast"))
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["fast", "deterministic"])
+def test_full_batch_gradient_and_loss(full, det):
+    b, grid, P, vol, rot, df, v, disk = full
+    # data near the model's images (the regime of the iterations): the
+    # oracle's projections of a second blob volume plus noise
+    x = (o_project(grid, oracle.Optics(), P, synth.blob_volume(M, 1000, SEED + 1))
+         + 30.0 * synth.random_complex((N_IMG, M, M), 7, stream=14)) * disk[None]
+    x = x.astype(np.complex64)
+    scale, lam = 195.3, 0.05
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr = b.gradient(b.Grid(M), b.Optics(), rot, df, v, torch.from_numpy(x).cuda(), scale, lam, loss_out=loss,
+                    deterministic=det)
+    r = o_project(grid, oracle.Optics(), P, vol) - x.astype(np.complex128)
+    want = o_backproject(grid, oracle.Optics(), P, r, 1, scale) + lam * vol.astype(np.complex128)
+    close(gr.cpu().numpy(), want, 1e-4, 1e-4, "gradient (%s)" % ("deterministic" if det else "fast"))
+    vv = vol.astype(np.complex128)
+    want_f = scale * 0.5 * np.vdot(r, r).real + 0.5 * lam * np.vdot(vv, vv).real
+    assert loss.item() == pytest.approx(want_f, rel=1e-5)
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["fast", "deterministic"])
+def test_full_batch_hvp(full, det):
+    b, grid, P, vol, rot, df, v, disk = full
+    z = synth.random_complex((M, M, M), 9, stream=16)
+    scale, lam = 195.3, 0.05
+    hz = b.hvp(b.Grid(M), b.Optics(), rot, df, torch.from_numpy(z).cuda(), scale, lam, deterministic=det)
+    want = o_backproject(grid, oracle.Optics(), P, o_project(grid, oracle.Optics(), P, z), 1, scale) \
+        + lam * z.astype(np.complex128)
+    close(hz.cpu().numpy(), want, 1e-4, 1e-4, "hvp (%s)" % ("deterministic" if det else "fast"))
+
+
+def test_full_batch_hutchinson(full):
+    """The probe-pair product (packed 32-bit fixed-point accumulator) of the
+    whole batch against the oracle's z (.) H z for the same two Rademacher
+    probes, averaged."""
+    b, grid, P, vol, rot, df, v, disk = full
+    scale, lam, seed, p0 = 195.3, 0.05, 99, 6
+    got = b.hutchinson_diag(b.Grid(M), b.Optics(), rot, df, 2, seed=seed, scale=scale, lam=lam, probe0=p0)
+    want = np.zeros(M ** 3)
+    for p in (p0, p0 + 1):
+        z = oracle.rademacher(seed, p, M ** 3)
+        hz = o_backproject(grid, oracle.Optics(), P, o_project(grid, oracle.Optics(), P, z.reshape(M, M, M)), 1,
+                           scale).reshape(-1) + lam * z
+        want += z * hz.real / 2
+    close(got.cpu().numpy(), want, 1e-4, 1e-4, "hutchinson probe pair")
