@@ -24,7 +24,8 @@
  *  - All work is enqueued on `stream` (a hipStream_t, NULL = the null
  *    stream); calls are asynchronous unless stated.  Nothing is allocated:
  *    scratch memory comes from the caller's `workspace` (size from
- *    csg_workspace_bytes).
+ *    csg_workspace_bytes), or, for csg_gradient_noalloc only, from a static
+ *    device array that the library holds per GPU.
  *  - Return value: CSG_OK, or a negative code; csg_last_error() then holds
  *    a message (per thread).  No C++ exception crosses the ABI.
  */
@@ -140,6 +141,28 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
                  const float *vol, const float *x, float scale, float lambda, float *grad_out,
                  double *loss_out, int32_t deterministic, void *workspace, size_t workspace_bytes,
                  void *stream);
+
+/* Allocation-free form of csg_gradient (deterministic = 0), for callers that
+ * cannot allocate device memory or pass a workspace: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and error codes as csg_gradient with deterministic = 0,
+ * without the workspace.  The call allocates nothing (no hipMalloc, hipFree,
+ * events or library allocations); its scratch (device scalars and the
+ * per-brick image tables) is a static device array of
+ * CSG_STATIC_SCRATCH_BYTES bytes per GPU, which the library holds from its
+ * first use on that GPU until the process ends.  The array of the CURRENT
+ * device is used, so `stream` must belong to the current device.  Batches
+ * whose brick tables exceed the array are processed in sub-batches (as many
+ * images per launch as fit; at most 2048 as in csg_gradient); a grid too
+ * large for the tables of one image returns CSG_EWORKSPACE.
+ * Every call on one GPU shares that GPU's array and every call overwrites
+ * it: calls that overlap in time on one GPU (different streams, or threads
+ * without ordering) race and give wrong results.  Calls in order on one
+ * stream are safe. */
+#define CSG_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int csg_gradient_noalloc(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                         const float *vol, const float *x, float scale, float lambda, float *grad_out,
+                         double *loss_out, void *stream);
 
 /* Hessian-vector product of the same objective (eq. (hessian)); H is real and
  * independent of v, so a complex z carries two real products:

@@ -52,6 +52,8 @@ EXPORTS = {
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "csg_gradient": [ctypes.c_void_p] * 5 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "csg_gradient_noalloc": [ctypes.c_void_p] * 5 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                                     ctypes.c_void_p, ctypes.c_void_p],
     "csg_hvp": [ctypes.c_void_p] * 4 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "csg_rademacher": [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
@@ -247,6 +249,22 @@ def gradient(grid: Grid, optics: Optics, rot, defocus, vol, x, scale: float, lam
                               _cplx(grad_out, (M, M, M), "grad_out"),
                               None if loss_out is None else _ptr(loss_out), int(bool(deterministic)), wp, wn,
                               _stream(stream)), "csg_gradient")
+    return grad_out
+
+
+def gradient_noalloc(grid: Grid, optics: Optics, rot, defocus, vol, x, scale: float, lam: float, grad_out,
+                     loss_out=None, stream=None, shift=None):
+    """csg_gradient (fast mode) with the library's static per-GPU scratch
+    instead of a workspace; grad_out (and loss_out, if wanted) are passed in,
+    so nothing is allocated on either side of the call."""
+    M = grid.M
+    p = _poses(rot, defocus, shift)
+    g, o = grid.c(), optics.c()
+    _check(lib().csg_gradient_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), _cplx(vol, (M, M, M), "vol"),
+                                      _cplx(x, (p.n, M, M), "x"), float(scale), float(lam),
+                                      _cplx(grad_out, (M, M, M), "grad_out"),
+                                      None if loss_out is None else _ptr(loss_out), _stream(stream)),
+           "csg_gradient_noalloc")
     return grad_out
 
 

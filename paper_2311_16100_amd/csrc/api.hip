@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/cryosgd.h"
@@ -234,6 +235,94 @@ int csg_gradient(const csg_grid *grid, const csg_optics *optics, const csg_poses
         }
     }
     if (loss_out) CSG_TRY(csg::launch_finish_loss(loss_out, sc, sc + 1, scale, lambda, st), "csg_gradient");
+    return CSG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free gradient: the scratch of csg_gradient (device scalars and
+// the brick tables) in a static device array, one per GPU, held until the
+// process ends.  Host code uses the array only through the device address
+// that hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticScratchBytes = CSG_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up on the first call
+// on that device.
+int static_scratch(void **out) {
+    int dev = -1;
+    CSG_TRY(hipGetDevice(&dev), "csg_gradient_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(CSG_EINVAL, "csg_gradient_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        CSG_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "csg_gradient_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255u) != 0)
+            return fail(CSG_EHIP, "csg_gradient_noalloc: scratch address %p is not 256-byte aligned", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csg_gradient_noalloc(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *vol,
+                         const float *x, float scale, float lambda, float *grad_out, double *loss_out, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (!vol || !grad_out || (poses->n > 0 && !x))
+        return fail(CSG_EINVAL, "csg_gradient_noalloc: vol, x and grad_out must be non-NULL");
+    if (vol == grad_out) return fail(CSG_EINVAL, "csg_gradient_noalloc: grad_out must not alias vol");
+    // images per launch: all of them, or the most whose brick tables fit (the
+    // table size grows with the images per launch)
+    int64_t sub = poses->n < csg::kBrickSubBatch ? poses->n : csg::kBrickSubBatch;
+    if (sub < 1) sub = 1;
+    if (g.interp != 0) {
+        auto fits = [&](int64_t s) { return kScalarBytes + csg::brick_workspace_bytes_sub(g.M, s) <= kStaticScratchBytes; };
+        if (!fits(sub)) {
+            int64_t lo = 0, hi = sub;  // fits(lo) or lo == 0; !fits(hi)
+            while (hi - lo > 1) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (fits(mid)) lo = mid;
+                else hi = mid;
+            }
+            sub = lo;
+        }
+        if (sub < 1)
+            return fail(CSG_EWORKSPACE,
+                        "csg_gradient_noalloc: grid M=%d needs %zu bytes of scratch for one image per launch; the "
+                        "static scratch holds %zu",
+                        g.M, kScalarBytes + csg::brick_workspace_bytes_sub(g.M, 1), kStaticScratchBytes);
+    }
+    void *ws = nullptr;
+    if ((rc = static_scratch(&ws))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double *sc = (double *)ws;  // sc[0] = 1/2 sum |r|^2, sc[1] = ||v||^2 (cleared by a kernel)
+    const int64_t nv = nvox_of(g);
+    CSG_TRY(csg::launch_fill_f64(sc, 2, 0.0, st), "csg_gradient_noalloc");
+    CSG_TRY(csg::launch_scaled_copy((float2 *)grad_out, (const float2 *)vol, lambda, nv, sc + 1, st),
+            "csg_gradient_noalloc");
+    if (poses->n > 0)
+        CSG_TRY(csg::launch_brick_gradient(g, poses->rot, poses->defocus_A, poses->shift_px, poses->n,
+                                           (const float2 *)vol, (const float2 *)x, scale, (float2 *)grad_out, sc,
+                                           (char *)ws + kScalarBytes, st, sub, /*timed=*/false),
+                "csg_gradient_noalloc");
+    if (loss_out) CSG_TRY(csg::launch_finish_loss(loss_out, sc, sc + 1, scale, lambda, st), "csg_gradient_noalloc");
     return CSG_OK;
 }
 

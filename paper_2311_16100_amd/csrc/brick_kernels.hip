@@ -1178,11 +1178,15 @@ static size_t brick_items_cap(int M, int64_t sub) {
     return (size_t)brick_count(M) * (size_t)(per > 0 ? per : 1);
 }
 
-size_t brick_workspace_bytes(int M, int64_t n) {
-    const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
+// (sub = images per launch: the sub-batch the per-brick lists hold)
+size_t brick_workspace_bytes_sub(int M, int64_t sub) {
     const size_t nb = (size_t)brick_count(M);
     return align256(nb * 4) + align256(nb * (size_t)(sub > 0 ? sub : 1) * 4) + align256(brick_items_cap(M, sub) * 8) +
            256;
+}
+
+size_t brick_workspace_bytes(int M, int64_t n) {
+    return brick_workspace_bytes_sub(M, n < kBrickSubBatch ? n : kBrickSubBatch);
 }
 
 // Resident blocks of one brick-kernel mode on the current device (one wave
@@ -1207,11 +1211,13 @@ template <int MODE, bool FX = false>
 static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                  const float2 *src, const float2 *img, float2 *out, float2 *accum, double *loss,
                                  float scale, int ctf_power, void *ws, hipStream_t st, float *accum_real = nullptr,
-                                 const FxBuf *fb = nullptr, const ProbePair *probe = nullptr) {
+                                 const FxBuf *fb = nullptr, const ProbePair *probe = nullptr,
+                                 int64_t sub_cap = kBrickSubBatch, bool timed = true) {
     const int M = g.M;
     const int nbx = (M + BS - 1) / BS;
     const int nb = nbx * nbx * nbx;
-    const int64_t sub = n < kBrickSubBatch ? n : kBrickSubBatch;
+    if (sub_cap < 1 || sub_cap > kBrickSubBatch) sub_cap = kBrickSubBatch;
+    const int64_t sub = n < sub_cap ? n : sub_cap;
     char *w = (char *)ws;
     int *counts = (int *)w;
     w += align256((size_t)nb * 4);
@@ -1224,8 +1230,8 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
     constexpr int chunk = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
     const int64_t max_items = (int64_t)nb * ((sub + chunk - 1) / chunk);
     const int grid = (int)(resident_blocks<MODE, FX>() < max_items ? resident_blocks<MODE, FX>() : max_items);
-    for (int64_t s0 = 0; s0 < n; s0 += kBrickSubBatch) {
-        const int64_t ns = (n - s0) < kBrickSubBatch ? (n - s0) : kBrickSubBatch;
+    for (int64_t s0 = 0; s0 < n; s0 += sub) {
+        const int64_t ns = (n - s0) < sub ? (n - s0) : sub;
         const int stride = (int)ns;
         hipLaunchKernelGGL(brick_cull_kernel, dim3((unsigned)((nb + kCullWaves - 1) / kCullWaves)), dim3(kCullThreads), 0,
                            st, g, rot + s0 * 9, ns, nbx, nb, counts, lists, stride);
@@ -1272,7 +1278,7 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
         }
         // the probe HVP is timed with the HVP
         constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
-        hipEvent_t t0 = timing_begin(TMODE, st);
+        hipEvent_t t0 = timed ? timing_begin(TMODE, st) : nullptr;
         if (shift)
             hipLaunchKernelGGL((brick_kernel<MODE, true, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
         else
@@ -1312,10 +1318,11 @@ hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float
 
 hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                  const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
-                                 void *ws, hipStream_t st) {
+                                 void *ws, hipStream_t st, int64_t sub_cap, bool timed) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_gradient_atomic(g, rot, defocus, shift, n, vol, x, scale, accum, loss, st);
-    return run_brick_mode<kBGradient>(g, rot, defocus, shift, n, vol, x, nullptr, accum, loss, scale, 1, ws, st);
+    return run_brick_mode<kBGradient>(g, rot, defocus, shift, n, vol, x, nullptr, accum, loss, scale, 1, ws, st,
+                                      nullptr, nullptr, nullptr, sub_cap, timed);
 }
 
 hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,

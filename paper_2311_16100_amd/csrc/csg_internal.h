@@ -23,15 +23,20 @@ hipError_t timing_read(int kernel, double *total_ms, int64_t *launches);
 // brick-binned kernels (brick_kernels.hip)
 int brick_count(int M);
 size_t brick_workspace_bytes(int M, int64_t n);
+// the same for launches of at most `sub` images each
+size_t brick_workspace_bytes_sub(int M, int64_t sub);
 hipError_t launch_brick_project(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                 const float2 *vol, const float2 *subtract, float2 *out, double *loss, void *ws,
                                 hipStream_t st);
 hipError_t launch_brick_backproject(const Geom &g, const float *rot, const float *defocus, const float *shift,
                                     int64_t n, const float2 *img, int ctf_power, float scale, float2 *accum,
                                     void *ws, hipStream_t st);
+// sub_cap: images per launch (the brick tables in ws hold that many);
+// timed = false keeps the launches out of the optional kernel timing, which
+// creates events
 hipError_t launch_brick_gradient(const Geom &g, const float *rot, const float *defocus, const float *shift, int64_t n,
                                  const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
-                                 void *ws, hipStream_t st);
+                                 void *ws, hipStream_t st, int64_t sub_cap = kBrickSubBatch, bool timed = true);
 hipError_t launch_brick_feature_sums(const Geom &g, const float *rot, const float *defocus, int64_t n,
                                      float2 *accum, void *ws, hipStream_t st);
 hipError_t launch_brick_sq_diag(const Geom &g, const float *rot, const float *defocus, int64_t n, float scale,

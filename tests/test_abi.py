@@ -113,3 +113,17 @@ def test_timing_arguments_checked(b):
     # nothing recorded: zero launches, and reading needs no device
     assert b.timing_read("gradient") == (0.0, 0)
     b.timing_enable(False)
+
+
+def test_noalloc_gradient_checks_arguments_on_the_host(b):
+    """The allocation-free gradient rejects bad arguments before it looks up
+    its static scratch or enqueues anything."""
+    L = b.lib()
+    g, o = b.Grid(32).c(), b.Optics().c()
+    p = b._Poses(4, None, None)
+    assert L.csg_gradient_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), None, None, 1.0, 0.0, None,
+                                  None, None) == -1
+    bad = b._Grid(33, 10.0, 1)
+    assert L.csg_gradient_noalloc(ctypes.byref(bad), ctypes.byref(o), ctypes.byref(p), None, None, 1.0, 0.0, None,
+                                  None, None) == -1
+    assert b"must be even" in L.csg_last_error()
