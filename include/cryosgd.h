@@ -265,9 +265,13 @@ int csg_mlp_forward(const float *params, const float *X, int64_t n, float *y, vo
 /* Gradient of the mean squared error L = 1/n sum_s (mlp(X[s]) - T[s])^2 with
  * respect to the parameter vector (bfloat16 roundings passed straight
  * through).  grad device float [param_count] and loss_out device double [1]
- * are overwritten. */
+ * are overwritten.  The sums run in a fixed order (per-block partials in the
+ * workspace, added in block order), so equal inputs give bitwise equal
+ * results.  workspace: device, 256-byte aligned, at least
+ * csg_mlp_grad_workspace_bytes(n) bytes (NULL allowed for n = 0). */
+size_t csg_mlp_grad_workspace_bytes(int64_t n);
 int csg_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad,
-                 double *loss_out, void *stream);
+                 double *loss_out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* One Adam step (Kingma & Ba) on params with moment buffers m, v (device
  * float [param_count], zero before step 1); step >= 1 counts the updates. */

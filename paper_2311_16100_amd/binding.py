@@ -71,7 +71,8 @@ EXPORTS = {
     "csg_mlp_param_count": [],
     "csg_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "csg_mlp_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                     ctypes.c_void_p, ctypes.c_void_p],
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "csg_mlp_grad_workspace_bytes": [ctypes.c_int64],
     "csg_mlp_adam": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                      ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_void_p],
     "csg_learned_diag": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
@@ -98,6 +99,7 @@ def lib() -> ctypes.CDLL:
             f.argtypes = args
             f.restype = ctypes.c_int
         L.csg_workspace_bytes.restype = ctypes.c_size_t
+        L.csg_mlp_grad_workspace_bytes.restype = ctypes.c_size_t
         L.csg_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -402,15 +404,24 @@ def mlp_forward(params, X, y=None, stream=None):
     return y
 
 
-def mlp_grad(params, X, T, grad=None, loss=None, stream=None):
-    """Gradient (and value) of the mean squared error of mlp(X) against T."""
+def mlp_grad_workspace(n: int, device=None) -> torch.Tensor | None:
+    nb = int(lib().csg_mlp_grad_workspace_bytes(int(n)))
+    return None if nb == 0 else torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
+
+
+def mlp_grad(params, X, T, grad=None, loss=None, workspace=None, stream=None):
+    """Gradient (and value) of the mean squared error of mlp(X) against T
+    (bitwise reproducible: fixed-order sums)."""
     n = X.shape[0]
     if grad is None:
         grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=X.device)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    if workspace is None:
+        workspace = mlp_grad_workspace(n, X.device)
+    wp, wn = _ws(workspace)
     _check(lib().csg_mlp_grad(_f32(params, "params", mlp_param_count()), _f32(X, "X", 3 * n), _f32(T, "T", n),
-                              int(n), _f32(grad, "grad", mlp_param_count()), _ptr(loss), _stream(stream)),
+                              int(n), _f32(grad, "grad", mlp_param_count()), _ptr(loss), wp, wn, _stream(stream)),
            "csg_mlp_grad")
     return grad, loss
 

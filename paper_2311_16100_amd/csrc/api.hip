@@ -525,12 +525,17 @@ int csg_mlp_forward(const float *params, const float *X, int64_t n, float *y, vo
     return CSG_OK;
 }
 
+size_t csg_mlp_grad_workspace_bytes(int64_t n) { return n < 0 ? 0 : csg::mlp_grad_workspace_bytes(n); }
+
 int csg_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad, double *loss_out,
-                 void *stream) {
+                 void *workspace, size_t workspace_bytes, void *stream) {
     if (n < 0) return fail(CSG_EINVAL, "csg_mlp_grad: n must be non-negative");
     if (!params || !grad || !loss_out || (n > 0 && (!X || !T)))
         return fail(CSG_EINVAL, "csg_mlp_grad: params, X, T, grad and loss_out must be non-NULL");
-    CSG_TRY(csg::launch_mlp_grad(params, X, T, n, grad, loss_out, (hipStream_t)stream), "csg_mlp_grad");
+    int rc;
+    if (n > 0 && (rc = need_workspace(workspace, workspace_bytes, csg::mlp_grad_workspace_bytes(n), "csg_mlp_grad")))
+        return rc;
+    CSG_TRY(csg::launch_mlp_grad(params, X, T, n, grad, loss_out, workspace, (hipStream_t)stream), "csg_mlp_grad");
     return CSG_OK;
 }
 

@@ -123,8 +123,9 @@ int mlp_param_count();
 hipError_t launch_mlp_forward(const float *params, const float *X, float *y, int64_t n, hipStream_t st);
 hipError_t launch_learned_diag(const float *params, int M, float N, float lambda, const float *ctf2,
                                const float *cover, float *D, hipStream_t st);
+size_t mlp_grad_workspace_bytes(int64_t n);
 hipError_t launch_mlp_grad(const float *params, const float *X, const float *T, int64_t n, float *grad,
-                           double *loss, hipStream_t st);
+                           double *loss, void *ws, hipStream_t st);
 hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
                            float beta2, float eps, hipStream_t st);
 

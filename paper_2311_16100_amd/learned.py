@@ -121,9 +121,13 @@ def train(sets, steps: int = 2000, batch: int = 8192, lr: float = 3e-3, seed: in
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     hist = []
+    nb = min(batch, n)
+    ws = B.mlp_grad_workspace(nb, device)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float64, device=device)
     for step in range(1, steps + 1):
-        idx = torch.randint(0, n, (min(batch, n),), generator=gen, device=device)
-        grad, loss = B.mlp_grad(params, X[idx].contiguous(), T[idx].contiguous())
+        idx = torch.randint(0, n, (nb,), generator=gen, device=device)
+        B.mlp_grad(params, X[idx].contiguous(), T[idx].contiguous(), grad=grad, loss=loss, workspace=ws)
         lr_t = lr * (0.5 * (1 + math.cos(math.pi * step / steps)))  # cosine schedule
         B.mlp_adam(params, m, v, grad, step, lr_t)
         if step % 200 == 0 or step == steps:

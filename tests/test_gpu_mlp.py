@@ -109,3 +109,48 @@ def test_learned_diag_fused(B):
     want = np.where(cover.ravel() > 0, lam + N / M * np.exp(y), lam)
     assert rel(D.ravel(), want) <= 1e-2
     assert np.all(D.ravel()[cover.ravel() == 0] == np.float32(lam))
+
+
+def test_learned_diag_skips_unreached_tiles(B):
+    """Voxels no image reaches (here: outside a ball, whole tiles of 32) get
+    lambda without the network; the rest still matches the oracle network."""
+    M, N, lam = 64, 400, 0.7
+    rng = np.random.default_rng(12)
+    ax = np.arange(M) - M // 2
+    r = np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2)
+    ctf2 = rng.uniform(0.5, 5.0, (M, M, M)).astype(np.float32)
+    cover = np.where(r <= 20, rng.integers(1, 30, (M, M, M)), 0).astype(np.float32)
+    p = params(13, 0.1)
+    D = B.learned_diag(B.Grid(M), N, lam, torch.from_numpy(p).cuda(), torch.from_numpy(ctf2).cuda(),
+                       torch.from_numpy(cover).cuda()).cpu().numpy().ravel()
+    X = np.stack([(r / (M // 2)).ravel(), np.log(np.maximum(ctf2.ravel() * M / N, 1e-30)),
+                  np.log(np.maximum(cover.ravel() * M / N, 1e-30))], axis=1).astype(np.float32)
+    inside = cover.ravel() > 0
+    want = lam + N / M * np.exp(oracle.mlp_forward(p, X[inside]))
+    assert rel(D[inside], want) <= 1e-2
+    assert np.all(D[~inside] == np.float32(lam))
+
+
+def test_gradient_is_bitwise_reproducible(B):
+    """Fixed-order sums: equal inputs give equal bits (many blocks)."""
+    n = 20000
+    p = torch.from_numpy(params(14)).cuda()
+    X = torch.from_numpy(np.random.default_rng(15).standard_normal((n, 3)).astype(np.float32)).cuda()
+    T = torch.from_numpy(np.random.default_rng(16).standard_normal(n).astype(np.float32)).cuda()
+    g1, L1 = B.mlp_grad(p, X, T)
+    g1, L1 = g1.clone(), L1.clone()
+    for _ in range(3):
+        g2, L2 = B.mlp_grad(p, X, T)
+        assert torch.equal(g1, g2) and torch.equal(L1, L2)
+
+
+def test_training_is_reproducible(B):
+    """Two trainings from the same seed give bitwise equal parameters."""
+    from paper_2311_16100_amd import learned as L
+    rng = np.random.default_rng(17)
+    X = torch.from_numpy(rng.uniform(-1, 1, (6000, 3)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal(6000).astype(np.float32)).cuda()
+    sets = [L.TrainingSet(X, T)]
+    p1, h1 = L.train(sets, steps=60, batch=2048, seed=3)
+    p2, h2 = L.train(sets, steps=60, batch=2048, seed=3)
+    assert torch.equal(p1, p2) and h1 == h2
