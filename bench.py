@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--M", type=int, default=256)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-images", type=int, default=48, help="images in the oracle's timed sample")
+    ap.add_argument("--cpu-images", type=int, default=192, help="images in the oracle's timed sample")
     ap.add_argument("--deterministic", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-2 comparison of the SGD arms")
     return ap.parse_args()
@@ -234,7 +234,10 @@ def main():
         from paper_2311_16100_amd import tta as TTA
         log = lambda m: print(m, file=sys.stderr, flush=True)
         params, _ = TTA.train_network(log=log)
-        tta = TTA.evaluate(params, log=log)
+        # the precomputed arm: the paper's 1000 epochs at 128^3; 100 epochs at
+        # 256^3 (20 000 iterations) to keep the run within minutes
+        tta = TTA.evaluate(params, configs=("mid_128", "hires_256", "mid_128_snr005"), log=log,
+                           precomputed_epochs={"mid_128": 1000, "hires_256": 100, "mid_128_snr005": 1000})
 
     out = {
         "metric": METRIC,

@@ -214,7 +214,11 @@ int csg_exact_diag(const csg_grid *grid, const csg_optics *optics, const csg_pos
  *   v, g, v_out device complex [nvox] (v_out may alias v only if g does not)
  *   D, D_avg device float [nvox] updated in place (D_avg may be NULL when
  *            zHz is NULL); Dhat_out device float [nvox] or NULL
- *   stats_out device double [2], overwritten. */
+ *   stats_out device double [2], overwritten.
+ * With v, g, v_out and stats_out all NULL (and D, D_avg, zHz given) only the
+ * diagonal estimate is updated (eq. (diag est rule) with the running mean
+ * of Algorithm 1) and D_hat written if asked for: the precomputation of a
+ * preconditioner over many epochs before SGD starts (Sec. 4.1). */
 int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D, float *D_avg,
                          const float *zHz, int64_t k, float beta, float alpha, float eta,
                          float *v_out, float *Dhat_out, double *stats_out, void *stream);

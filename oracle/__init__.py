@@ -308,6 +308,24 @@ def precond_update(D, D_avg, zHz, k: int, beta: float, alpha: float):
     return D, D_avg, D_hat
 
 
+def precomputed_diagonal(grid, optics, poses, batches, scale: float, lam: float, beta: float, n_probe: int,
+                         probe_seed: int):
+    """The precomputed preconditioner of Sec. 4.1 (SGD's second arm): the
+    diagonal estimate of eq. (diag est rule), read with Algorithm 1's running
+    mean, run over the given minibatches (index arrays, in order: many epochs
+    of batches) before SGD starts, from D = 1, D_avg = 0.  Iteration k's
+    sample is Hutchinson's estimate on its minibatch with the probes
+    (k-1) n_probe .. k n_probe - 1.  Returns (D, D_avg), unthresholded."""
+    M = grid.M
+    D = np.ones(M ** 3)
+    D_avg = np.zeros(M ** 3)
+    for k, idx in enumerate(batches, start=1):
+        zHz = hutchinson_diag(grid, optics, poses.subset(list(idx)), n_probe, probe_seed, scale, lam,
+                              probe0=(k - 1) * n_probe).reshape(-1)
+        D, D_avg, _ = precond_update(D, D_avg, zHz, k, beta, 0.0)
+    return D, D_avg
+
+
 def precond_step(v, g, D_hat, eta: float):
     """v - eta D_hat^{-1} g (eq. (sgd step)) and ||g||^2_{D_hat^{-1}}."""
     v = _c128(v).reshape(-1)

@@ -379,6 +379,16 @@ def precond_sgd_step(v, g, D, D_avg, zHz, k: int, beta: float, alpha: float, eta
     return v_out, stats_out
 
 
+def diag_update(D, D_avg, zHz, k: int, beta: float, alpha: float = 0.0, Dhat_out=None, stream=None):
+    """The diagonal estimate's update alone (csg_precond_sgd_step with no
+    step): D_avg = (k-1)/k D_avg + zHz/k, D = beta D + (1-beta) D_avg, and
+    D_hat = max(|D|, alpha) into Dhat_out if given."""
+    _check(lib().csg_precond_sgd_step(int(D.numel()), None, None, _ptr(D), _ptr(D_avg), _ptr(zHz), int(k),
+                                      float(beta), float(alpha), 0.0, None, _ptr(Dhat_out), None, _stream(stream)),
+           "csg_precond_sgd_step")
+    return D
+
+
 # ---------------------------------------------------------------------------
 # Learned preconditioner network
 # ---------------------------------------------------------------------------

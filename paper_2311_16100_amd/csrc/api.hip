@@ -502,11 +502,14 @@ int csg_precond_sgd_step(int64_t nvox, const float *v, const float *g, float *D,
                          int64_t k, float beta, float alpha, float eta, float *v_out, float *Dhat_out,
                          double *stats_out, void *stream) {
     if (nvox < 0) return fail(CSG_EINVAL, "csg_precond_sgd_step: nvox must be non-negative");
-    if (!v || !g || !v_out || !stats_out)
+    const bool d_only = !v && !g && !v_out && !stats_out;
+    if (d_only && !(D && zHz))
+        return fail(CSG_EINVAL, "csg_precond_sgd_step: the diagonal update alone needs D, D_avg and zHz");
+    if (!d_only && (!v || !g || !v_out || !stats_out))
         return fail(CSG_EINVAL, "csg_precond_sgd_step: v, g, v_out and stats_out must be non-NULL");
     if (zHz && (!D || !D_avg)) return fail(CSG_EINVAL, "csg_precond_sgd_step: a probe sample needs D and D_avg");
     if (zHz && k < 1) return fail(CSG_EINVAL, "csg_precond_sgd_step: iteration k=%lld must be >= 1", (long long)k);
-    if (v_out == g) return fail(CSG_EINVAL, "csg_precond_sgd_step: v_out must not alias g");
+    if (!d_only && v_out == g) return fail(CSG_EINVAL, "csg_precond_sgd_step: v_out must not alias g");
     if (!(eta >= 0.0f)) return fail(CSG_EINVAL, "csg_precond_sgd_step: eta must be non-negative");
     if (D && !(alpha >= 0.0f)) return fail(CSG_EINVAL, "csg_precond_sgd_step: alpha must be non-negative");
     CSG_TRY(csg::launch_precond_step(nvox, (const float2 *)v, (const float2 *)g, D, D_avg, zHz, k, beta, alpha, eta,

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void precond_step_kernel(int64_t nvox, cons
             dh = fmaxf(fabsf(d), alpha);
         }
         if (Dhat_out) Dhat_out[k] = dh;
+        if (!v_out) continue;  // the diagonal update alone
         const float2 gk = g[k], vk = v[k];
         const float inv = 1.0f / dh;
         const float2 o = make_float2(vk.x - eta * gk.x * inv, vk.y - eta * gk.y * inv);
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(kBlock) void precond_step_kernel(int64_t nvox, cons
         s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh;
         s1 += (double)o.x * o.x + (double)o.y * o.y;
     }
+    if (!v_out) return;
     const double t0 = block_sum(s0, red);
     const double t1 = block_sum(s1, red);
     if (threadIdx.x == 0) {
@@ -274,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void precond_step2_kernel(int64_t npair, co
             dh = make_float2(fmaxf(fabsf(d.x), alpha), fmaxf(fabsf(d.y), alpha));
         }
         if (Dhat_out) Dhat_out[k] = dh;
+        if (!v_out) continue;  // the diagonal update alone
         const float4 gk = g[k], vk = v[k];
         const float i0 = 1.0f / dh.x, i1 = 1.0f / dh.y;
         const float4 o = make_float4(vk.x - eta * gk.x * i0, vk.y - eta * gk.y * i0, vk.z - eta * gk.z * i1,
@@ -283,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void precond_step2_kernel(int64_t npair, co
               ((double)gk.z * gk.z + (double)gk.w * gk.w) / (double)dh.y;
         s1 += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
     }
+    if (!v_out) return;
     const double t0 = block_sum(s0, red);
     const double t1 = block_sum(s1, red);
     if (threadIdx.x == 0) {
@@ -441,8 +445,10 @@ hipError_t launch_precond_step(int64_t nvox, const float2 *v, const float2 *g, f
                                float *Dhat_out, double *stats, hipStream_t st) {
     const float wk_old = k > 0 ? (float)((double)(k - 1) / (double)k) : 0.f;
     const float wk_new = k > 0 ? (float)(1.0 / (double)k) : 0.f;
-    hipError_t e = launch_fill_f64(stats, 2, 0.0, st);
-    if (e != hipSuccess) return e;
+    if (stats) {
+        hipError_t e = launch_fill_f64(stats, 2, 0.0, st);
+        if (e != hipSuccess) return e;
+    }
     if (nvox % 2 == 0 && aligned(v, 16) && aligned(g, 16) && aligned(v_out, 16) && aligned(D, 8) &&
         aligned(D_avg, 8) && aligned(zHz, 8) && aligned(Dhat_out, 8)) {
         const int64_t np = nvox / 2;

@@ -17,8 +17,12 @@ Arms (all share Algorithm 1's loop, the Armijo rule and the step schedule):
   plain        D_hat = 1
   hutchinson   D estimated on the fly (Algorithm 1)
   learned      D_hat = max(D_pred, alpha) from the preconditioner network
+  precomputed  D_hat = max(|D|, alpha), D from eq. (diag est rule) run over
+               many epochs before SGD starts (Sec. 4.1: 1000 epochs, batch
+               1000), then held fixed
   exact        D_hat = max(diag H, alpha), diag H from one squared-weight
-               backprojection (the "precomputed" arm of Sec. 4)
+               backprojection: the exact diagonal, the limit the precomputed
+               estimate approaches
 """
 from __future__ import annotations
 
@@ -156,6 +160,40 @@ def exact_diagonal(ds: Dataset, scale: float = 1.0) -> torch.Tensor:
     return d + ds.lam
 
 
+def precomputed_diagonal(grid: B.Grid, optics: B.Optics, rot: torch.Tensor, defocus: torch.Tensor, lam: float,
+                         epochs: int, batch: int, n_probe: int = 2, probe_seed: int = 0, perm_seed: int = 0,
+                         beta: float = 0.9, progress=None):
+    """The precomputed preconditioner of Sec. 4.1: the diagonal estimate of
+    eq. (diag est rule), with Algorithm 1's running mean, run for `epochs`
+    epochs of minibatches of `batch` images (a permutation per epoch) before
+    SGD starts, from D = 1, D_avg = 0; iteration k's sample is the Hutchinson
+    product of its minibatch with the probes (k-1) n_probe .. k n_probe - 1.
+    Every step runs in the library (csg_hutchinson_diag, then the diagonal
+    update of csg_precond_sgd_step).  Returns (D, D_avg, iterations)."""
+    dev = rot.device
+    N = rot.shape[0]
+    M = grid.M
+    scale = N / batch
+    D = torch.ones((M, M, M), dtype=torch.float32, device=dev)
+    D_avg = torch.zeros_like(D)
+    zHz = torch.empty_like(D)
+    ws = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev)
+    k = 0
+    t_log = time.perf_counter()
+    for epoch in range(epochs):
+        perm = torch.from_numpy(synth.epoch_permutation(N, perm_seed, epoch)).to(dev)
+        for s in range(0, N - batch + 1, batch):
+            idx = perm[s:s + batch]
+            k += 1
+            B.hutchinson_diag(grid, optics, rot[idx].contiguous(), defocus[idx].contiguous(), n_probe, probe_seed,
+                              scale, lam, probe0=(k - 1) * n_probe, diag_out=zHz, workspace=ws)
+            B.diag_update(D, D_avg, zHz, k, beta)
+        if progress and time.perf_counter() - t_log > 30.0:
+            t_log = time.perf_counter()
+            progress("  precomputed diagonal: epoch %d of %d" % (epoch + 1, epochs))
+    return D, D_avg, k
+
+
 def ground_truth(ds: Dataset, tol: float = 1e-6, max_iter: int = 500, log=None):
     """v* = H^{-1} b by Jacobi-preconditioned CG (double-precision dots).
     Returns (v*, iterations, true relative residual ||b - H v*|| / ||b||).
@@ -208,6 +246,7 @@ class RunResult:
     halvings: int = 0
     capped: int = 0
     gen_seconds: float = 0.0  # regeneration of streamed images (not in `seconds`)
+    eval_seconds: float = 0.0  # error evaluations (not in `seconds`)
     fsc: list = field(default_factory=list)  # (iteration, FSC per shell vs v*) at epoch ends and at the stop
     note: str = ""
 
@@ -224,23 +263,32 @@ def high_band_mask(M: int, r_max: float, device) -> torch.Tensor:
 
 
 def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
-            eval_every: int = 5, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
+            eval_every: int = 1, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
             seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball",
-            deterministic: bool = False, progress=None, queue_probes: bool = True) -> RunResult:
+            deterministic: bool = False, progress=None, queue_probes: bool = True,
+            average_from_epoch: int | None = None, fsc_every: int = 0) -> RunResult:
     """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
-    the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target.
-    `decay_epochs` > 0 halves the step-size cap every that many epochs
-    (identically in every arm).  Wall time counts iterations and error
-    evaluations; for a streamed data set the regeneration of each batch's
-    images is timed apart (`gen_seconds`) and not counted.
+    the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target,
+    evaluated every `eval_every` iterations.
+    `decay_epochs` > 0 halves the step-size cap every that many epochs, and
+    `average_from_epoch` (not None) keeps from that epoch on the running
+    (Polyak-Ruppert) average of the iterates, whose error is then the one
+    reported and tested; both identically in every arm (a schedule for noisy
+    data; Algorithm 1 itself has neither).  Wall time counts the iterations
+    (and the averaging); the error evaluations are timed apart (`eval_seconds`)
+    and not counted, and for a streamed data set neither is the regeneration
+    of each batch's images (`gen_seconds`).
     `deterministic` selects the bitwise-reproducible adjoint.  With
     `queue_probes` the runner is told the next batch's poses (the Hutchinson
-    arm then computes its next probe product during the line search)."""
+    arm then computes its next probe product during the line search).
+    The shell correlation with v* is recorded after every epoch, at the stop,
+    and every `fsc_every` iterations if that is > 0 (outside the timing)."""
     dev = ds.device
     scale = ds.N / batch
     alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
     cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17, deterministic=deterministic)
-    kind = {"plain": "plain", "hutchinson": "hutchinson", "learned": "fixed", "exact": "fixed"}[arm]
+    kind = {"plain": "plain", "hutchinson": "hutchinson", "learned": "fixed", "exact": "fixed",
+            "precomputed": "fixed"}[arm]
     v0 = torch.zeros_like(v_star)
     run = Alg1Runner(ds.grid, ds.optics, kind, scale, ds.lam, alpha, cfg, v0, D_fixed=D_fixed, batch=batch)
     ball = ball_mask(ds.M, ds.grid.rmax, dev)
@@ -251,6 +299,21 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     t_log = t0
     it = 0
     eta_cap = eta0
+    v_avg = None  # Polyak-Ruppert average of the iterates
+    n_avg = 0
+
+    def evaluate(now):
+        """Record the error (of the average, when averaging) at `now`; the
+        evaluation's own time is added to res.eval_seconds."""
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        el = now - t0 - res.gen_seconds - res.eval_seconds
+        v_eval = v_avg if v_avg is not None else run.state.v
+        eb = rel_error(v_eval, v_star, ball)
+        eh = rel_error(v_eval, v_star, high)
+        res.errors.append((it, el, eb, eh))
+        res.eval_seconds += time.perf_counter() - te
+        return el, (eb if stop_on == "ball" else eh), v_eval
 
     def poses_of(idx):
         return ds.rot[idx].contiguous(), ds.defocus[idx].contiguous()
@@ -291,46 +354,81 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
             cur = nxt
             del xb
             it += 1
+            if average_from_epoch is not None and epoch >= average_from_epoch:
+                n_avg += 1
+                if v_avg is None:
+                    v_avg = run.state.v.clone()
+                else:
+                    v_avg.lerp_(run.state.v, 1.0 / n_avg)
             if progress and time.perf_counter() - t_log > 30.0:
                 t_log = time.perf_counter()
-                progress("  %s: iteration %d, %.1f s" % (arm, it, t_log - t0 - res.gen_seconds))
+                progress("  %s: iteration %d, %.1f s" % (arm, it, t_log - t0 - res.gen_seconds - res.eval_seconds))
+            if fsc_every and it % fsc_every == 0:
+                tf = time.perf_counter()
+                res.fsc.append((it, B.fsc(ds.grid, v_avg if v_avg is not None else run.state.v,
+                                          v_star).cpu().tolist()))
+                t0 += time.perf_counter() - tf
             if it % eval_every == 0:
-                eb = rel_error(run.state.v, v_star, ball)
-                eh = rel_error(run.state.v, v_star, high)
-                el = time.perf_counter() - t0 - res.gen_seconds
-                res.errors.append((it, el, eb, eh))
-                if (eb if stop_on == "ball" else eh) <= target:
+                el, e_stop, v_eval = evaluate(time.perf_counter())
+                if e_stop <= target:
                     res.reached, res.iterations, res.seconds = True, it, el
                     res.capped = run.state.capped
-                    res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
+                    res.fsc.append((it, B.fsc(ds.grid, v_eval, v_star).cpu().tolist()))
                     return res
                 if el > time_limit:
                     res.iterations, res.seconds, res.note = it, el, "time limit"
                     res.capped = run.state.capped
-                    res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
+                    res.fsc.append((it, B.fsc(ds.grid, v_eval, v_star).cpu().tolist()))
                     return res
         # shell correlation with v* after each epoch (Sec. 4.1), outside the timed region
-        tf = time.perf_counter()
-        res.fsc.append((it, B.fsc(ds.grid, run.state.v, v_star).cpu().tolist()))
-        t0 += time.perf_counter() - tf
-    res.iterations, res.seconds, res.note = it, time.perf_counter() - t0 - res.gen_seconds, "epoch limit"
+        if not (res.fsc and res.fsc[-1][0] == it):
+            tf = time.perf_counter()
+            res.fsc.append((it, B.fsc(ds.grid, v_avg if v_avg is not None else run.state.v,
+                                      v_star).cpu().tolist()))
+            t0 += time.perf_counter() - tf
+    res.iterations, res.note = it, "epoch limit"
+    res.seconds = time.perf_counter() - t0 - res.gen_seconds - res.eval_seconds
     res.capped = run.state.capped
+    if not res.errors or res.errors[-1][0] != it:
+        evaluate(time.perf_counter())
     return res
 
 
-def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinson", "learned", "exact"),
+def compare_diagonals(D_est: torch.Tensor, D_ref: torch.Tensor, ds: Dataset) -> dict:
+    """How far an estimated diagonal is from a reference one: relative L2
+    over the ball, and the relative error of the Fourier-shell means (largest
+    over the shells and count-weighted)."""
+    from . import learned as L
+    a, n = L.shell_stats(D_est, ds.M)
+    b, _ = L.shell_stats(D_ref, ds.M)
+    shell_rel = torch.abs(a - b) / torch.abs(b)
+    return {"ball_rel_l2": round(L.diag_rel_error(D_est, D_ref, ds), 6),
+            "shell_mean_rel_max": round(float(shell_rel.max().item()), 6),
+            "shell_mean_rel_weighted": round(float((torch.sqrt(torch.sum(n * (a - b) ** 2))
+                                                     / torch.sqrt(torch.sum(n * b * b))).item()), 6)}
+
+
+def compare_arms(ds: Dataset, batch: int, params=None,
+                 arms=("plain", "hutchinson", "learned", "precomputed", "exact"),
                  target: float = 1e-2, stop_on: str = "ball", judge_threshold: float = 0.2, log=print,
                  feature_images: int = 8192, judge_images: int = 4096, cg_tol: float = 1e-6, cg_max_iter: int = 500,
-                 **kw):
+                 precomputed_epochs: int = 1000, precomputed_batch: int = 1000, v_star=None, cache=None, **kw):
     """Time to `target` for each arm on the same data set and ground truth.
     Setup time is charged to the arm that needs it: the exact arm one
-    squared-weight pass over the data; the learned arm the feature pass (over
-    `feature_images` random images), the network and the judge (one complex
-    probe over `judge_images` images); if the judge rejects the prediction the
-    arm continues as the Hutchinson arm."""
+    squared-weight pass over the data; the precomputed arm its
+    `precomputed_epochs` epochs of eq. (diag est rule) at batch
+    `precomputed_batch` (reported, as in the paper, as a precomputation); the
+    learned arm the feature pass (over `feature_images` random images), the
+    network and the judge (one complex probe over `judge_images` images); if
+    the judge rejects the prediction the arm continues as the Hutchinson arm.
+    The precomputed and learned diagonals are also compared with the exact
+    one.  `v_star` = (v*, CG iterations, residual) reuses a ground truth;
+    `cache` (a dict) keeps the precomputed diagonal and its setup time for
+    later calls on the same data set."""
     from . import learned as L
-    v_star, cg_it, cg_res = ground_truth(ds, tol=cg_tol, max_iter=cg_max_iter,
-                                         log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
+    if v_star is None:
+        v_star = ground_truth(ds, tol=cg_tol, max_iter=cg_max_iter, log=log if ds.N * ds.M ** 2 > 10 ** 10 else None)
+    v_star, cg_it, cg_res = v_star
     # one untimed pass through every setup kernel on a few images, so that no
     # arm is charged for first-launch costs
     few = min(ds.N, 64)
@@ -339,7 +437,8 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
         c2, cv = L.features(ds, n_images=few)
         L.judge(ds, L.predict(ds, params, c2, cv), n_images=few)
     torch.cuda.synchronize()
-    out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}}
+    out = {"cg_iterations": cg_it, "cg_residual": cg_res, "arms": {}, "diagonals": {}}
+    D_exact = None
     for arm in arms:
         D = None
         setup = 0.0
@@ -349,6 +448,15 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
         t0 = time.perf_counter()
         if arm == "exact":
             D = exact_diagonal(ds)
+        elif arm == "precomputed":
+            if cache is not None and "precomputed" in cache:
+                D, setup, note = cache["precomputed"]
+            else:
+                D, _, n_it = precomputed_diagonal(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam, precomputed_epochs,
+                                                  min(precomputed_batch, ds.N), probe_seed=ds.seed + 29,
+                                                  perm_seed=ds.seed + 31, progress=log)
+                note = "%d epochs x batch %d (%d iterations)" % (precomputed_epochs, min(precomputed_batch, ds.N),
+                                                                 n_it)
         elif arm == "learned":
             if params is None:
                 continue
@@ -359,7 +467,14 @@ def compare_arms(ds: Dataset, batch: int, params=None, arms=("plain", "hutchinso
             if not math.isfinite(err) or err > judge_threshold:
                 run_as, D, note = "hutchinson", None, note + " -> fallback to hutchinson"
         torch.cuda.synchronize()
-        setup = time.perf_counter() - t0
+        if not (arm == "precomputed" and cache is not None and "precomputed" in cache):
+            setup = time.perf_counter() - t0
+        if arm == "precomputed" and cache is not None:
+            cache["precomputed"] = (D, setup, note)
+        if D is not None and arm in ("precomputed", "learned"):
+            if D_exact is None:
+                D_exact = exact_diagonal(ds)
+            out["diagonals"][arm] = compare_diagonals(D, D_exact, ds)
         r = run_arm(ds, v_star, run_as, batch, target=target, D_fixed=D, setup_seconds=setup, stop_on=stop_on,
                     progress=log, **kw)
         r.arm, r.note = arm, (r.note + " " + note).strip()

@@ -172,16 +172,62 @@ def shell_stats(d: torch.Tensor, M: int):
     return sums / cnt, cnt
 
 
-def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 2, n_images: int = 4096, seed: int = 99):
-    """Relative error between the Fourier-shell means of the prediction and
-    of a short Hutchinson estimate (n_probe probes over n_images images,
-    rescaled to the data set), each shell weighted by its voxel count.  Shell
-    means average out the probe noise of a short estimate; the count weights
-    keep the few-voxel central shells from dominating."""
+_SECTORS = {}
+
+
+def sector_index(M: int, device):
+    """Bin of every voxel: Fourier shell round(|k|) (< M/2, else -1) times 6
+    plus the direction sector, the signed axis of the largest |k_d| (ties to
+    the lower axis).  Within a shell the sectors separate directions, which
+    preferred orientations make differ."""
+    key = (M, str(device))
+    if key not in _SECTORS:
+        ax = torch.arange(M, device=device) - M // 2
+        kz, ky, kx = torch.meshgrid(ax, ax, ax, indexing="ij")
+        k = torch.stack([kx, ky, kz]).reshape(3, -1)
+        shell = torch.round(torch.sqrt((k.double() ** 2).sum(0))).long()
+        axis = torch.argmax(torch.abs(k), dim=0)
+        sign = (torch.gather(k, 0, axis[None])[0] < 0).long()
+        idx = shell * 6 + axis * 2 + sign
+        idx[shell >= M // 2] = -1
+        _SECTORS[key] = idx
+    return _SECTORS[key]
+
+
+def sector_stats(d: torch.Tensor, M: int):
+    """(means, voxel counts) over the shell x direction-sector bins of
+    sector_index (empty bins have count 0 and mean 0)."""
+    idx = sector_index(M, d.device)
+    keep = idx >= 0
+    nb = (M // 2) * 6
+    sums = torch.bincount(idx[keep], weights=d.reshape(-1)[keep].double(), minlength=nb)
+    cnt = torch.bincount(idx[keep], minlength=nb).double()
+    return sums / torch.clamp(cnt, min=1.0), cnt
+
+
+def _binned_rel_error(a, b, n):
+    return float((torch.sqrt(torch.sum(n * (a - b) ** 2)) / torch.sqrt(torch.sum(n * b * b))).item())
+
+
+def judge(ds: Dataset, D_pred: torch.Tensor, n_probe: int = 2, n_images: int = 4096, seed: int = 99,
+          detail: bool = False):
+    """Relative error between the prediction and a short Hutchinson estimate
+    (n_probe probes over n_images images, rescaled to the data set), on bin
+    means weighted by their voxel counts, the larger of two binnings: the
+    Fourier shells, and the shells split into six direction sectors (a
+    prediction can match the shell means and still be wrong by direction,
+    as with preferred orientations).  Bin means average out the probe noise
+    of a short estimate; the count weights keep the few-voxel central bins
+    from dominating.  detail=True also returns the two figures."""
     Dh = hutchinson_full(ds, n_probe, seed, n_images=n_images, probe0=1_000_000)
     a, n = shell_stats(D_pred, ds.M)
     b, _ = shell_stats(Dh, ds.M)
-    return float((torch.sqrt(torch.sum(n * (a - b) ** 2)) / torch.sqrt(torch.sum(n * b * b))).item())
+    e_shell = _binned_rel_error(a, b, n)
+    a, n = sector_stats(D_pred, ds.M)
+    b, _ = sector_stats(Dh, ds.M)
+    e_sector = _binned_rel_error(a, b, n)
+    e = max(e_shell, e_sector)
+    return (e, e_shell, e_sector) if detail else e
 
 
 def diag_rel_error(D_a: torch.Tensor, D_b: torch.Tensor, ds: Dataset) -> float:

@@ -53,3 +53,24 @@ def test_kappa_unseen_voxel(C):
     assert r.unseen > 0
     assert r.kappa == pytest.approx((N + lam) / lam, rel=1e-9)
     assert r.bound == pytest.approx((N + lam) / lam, rel=1e-12)
+
+
+def test_z0_slice_matches_oracle(C):
+    """Panels (b, c) of the figure: the kz = 0 plane of the nearest-neighbour
+    Hessian diagonal, against the oracle's counts."""
+    N, M, lam = 5, 24, 1e-8
+    plane, prof = C.z0_slice(N, M=M, lam=lam, seed=11)
+    P = oracle.Poses(synth.uniform_rotations(N, 11), np.zeros(N, np.float32))
+    ref = oracle.exact_diag(oracle.Grid(M, interp=0), oracle.NO_CTF, P, 1.0, lam)
+    assert np.allclose(plane, ref[M // 2], rtol=0, atol=1e-12)
+    assert len(prof) == M // 2 and prof[0]["mean"] == pytest.approx(N + lam)
+
+
+def test_kappa_spread_over_pose_sets(C):
+    # kappa(R) is taken on the full-resolution grid of the largest radius, so
+    # the single-set run uses the same radii
+    rows = C.kappa_vs_radius(N=300, radii=(1, 6, 12), lam=1e-8, seed=21, sets=3)
+    one = C.kappa_vs_radius(N=300, radii=(1, 6, 12), lam=1e-8, seed=21)
+    for r, r1 in zip(rows, one):
+        assert r.sets == 3 and r.kappa_min <= r.kappa_mean <= r.kappa_max
+        assert r.kappa == pytest.approx(r1.kappa) and r1.kappa_mean == pytest.approx(r1.kappa)

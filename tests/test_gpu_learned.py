@@ -101,3 +101,29 @@ def test_learned_arm_gains_iterations(mods, trained, ds64):
     assert all(a.reached for a in r["arms"].values()), it
     assert r["arms"]["learned"].iterations < r["arms"]["plain"].iterations
     assert r["arms"]["learned"].iterations <= r["arms"]["hutchinson"].iterations
+
+
+def test_judge_sees_a_wrong_direction_dependence(mods, trained, ds64):
+    """A prediction with the right shell means but the wrong dependence on
+    direction (the data term doubled on one side of kz = 0 and zeroed on the
+    other) passes the shell comparison and is rejected by the shell x sector
+    comparison."""
+    _, _, L, _ = mods
+    params, _ = trained
+    good = L.predict(ds64, params)
+    M = ds64.M
+    kz = (torch.arange(M, device=good.device) - M // 2)[:, None, None].expand(M, M, M)
+    # voxels whose largest |k_d| is along z, on the two sides of kz = 0:
+    # the data term doubled on one side, zeroed on the other; shell sums of
+    # the two sides are equal by the symmetry of the sets' diagonal
+    idx = L.sector_index(M, good.device).reshape(M, M, M)
+    along_z = ((idx % 6) // 2 == 2)
+    f = torch.ones_like(good)
+    f[along_z & (kz > 0)] = 2.0
+    f[along_z & (kz < 0)] = 0.0
+    warped = ds64.lam + (good - ds64.lam) * f
+    e, e_shell, e_sector = L.judge(ds64, warped, detail=True)
+    e_ok, _, _ = L.judge(ds64, good, detail=True)
+    print("[learned] warped prediction: shell %.4f sector %.4f (correct one %.4f)" % (e_shell, e_sector, e_ok))
+    assert e_ok < 0.2
+    assert e_shell < 0.2 < e_sector and e == e_sector

@@ -635,3 +635,41 @@ def test_fast_adjoint_redoes_items_above_the_guess(b):
     assert rel(gr, gd) <= 1e-5
     assert loss.item() == pytest.approx(oracle.loss(grid_o, opt_o, P, vol * 1e-3, x_np * disk[None], 2.0, 0.1),
                                         rel=1e-5)
+
+
+def test_diagonal_update_alone(b):
+    """csg_precond_sgd_step with no step (v, g, v_out, stats NULL): the
+    running mean, the exponential average and D_hat only."""
+    n = 4097
+    g0 = np.random.default_rng(31)
+    D = g0.uniform(-1, 3, n).astype(np.float32)
+    Da = g0.uniform(0, 2, n).astype(np.float32)
+    zHz = g0.uniform(-1, 4, n).astype(np.float32)
+    Dd, Dad, zd = to_dev(D, Da, zHz)
+    Dh = torch.empty(n, dtype=torch.float32, device="cuda")
+    b.diag_update(Dd, Dad, zd, 5, 0.9, 0.4, Dhat_out=Dh)
+    wD, wDa, wDh = oracle.precond_update(D.astype(np.float64), Da.astype(np.float64), zHz.astype(np.float64),
+                                         5, 0.9, 0.4)
+    assert np.allclose(Dd.cpu().numpy(), wD, rtol=1e-6, atol=1e-6)
+    assert np.allclose(Dad.cpu().numpy(), wDa, rtol=1e-6, atol=1e-6)
+    assert np.allclose(Dh.cpu().numpy(), wDh, rtol=1e-6, atol=1e-6)
+
+
+def test_precomputed_diagonal_parity(b):
+    """Sec. 4.1's precomputed preconditioner (three epochs of minibatches,
+    Hutchinson samples, running mean and exponential average) against the
+    oracle's run over the same minibatches and probes."""
+    from paper_2311_16100_amd import experiment as E
+    M, N, Bt, epochs = 20, 48, 16, 3
+    grid_o, opt_o = oracle.Grid(M), oracle.Optics()
+    rot = synth.uniform_rotations(N, 32)
+    df = synth.defocus_values(N, 1.0, 3.0, 32)
+    lam = 0.05
+    D, Da, k = E.precomputed_diagonal(b.Grid(M), b.Optics(), torch.from_numpy(rot).cuda(),
+                                      torch.from_numpy(df).cuda(), lam, epochs, Bt, n_probe=2, probe_seed=33,
+                                      perm_seed=34)
+    batches = [synth.epoch_permutation(N, 34, e)[s:s + Bt] for e in range(epochs) for s in range(0, N - Bt + 1, Bt)]
+    assert k == len(batches)
+    wD, wDa = oracle.precomputed_diagonal(grid_o, opt_o, oracle.Poses(rot, df), batches, N / Bt, lam, 0.9, 2, 33)
+    close(D.cpu().numpy(), wD, 1e-4, "D")
+    close(Da.cpu().numpy(), wDa, 1e-4, "D_avg")

@@ -402,3 +402,40 @@ def test_alg1_non_finite_raises(orc):
     with pytest.raises(FloatingPointError):
         orc.alg1_iteration(grid, opt, poses, x, st, 1.0, 0.1, 0.0, 0.9, 0.1)
     assert np.array_equal(st.v, v0)
+
+
+def test_precomputed_diagonal_nearest_neighbour_closed_form(orc):
+    # Sec. 4.1's precomputed preconditioner with nearest-neighbour
+    # interpolation: H_I is diagonal, so every iteration's Hutchinson sample
+    # is exactly diag(H_I) (the Remark after the diagonal estimate), whatever
+    # the probes.  The result must then equal the exponential average (from
+    # D^(0) = 1) of the running means of the batch diagonals, each computed
+    # here from the squared-weight backprojection (a code path that shares
+    # nothing with the HVP): after the first epoch the running mean is diag H
+    # itself, and D approaches it like beta^k.
+    M, N, B = 8, 12, 4
+    grid, opt = orc.Grid(M, interp=0), orc.Optics()
+    poses = orc.Poses(synth.uniform_rotations(N, seed=81), synth.defocus_values(N, 1.0, 3.0, seed=81))
+    scale, lam, beta = N / B, 0.2, 0.9
+    batches = [synth.epoch_permutation(N, 82, e)[s:s + B] for e in range(4) for s in range(0, N, B)]
+    D, D_avg = orc.precomputed_diagonal(grid, opt, poses, batches, scale, lam, beta, 2, 83)
+    samples = [orc.exact_diag(grid, opt, poses.subset(list(b)), scale, lam).reshape(-1) for b in batches]
+    running = [np.mean(samples[:k], axis=0) for k in range(1, len(samples) + 1)]
+    want = np.ones(M ** 3)
+    for r in running:
+        want = beta * want + (1 - beta) * r
+    assert np.allclose(D_avg, running[-1], rtol=1e-12, atol=1e-12)
+    assert np.allclose(D, want, rtol=1e-12, atol=1e-12)
+    # a whole number of epochs: the running mean is the full diagonal
+    full = orc.exact_diag(grid, opt, poses, 1.0, lam).reshape(-1)
+    assert np.allclose(D_avg, full, rtol=1e-12, atol=1e-12)
+    assert np.max(np.abs(D - full)) <= beta ** len(batches) * np.max(np.abs(1 - full)) + \
+        np.max(np.abs(np.array(running[: N // B]) - full)) + 1e-12
+
+
+def test_conditioning_shell_counts_match_oracle(orc):
+    # p(R) of the paper's condition-number figure comes from the same integer
+    # shells as the threshold of eq. (thresh value)
+    from paper_2311_16100_amd import conditioning as C
+    for R in (1, 2, 5, 16, 31):
+        assert C.shell_point_counts(R) == tuple(orc.shell_counts(2 * R + 4, R))
