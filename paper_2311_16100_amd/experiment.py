@@ -262,11 +262,26 @@ def high_band_mask(M: int, r_max: float, device) -> torch.Tensor:
     return (k2 >= (M / 4) ** 2) & (k2 <= r_max * r_max)
 
 
+def save_checkpoint(path: str, arrays: dict, meta: dict):
+    """Arrays and a JSON record in one .npz (read back without pickle)."""
+    import json
+    np.savez(path, __meta__=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8), **arrays)
+
+
+def load_checkpoint(path: str):
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["__meta__"]).decode())
+        arrays = {k: z[k].copy() for k in z.files if k != "__meta__"}
+    return arrays, meta
+
+
 def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
             eval_every: int = 1, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
             seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball",
             deterministic: bool = False, progress=None, queue_probes: bool = True,
-            average_from_epoch: int | None = None, fsc_every: int = 0) -> RunResult:
+            average_from_epoch: int | None = None, fsc_every: int = 0, checkpoint: str | None = None,
+            checkpoint_every: int = 0, resume: str | None = None, stop_at: int | None = None) -> RunResult:
     """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
     the whole ball |k| <= r_max; "high": M/4 <= |k| <= r_max) is <= target,
     evaluated every `eval_every` iterations.
@@ -282,7 +297,15 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     `queue_probes` the runner is told the next batch's poses (the Hutchinson
     arm then computes its next probe product during the line search).
     The shell correlation with v* is recorded after every epoch, at the stop,
-    and every `fsc_every` iterations if that is > 0 (outside the timing)."""
+    and every `fsc_every` iterations if that is > 0 (outside the timing).
+    Checkpoints: with `checkpoint` a path, the run's state (iterate, diagonal
+    estimate, step size, iteration counter, position in the epoch, averaging
+    and the results so far) is written there every `checkpoint_every`
+    iterations and when `stop_at` iterations are done (the run then returns,
+    note "stopped"); `resume` continues from such a file.  The minibatch order
+    (a permutation per epoch) and the probes (numbered by iteration) are
+    functions of the seeds and counters, so a resumed run takes the same
+    minibatches and probes as an uninterrupted one."""
     dev = ds.device
     scale = ds.N / batch
     alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
@@ -301,6 +324,36 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     eta_cap = eta0
     v_avg = None  # Polyak-Ruppert average of the iterates
     n_avg = 0
+    start_epoch, start_s = 0, 0
+    if resume:
+        arrays, meta = load_checkpoint(resume)
+        if meta["arm"] != arm or meta["batch"] != batch or meta["N"] != ds.N or meta["M"] != ds.M:
+            raise ValueError("checkpoint %s is for another run" % resume)
+        run.load_state_dict({"arrays": {k: arrays[k] for k in ("v", "D", "D_avg") if k in arrays},
+                             **{k: meta[k] for k in ("eta", "k", "capped", "halvings")}})
+        it, eta_cap, n_avg = meta["it"], meta["eta_cap"], meta["n_avg"]
+        start_epoch, start_s = meta["epoch"], meta["s"]
+        if "v_avg" in arrays:
+            v_avg = torch.from_numpy(arrays["v_avg"]).to(dev)
+        res.errors = [tuple(e) for e in meta["errors"]]
+        res.fsc = [(i, f) for i, f in meta["fsc"]]
+        res.halvings, res.gen_seconds, res.eval_seconds = meta["halvings_sum"], meta["gen_s"], meta["eval_s"]
+        t0 -= meta["seconds"]  # continue the wall-time count
+
+    def write_checkpoint(epoch, s_next):
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        sd = run.state_dict()
+        arrays = dict(sd["arrays"])
+        if v_avg is not None:
+            arrays["v_avg"] = v_avg.cpu().numpy()
+        meta = {"arm": arm, "batch": batch, "N": ds.N, "M": ds.M, "epoch": epoch, "s": s_next, "it": it,
+                "eta_cap": eta_cap, "n_avg": n_avg, "eta": sd["eta"], "k": sd["k"], "capped": sd["capped"],
+                "halvings": sd["halvings"], "errors": res.errors, "fsc": res.fsc, "halvings_sum": res.halvings,
+                "gen_s": res.gen_seconds, "eval_s": res.eval_seconds,
+                "seconds": tc - t0 - res.gen_seconds - res.eval_seconds}
+        save_checkpoint(checkpoint, arrays, meta)
+        return time.perf_counter() - tc
 
     def evaluate(now):
         """Record the error (of the average, when averaging) at `now`; the
@@ -322,14 +375,16 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     # Hutchinson arm compute its next probe product during the line search
     cur = None
     perm_next = None
-    for epoch in range(max_epochs):
-        if decay_epochs and epoch > 0 and epoch % decay_epochs == 0:
+    for epoch in range(start_epoch, max_epochs):
+        if decay_epochs and epoch > 0 and epoch % decay_epochs == 0 and not (resume and epoch == start_epoch
+                                                                             and start_s > 0):
             eta_cap *= 0.5
             run.state.eta = min(run.state.eta, eta_cap)
         perm = perm_next if perm_next is not None else torch.from_numpy(
             synth.epoch_permutation(ds.N, seed, epoch)).to(dev)
         perm_next = None
-        for s in range(0, ds.N - batch + 1, batch):
+        first_s = start_s if epoch == start_epoch else 0
+        for s in range(first_s, ds.N - batch + 1, batch):
             idx = perm[s:s + batch]
             if cur is None:
                 cur = poses_of(idx)
@@ -363,6 +418,15 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
             if progress and time.perf_counter() - t_log > 30.0:
                 t_log = time.perf_counter()
                 progress("  %s: iteration %d, %.1f s" % (arm, it, t_log - t0 - res.gen_seconds - res.eval_seconds))
+            if checkpoint and ((checkpoint_every and it % checkpoint_every == 0) or it == stop_at):
+                nxt_s = s + batch
+                ce, cs = (epoch, nxt_s) if nxt_s <= ds.N - batch else (epoch + 1, 0)
+                t0 += write_checkpoint(ce, cs)
+            if stop_at is not None and it >= stop_at:
+                res.iterations, res.note = it, "stopped"
+                res.seconds = time.perf_counter() - t0 - res.gen_seconds - res.eval_seconds
+                res.capped = run.state.capped
+                return res
             if fsc_every and it % fsc_every == 0:
                 tf = time.perf_counter()
                 res.fsc.append((it, B.fsc(ds.grid, v_avg if v_avg is not None else run.state.v,

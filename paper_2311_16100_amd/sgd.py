@@ -86,6 +86,30 @@ class Alg1Runner:
         self.ws_hutch = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev) if arm == "hutchinson" else None
         self.ws_proj = B.alloc_workspace(grid, batch, B.CSG_WS_PROJECT, dev)
 
+    def state_dict(self) -> dict:
+        """The iteration state (v, D, D_avg, eta, k and the line-search
+        counters) as host arrays and numbers, for a checkpoint."""
+        st = self.state
+        arrays = {"v": st.v.cpu().numpy()}
+        if st.D is not None:
+            arrays["D"] = st.D.cpu().numpy()
+        if st.D_avg is not None:
+            arrays["D_avg"] = st.D_avg.cpu().numpy()
+        return {"arrays": arrays, "eta": st.eta, "k": st.k, "capped": st.capped, "halvings": list(st.halvings)}
+
+    def load_state_dict(self, sd: dict):
+        """Restore what state_dict returned (same arm and grid); a probe
+        product queued for the next batch is dropped and recomputed."""
+        st = self.state
+        st.v.copy_(torch.from_numpy(sd["arrays"]["v"]))
+        if st.D is not None and "D" in sd["arrays"]:
+            st.D.copy_(torch.from_numpy(sd["arrays"]["D"]))
+        if st.D_avg is not None and "D_avg" in sd["arrays"]:
+            st.D_avg.copy_(torch.from_numpy(sd["arrays"]["D_avg"]))
+        st.eta, st.k, st.capped = float(sd["eta"]), int(sd["k"]), int(sd["capped"])
+        st.halvings = list(sd["halvings"])
+        self._queued = None
+
     def iteration(self, rot_I, df_I, x_I, next_poses=None) -> int:
         """One iteration on the batch (rot_I, df_I, x_I).  `next_poses` =
         (rot, defocus) of the next call's batch, if known: the Hutchinson arm

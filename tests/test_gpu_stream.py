@@ -58,3 +58,39 @@ def test_queued_probes_leave_the_run_unchanged(E):
     # did not belong together would move the errors far beyond this
     ea, eb = [e[2] for e in a.errors], [e[2] for e in b.errors]
     assert len(ea) == len(eb) and max(abs(x - y) / y for x, y in zip(ea, eb)) < 1e-3
+
+
+def test_checkpoint_resume_is_bit_exact(E, tmp_path):
+    """A run stopped mid-epoch and resumed from its checkpoint ends where the
+    uninterrupted run ends, bit for bit, on the deterministic path (fixed
+    diagonal, fixed-point gradient); across an epoch boundary with the step
+    halving and iterate averaging too."""
+    ds = E.make_dataset(24, 320, 12, 15, float("inf"))
+    v_star, _, _ = E.ground_truth(ds)
+    D = E.exact_diagonal(ds)
+    kw = dict(D_fixed=D, max_epochs=3, eval_every=3, deterministic=True, target=1e-9, seed=3)
+    for stop, extra in ((13, {}), (20, dict(decay_epochs=1, average_from_epoch=1))):
+        full = E.run_arm(ds, v_star, "exact", 32, **kw, **extra)
+        ck = str(tmp_path / ("ck%d.npz" % stop))
+        part = E.run_arm(ds, v_star, "exact", 32, **kw, **extra, checkpoint=ck, stop_at=stop)
+        assert part.note == "stopped" and part.iterations == stop
+        rest = E.run_arm(ds, v_star, "exact", 32, **kw, **extra, resume=ck)
+        assert rest.iterations == full.iterations == 30
+        assert [e[:1] + e[2:] for e in rest.errors] == [e[:1] + e[2:] for e in full.errors]
+        assert rest.halvings == full.halvings
+
+
+def test_checkpoint_resume_hutchinson(E, tmp_path):
+    """The Hutchinson arm resumed from a checkpoint (D and D_avg restored, the
+    probes numbered by iteration) follows the uninterrupted run; its probe
+    products sum with float atomics, so the match is to rounding."""
+    ds = E.make_dataset(24, 320, 12, 16, float("inf"))
+    v_star, _, _ = E.ground_truth(ds)
+    kw = dict(max_epochs=2, eval_every=2, target=1e-9, seed=4)
+    full = E.run_arm(ds, v_star, "hutchinson", 32, **kw)
+    ck = str(tmp_path / "ckh.npz")
+    E.run_arm(ds, v_star, "hutchinson", 32, **kw, checkpoint=ck, stop_at=7)
+    rest = E.run_arm(ds, v_star, "hutchinson", 32, **kw, resume=ck)
+    assert rest.iterations == full.iterations == 20
+    ea, eb = [e[2] for e in rest.errors], [e[2] for e in full.errors]
+    assert len(ea) == len(eb) and max(abs(x - y) / y for x, y in zip(ea, eb)) < 1e-4
