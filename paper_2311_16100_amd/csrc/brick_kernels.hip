@@ -434,8 +434,11 @@ struct PackedScale {
         p.invS = ldexpf(1.f, -e);
         return p;
     }
-    __device__ __forceinline__ unsigned long long pack(float re, float im) const {
-        const int qr = (int)rintf(re * S), qi = (int)rintf(im * S);
+    // re and im already carry the factor S (S is a power of two, so scaling
+    // the value once per pixel instead of every corner term gives the same
+    // products)
+    __device__ __forceinline__ unsigned long long pack_scaled(float re, float im) const {
+        const int qr = (int)rintf(re), qi = (int)rintf(im);
         return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
     }
     __device__ __forceinline__ void unpack(unsigned long long v, float &re, float &im) const {
@@ -1051,6 +1054,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                         } else if (MODE == kBSqDiag) {
                                             val = make_float2(a.scale * C * C, 0.0f);
                                         }
+                                        if (PK_ALWAYS) val = make_float2(val.x * pk.S, val.y * pk.S);
                                         if (SCATTER) {
                                             // all eight corners; a corner beyond the grid edge
                                             // lands in a slot that is never written back
@@ -1064,7 +1068,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                 } else if (MODE == kBSqDiag) {
                                                     atomicAdd(&acc_re[li], (double)(w * w * val.x));
                                                 } else if (PK_ALWAYS) {
-                                                    atomicAdd(&acc_pk[li], pk.pack(w * val.x, w * val.y));
+                                                    atomicAdd(&acc_pk[li], pk.pack_scaled(w * val.x, w * val.y));
                                                 } else if (QLDS) {
                                                     const double S = FX ? fxS : qs.S;
                                                     atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
