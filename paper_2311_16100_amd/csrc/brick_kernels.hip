@@ -10,17 +10,21 @@
 //   - stages the brick and the voxels one step above it on each axis (13^3
 //     complex values of the gathered volume) in LDS once, so every trilinear
 //     gather is 8 LDS reads;
-//   - accumulates the adjoint into an LDS array of the same extent as 64-bit
-//     fixed-point integers, one per component (ItemScale; the deterministic
-//     mode: FxScale; the probe HVP packs both components into one, see
-//     PackedScale: flushed after every chunk), and adds it to HBM once per
-//     voxel at the end with global
+//   - accumulates the adjoint into an LDS array of the same extent as exact
+//     fixed-point integers: in the gradient and the HVP both components
+//     of a contribution in one 64-bit word with wrap counters (CarryScale),
+//     elsewhere one 64-bit integer per component (ItemScale; the
+//     deterministic mode: FxScale; the probe HVP packs both components into
+//     one, see PackedScale: flushed after every chunk), and adds it to HBM
+//     once per voxel at the end with global
 //     atomics (the upper faces of the extent belong to the neighbouring
 //     bricks, which other blocks may be flushing at the same time).  On gfx950
 //     the LDS single-precision atomic add sustains about a twentieth of the
 //     lane rate of the 64-bit ones, and in these kernels the integer add is
 //     cheaper than the double one, so the wide integer accumulator is also
-//     the fastest.
+//     the fastest; the scatter to effectively random voxels of the extent
+//     is bound by LDS bank conflicts, which cost per atomic instruction, so
+//     one instruction per contribution beats two.
 // The pixels of an image that matter for a brick are found row by row: for
 // image row ky the sample points form a line, and the pixels whose cell
 // reaches the brick's box form an interval of kx, computed by clipping the
@@ -50,6 +54,8 @@
 //                  sum of every voxel (no image is read)
 //   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
 //                  Hessian (real accumulator; no image is read)
+#include <type_traits>
+
 #include "csg_device.h"
 #include "csg_internal.h"
 
@@ -480,6 +486,78 @@ struct ItemScale {
     }
 };
 
+// Packed accumulator with wrap counters (gradient and HVP).  A
+// contribution (w val.x, w val.y) is rounded to integers (qr, qi) at a
+// per-item power-of-two scale S with |val| S <= 2^29, so every integer fits
+// in 30 bits.  One 64-bit LDS atomic adds qr + 2^32 qi to the voxel's word
+// W, whose low half then holds the real sum R and whose high half the
+// imaginary sum I, each modulo 2^32: R = lo + 2^32 c_lo, I = H - c_lo +
+// 2^32 c_hi, with lo the low half as a signed number, H the high half plus
+// one where lo is negative, and c_lo, c_hi the net count of signed wraps of
+// lo and of H.  The atomic returns the word it added to; from that old value
+// the lane that made a half wrap sees it happen (the exact test runs only
+// when an old half lies outside [-2^30, 2^30), where a 30-bit addend can
+// wrap it) and adds +-1 to the counter.  Every addition is exact, so the
+// sums are exact 64-bit integers (as with one 64-bit word per component)
+// while each contribution costs one LDS atomic instead of two; each
+// contribution is rounded by at most 2^-30 |val|max, and the flush converts
+// each sum to float once.
+struct CarryScale {
+    float S = 1.f;
+    double invS = 1.0;
+    int ok = 1;
+    static __device__ __forceinline__ CarryScale make(double V) {
+        CarryScale q;
+        q.ok = isfinite(V) ? 1 : 0;
+        if (q.ok && V > 0.0) {
+            int kv;
+            (void)frexp(V, &kv);  // V < 2^kv
+            int e = 29 - kv;
+            if (e < -126) q.ok = 0;
+            e = min(max(e, -126), 127);
+            q.S = ldexpf(1.f, e);
+            q.invS = ldexp(1.0, -e);
+        }
+        return q;
+    }
+};
+
+// corners whose atomics are issued before their old words are looked at
+// (measured at 256^3 with 1024 images: 2 beats 1, 4 and 8, where the held
+// words spill)
+#ifndef CSG_CARRY_GROUP
+#define CSG_CARRY_GROUP 2
+#endif
+constexpr int CARRY_GROUP = CSG_CARRY_GROUP;
+
+__device__ __forceinline__ unsigned long long carry_pack(int qr, int qi) {
+    return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
+}
+
+// sign bit set when a half of the old word lies outside [-2^30, 2^30)
+__device__ __forceinline__ uint32_t carry_may_wrap(unsigned long long old) {
+    return ((uint32_t)old + 0x40000000u) | ((uint32_t)(old >> 32) + 0x40000000u);
+}
+
+// the wraps made by adding (qr, qi) to the word whose old value was `old`
+__device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi, int *c_lo, int *c_hi) {
+    const int lo_old = (int)(uint32_t)old;
+    const int lo_new = (int)((uint32_t)lo_old + (uint32_t)qr);
+    const int dl = ((lo_old ^ lo_new) & (qr ^ lo_new)) < 0 ? (qr > 0 ? 1 : -1) : 0;
+    const int h_old = (int)((uint32_t)(old >> 32) + (lo_old < 0 ? 1u : 0u));
+    const long long h_new = (long long)h_old + qi + dl;
+    const int dh = h_new > 0x7fffffffll ? 1 : (h_new < -0x80000000ll ? -1 : 0);
+    if (dl) atomicAdd(c_lo, dl);
+    if (dh) atomicAdd(c_hi, dh);
+}
+
+__device__ __forceinline__ void carry_decode(unsigned long long W, int c_lo, int c_hi, long long &R, long long &I) {
+    const int lo = (int)(uint32_t)W;
+    const int H = (int)((uint32_t)(W >> 32) + (lo < 0 ? 1u : 0u));
+    R = (long long)lo + (long long)c_lo * 4294967296ll;
+    I = (long long)H - c_lo + (long long)c_hi * 4294967296ll;
+}
+
 #ifndef CSG_BRICK_WAVES
 #define CSG_BRICK_WAVES 6
 #endif
@@ -505,13 +583,20 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // go into one 64-bit integer LDS atomic, as 32-bit fixed-point numbers with
     // a per-item power-of-two scale.  Only the probe HVP packs.
     constexpr bool PK_ALWAYS = MODE == kBHvpProbe;
-    // 64-bit fixed-point LDS accumulators: the deterministic modes (one
-    // launch-wide scale, FxScale) and the fast modes other than the packed
-    // probe (a scale per work item, ItemScale; the flush adds floats as
-    // before).  On gfx950 the LDS 64-bit integer atomic add is cheaper than
-    // the double one.
+    // fixed-point LDS accumulators: the deterministic modes (one 64-bit
+    // integer per component, one launch-wide scale, FxScale) and the fast
+    // modes other than the packed probe (a scale per work item: the carry
+    // accumulator of CarryScale in gradient and HVP, one 64-bit integer per
+    // component with ItemScale in the backproject, features and
+    // squared-weight modes; the flush adds floats).  On gfx950 the LDS 64-bit integer atomic
+    // add is cheaper than the double one.
     constexpr bool QLDS = FX || (CSG_LDS_FIXED && SCATTER && !PK_ALWAYS);
     constexpr bool QITEM = QLDS && !FX;
+    // the packed accumulator with wrap counters (see CarryScale)
+    // (gradient and HVP; in backproject, with its 80-register budget, the
+    // held old words cost spills that ate the gain)
+    constexpr bool QCARRY = QITEM && (MODE == kBGradient || MODE == kBHvp);
+    using QScale = typename std::conditional<QCARRY, CarryScale, ItemScale>::type;
     // the item bound needs the largest staged volume value (gradient, HVP)
     // and, where images are read (backproject, gradient), a bound on their
     // values: a guess, checked against every value read; an item that meets
@@ -527,6 +612,10 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // are zero in both)
     unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
+    // and the carry accumulator: its words in acc_re, its counters in acc_im
+    unsigned long long *const acc_w = reinterpret_cast<unsigned long long *>(acc_re);
+    int *const c_lo = reinterpret_cast<int *>(acc_im);
+    int *const c_hi = c_lo + XN;
     __shared__ unsigned s_wmax[kBT / 64];
     __shared__ unsigned s_xmax[kBT / 64];
     // probe HVP: signs of the staged rows ([row][probe]; see the staging)
@@ -718,7 +807,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             }
         }
         PackedScale pk;  // set in the first window (after a barrier)
-        ItemScale qs;    // likewise
+        QScale qs;       // likewise
         // the image-value guess of the item: twice the block's maximum so far
         // (the exponent raised by one, at most the largest float; a NaN or an
         // infinity stays and gives a NaN flush)
@@ -759,6 +848,18 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                     const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
                     if (qr) atomicAdd(&a.fx[2 * gi], qr);
                     if (qi) atomicAdd(&a.fx[2 * gi + 1], qi);
+                    continue;
+                }
+                if (QCARRY) {
+                    long long R, I;
+                    carry_decode(acc_w[li], c_lo[li], c_hi[li], R, I);
+                    if (!qs.ok) {
+                        atomicAdd(&a.accum[gi].x, __builtin_nanf(""));
+                        atomicAdd(&a.accum[gi].y, __builtin_nanf(""));
+                    } else {
+                        if (R) atomicAdd(&a.accum[gi].x, (float)((double)R * qs.invS));
+                        if (I) atomicAdd(&a.accum[gi].y, (float)((double)I * qs.invS));
+                    }
                     continue;
                 }
                 if (QITEM && MODE == kBSqDiag) {
@@ -803,7 +904,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             // (features: C^2 w <= 1 and w <= 1; squared weights: |scale| C^2 w^2;
             // backproject: |scale| times the image guess, set in the first window)
             if (QITEM && !GATHER && !READS_IMG)
-                qs = ItemScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
+                qs = QScale::make(MODE == kBFeatures ? 1.0 : fabs((double)a.scale));
             for (int first = first0; first < last; first += CHUNK) {
                 const int n_img = min(CHUNK, last - first);
                 if (first > first0 || attempt > 0) {
@@ -825,11 +926,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                         if (QITEM) {
                             const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
                             const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
-                            qs = ItemScale::make(fabs((double)a.scale) * ((double)zb + xg));
+                            qs = QScale::make(fabs((double)a.scale) * ((double)zb + xg));
                         }
                     }
                     if (QITEM && !GATHER && READS_IMG && w0 == 0)
-                        qs = ItemScale::make(fabs((double)a.scale) *
+                        qs = QScale::make(fabs((double)a.scale) *
                                              (double)__uint_as_float(__builtin_amdgcn_readfirstlane(s_guess)));
                     // ---- the window's images (one thread each): constants, first row,
                     // row count.  Image s owns row records s MAXROWS .. s MAXROWS +
@@ -1055,7 +1156,38 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                             val = make_float2(a.scale * C * C, 0.0f);
                                         }
                                         if (PK_ALWAYS) val = make_float2(val.x * pk.S, val.y * pk.S);
-                                        if (SCATTER) {
+                                        if (QCARRY) {
+                                            // the packed atomics of CARRY_GROUP corners, then one
+                                            // look at their old words (see CarryScale)
+                                            const float2 vs = make_float2(val.x * qs.S, val.y * qs.S);
+#pragma unroll
+                                            for (int c0 = 0; c0 < 8; c0 += CARRY_GROUP) {
+                                                unsigned long long old[CARRY_GROUP];
+#pragma unroll
+                                                for (int k = 0; k < CARRY_GROUP; ++k) {
+                                                    const int c = c0 + k;
+                                                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                    const float w = wx[ax] * wy[ay] * wz[az];
+                                                    const int li = lb + az * XP + ay * XR + ax;
+                                                    old[k] = atomicAdd(&acc_w[li], carry_pack((int)rintf(w * vs.x),
+                                                                                              (int)rintf(w * vs.y)));
+                                                }
+                                                uint32_t f = 0u;
+#pragma unroll
+                                                for (int k = 0; k < CARRY_GROUP; ++k) f |= carry_may_wrap(old[k]);
+                                                if ((int)f < 0) {
+#pragma unroll
+                                                    for (int k = 0; k < CARRY_GROUP; ++k) {
+                                                        const int c = c0 + k;
+                                                        const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                        const float w = wx[ax] * wy[ay] * wz[az];
+                                                        const int li = lb + az * XP + ay * XR + ax;
+                                                        carry_fix(old[k], (int)rintf(w * vs.x), (int)rintf(w * vs.y),
+                                                                  c_lo + li, c_hi + li);
+                                                    }
+                                                }
+                                            }
+                                        } else if (SCATTER) {
                                             // all eight corners; a corner beyond the grid edge
                                             // lands in a slot that is never written back
 #pragma unroll

@@ -1,6 +1,8 @@
 """Throughput probes and single-entry-point timings, for profiling.
 
   python -m paper_2311_16100_amd.microbench lds      LDS atomic add rates (u32, u64, f32, f64)
+  python -m paper_2311_16100_amd.microbench scatter  complex contributions to random LDS voxels,
+                                                     per accumulator design
   python -m paper_2311_16100_amd.microbench valu     vector FMA issue rate
   python -m paper_2311_16100_amd.microbench learned_diag [--M 256]
                                                      the learned preconditioner's volume inference
@@ -32,6 +34,8 @@ def _mb():
     L = ctypes.CDLL(MB_LIB)
     L.csg_mb_lds_add.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.csg_mb_lds_add.restype = ctypes.c_float
+    L.csg_mb_lds_scatter.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.csg_mb_lds_scatter.restype = ctypes.c_float
     L.csg_mb_valu_fma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     L.csg_mb_valu_fma.restype = ctypes.c_float
     return L
@@ -54,6 +58,31 @@ def lds(blocks_per_cu=(1, 2, 4, 8), reps=4096, strides=(1,)):
                 rate = ops / (ms * 1e-3)
                 out.append({"type": name, "blocks_per_cu": bpc, "stride": stride, "reps": r, "ms": round(ms, 4),
                             "lane_ops_per_s": rate, "per_cu_per_clock": round(rate / (CUS * CLOCK_HZ), 3)})
+    return out
+
+
+SCATTER_DESIGNS = {0: "two ds_add_u64", 1: "one packed ds_add_u64", 2: "two ds_add_rtn_u32 + carry",
+                   3: "two ds_add_u32 (no carry)", 4: "one packed ds_add_rtn_u64 + carry"}
+
+
+def scatter(blocks_per_cu=(2, 4), reps=4096):
+    """Complex contributions per clock per CU scattered to random LDS
+    voxels, for each accumulator design of csg_mb_lds_scatter."""
+    import torch
+    L = _mb()
+    out = []
+    for design, name in SCATTER_DESIGNS.items():
+        for bpc in blocks_per_cu:
+            blocks = CUS * bpc
+            buf = torch.zeros(blocks, dtype=torch.float64, device="cuda")
+            ms = L.csg_mb_lds_scatter(design, ctypes.c_void_p(buf.data_ptr()), blocks, reps)
+            if ms <= 0:
+                raise RuntimeError("probe failed")
+            n = blocks * 256 * reps
+            rate = n / (ms * 1e-3)
+            out.append({"design": name, "blocks_per_cu": bpc, "reps": reps, "ms": round(ms, 4),
+                        "contributions_per_cu_per_clock": round(rate / (CUS * CLOCK_HZ), 3),
+                        "lds_cycles_per_wave_contribution": round(64 * CUS * CLOCK_HZ / rate, 2)})
     return out
 
 
@@ -128,13 +157,15 @@ def mlp_grad(n=8192, reps=20):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("what", choices=["lds", "valu", "learned_diag", "mlp_grad"])
+    ap.add_argument("what", choices=["lds", "scatter", "valu", "learned_diag", "mlp_grad"])
     ap.add_argument("--M", type=int, default=256)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args(argv)
     if a.what == "lds":
         res = lds()
+    elif a.what == "scatter":
+        res = scatter()
     elif a.what == "valu":
         res = valu()
     elif a.what == "learned_diag":

@@ -183,6 +183,38 @@ def test_hvp_parity(b, case):
         close(hz.cpu().numpy(), want, 1e-4, det)
 
 
+@pytest.mark.parametrize("same_pose", [False, True], ids=["4poses", "1pose"])
+def test_adjoint_sums_that_wrap_32_bits(b, same_pose):
+    """The gradient and HVP accumulate both components of a contribution in
+    one 64-bit LDS word whose 32-bit halves wrap, with the wraps counted
+    apart.  2048 images on four poses (or one pose and one repeated image,
+    so that every contribution to a voxel has the same sign) put hundreds of
+    contributions of the largest size into each reached voxel: the halves
+    wrap many times per voxel and work item.  Against the oracle and the
+    deterministic adjoint."""
+    M, n = 24, 2048
+    rot = synth.uniform_rotations(4, 41)
+    rot = np.repeat(rot[:1], n, axis=0) if same_pose else np.tile(rot, (n // 4, 1, 1))
+    df = synth.defocus_values(n, 1.0, 3.0, 41)
+    if same_pose:
+        df[:] = df[0]
+    vol = synth.random_complex((M, M, M), 41, stream=11)
+    img = synth.random_complex((n, M, M), 41, stream=12)
+    if same_pose:
+        img[:] = img[0]
+    grid_o, opt_o, P = oracle.Grid(M), oracle.Optics(), oracle.Poses(rot, df)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rd, dd, v, x = to_dev(P.rot, P.defocus, vol, img)
+    scale, lam = 1.5, 0.25
+    want = oracle.gradient(grid_o, opt_o, P, vol, img * _disk(grid_o)[None], scale, lam)
+    got = b.gradient(g, o, rd, dd, v, x, scale, lam).cpu().numpy()
+    det = b.gradient(g, o, rd, dd, v, x, scale, lam, deterministic=True).cpu().numpy()
+    close(got, want, 1e-4, "gradient")
+    close(got, det, 1e-5, "gradient vs deterministic")
+    want = oracle.hvp(grid_o, opt_o, P, vol, scale, lam)
+    close(b.hvp(g, o, rd, dd, v, scale, lam).cpu().numpy(), want, 1e-4, "hvp")
+
+
 def test_rademacher_bit_exact(b):
     for nvox, seed, probe in ((36 ** 3, 5, 0), (1000, 2 ** 40 + 7, 3), (130, 1, 2 ** 33 + 1), (5, 9, 9)):
         z = b.rademacher(nvox, seed, probe).cpu().numpy()
