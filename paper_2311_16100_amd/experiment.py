@@ -45,7 +45,9 @@ CHUNK = 2048  # images per library call when sweeping a whole data set
 class Dataset:
     """Poses, defocus and ground truth of a synthetic data set, with its
     images either resident (`x`) or, for sets larger than device memory,
-    regenerated batch by batch from v_true (noise-free sets only)."""
+    regenerated batch by batch from v_true, with the noise of each image
+    made on the device from (seed, image index) (synth.gpu_noise), so a
+    regenerated image is always the same image."""
     grid: B.Grid
     optics: B.Optics
     rot: torch.Tensor
@@ -76,8 +78,14 @@ class Dataset:
         """Images of the index tensor or slice `idx` (contiguous)."""
         if self.x is not None:
             return self.x[idx].contiguous()
-        return B.project(self.grid, self.optics, self.rot[idx].contiguous(), self.defocus[idx].contiguous(),
-                         self.v_true)
+        y = B.project(self.grid, self.optics, self.rot[idx].contiguous(), self.defocus[idx].contiguous(),
+                      self.v_true)
+        if self.sigma2 > 0:
+            from synth import gpu_noise
+            ii = torch.arange(self.N, device=self.device)[idx] if isinstance(idx, slice) else idx
+            gpu_noise.add_disk_noise(y, ii.to(torch.int64), int(math.floor(self.grid.rmax ** 2)), self.sigma2,
+                                     gpu_noise.noise_seed(self.seed, synth.STREAM_NOISE))
+        return y
 
 
 def disk_mask(M: int, r: float, device) -> torch.Tensor:
@@ -93,16 +101,27 @@ def ball_mask(M: int, r: float, device) -> torch.Tensor:
 def make_dataset(M: int, N: int, n_blobs: int, seed: int, snr: float, defocus_um=(1.0, 3.0), poses="uniform",
                  kappa: float = 10.0, device="cuda", lam: float | None = None, stream: bool = False) -> Dataset:
     """stream=True keeps only poses and defocus resident and regenerates the
-    (noise-free) images of each batch when they are needed."""
+    images of each batch when they are needed (with their noise, made on the
+    device per image).  The noise variance is sigma^2 = (mean signal power
+    on the disk of the first 1024 images) / snr either way."""
     grid, optics = B.Grid(M), B.Optics()
     v_true = torch.from_numpy(synth.blob_volume(M, n_blobs, seed)).to(device)
     rot = synth.vmf_rotations(N, kappa, seed) if poses == "vmf" else synth.uniform_rotations(N, seed)
     rot = torch.from_numpy(rot).to(device)
     df = torch.from_numpy(synth.defocus_values(N, defocus_um[0], defocus_um[1], seed)).to(device)
+    noisy = math.isfinite(snr) and snr > 0
     if stream:
-        if math.isfinite(snr) and snr > 0:
-            raise ValueError("streamed data sets are noise-free (snr must be inf)")
-        return Dataset(grid, optics, rot, df, None, v_true, 0.0, float(1e-3 if lam is None else lam), seed)
+        if not noisy:
+            return Dataset(grid, optics, rot, df, None, v_true, 0.0, float(1e-3 if lam is None else lam), seed)
+        n0 = min(N, 1024)
+        pilot = B.project(grid, optics, rot[:n0].contiguous(), df[:n0].contiguous(), v_true)
+        disk = disk_mask(M, grid.rmax, device)
+        power = float((torch.abs(pilot) ** 2)[:, disk].mean().item())
+        del pilot
+        tau2 = float((torch.abs(v_true) ** 2)[ball_mask(M, grid.rmax, device)].mean().item())
+        sigma2 = power / snr
+        return Dataset(grid, optics, rot, df, None, v_true, sigma2, float(sigma2 / tau2 if lam is None else lam),
+                       seed)
     x = torch.empty((N, M, M), dtype=torch.complex64, device=device)
     for s in range(0, N, CHUNK):
         e = min(N, s + CHUNK)

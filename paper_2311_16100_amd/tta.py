@@ -52,6 +52,13 @@ EVAL_SPECS = {
     "stress_320": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
                        poses="vmf", kappa=10.0, stream=True, deterministic=True, cg_tol=1e-9, cg_max_iter=150, max_epochs=8,
                        time_limit=150.0, fsc_every=61),
+    # the stress set at its own SNR (0.02), lambda = sigma^2 / tau^2, the
+    # noise of each regenerated image made on the device from its index;
+    # iterates averaged from epoch 1 on in every arm, as for the mid set
+    "stress_320_snr002": dict(M=320, N=500_000, n_blobs=1000, batch=2048, defocus_um=(0.5, 4.0), seed=5320,
+                              poses="vmf", kappa=10.0, stream=True, deterministic=True, snr=0.02, cg_tol=1e-7,
+                              cg_max_iter=150, average_from_epoch=1, max_epochs=40, time_limit=150.0,
+                              stops=("ball",)),
 }
 
 

@@ -22,6 +22,52 @@ def test_streamed_images_equal_resident(E):
     assert st.lam == res.lam
 
 
+def test_streamed_noise_is_a_function_of_the_image_index(E):
+    """A noisy streamed set: an image carries the same noise in any batch
+    and position; the noise has the set's variance on the disk (real and
+    imaginary parts each half of it), none outside, no mean, and is
+    uncorrelated between images; a few pixels against the generator's
+    definition (Philox4x32-10 from the oracle's copy, then Box-Muller)."""
+    import math
+
+    import numpy as np
+
+    import oracle
+    import synth
+    from synth import gpu_noise
+    ds = E.make_dataset(48, 4000, 20, 15, 0.05, stream=True)
+    assert ds.streamed and ds.sigma2 > 0
+    clean = E.make_dataset(48, 4000, 20, 15, float("inf"), stream=True)
+    a = torch.tensor([5, 3999, 17, 2048], device=ds.device)
+    b = torch.tensor([17, 1, 5, 2, 3999, 6], device=ds.device)
+    xa, xb = ds.images(a), ds.images(b)
+    assert torch.equal(xa[0], xb[2]) and torch.equal(xa[2], xb[0]) and torch.equal(xa[1], xb[4])
+    assert torch.equal(ds.images(slice(2040, 2050))[8], xa[3])
+    idx = torch.arange(0, 4000, 3, device=ds.device)
+    nz = (ds.images(idx) - clean.images(idx)).cpu().numpy()
+    ax = np.arange(48) - 24
+    disk = (ax[:, None] ** 2 + ax[None, :] ** 2) <= math.floor(ds.grid.rmax ** 2)
+    assert np.all(nz[:, ~disk] == 0)
+    v = nz[:, disk]
+    n = v.size
+    assert abs(np.mean(np.abs(v) ** 2) / ds.sigma2 - 1) < 6 / math.sqrt(n)
+    assert abs(np.mean(v.real ** 2) / (ds.sigma2 / 2) - 1) < 8 / math.sqrt(n)
+    assert abs(np.mean(v)) / math.sqrt(ds.sigma2) < 6 / math.sqrt(n)
+    c = np.vdot(v[0], v[1]) / np.sqrt(np.vdot(v[0], v[0]).real * np.vdot(v[1], v[1]).real)
+    assert abs(c) < 6 / math.sqrt(v.shape[1])
+    key = gpu_noise.noise_seed(ds.seed, synth.STREAM_NOISE)
+    sd = math.sqrt(ds.sigma2 / 2)
+    for i_row, img in ((0, 0), (5, 15), (100, 300)):
+        for p in (24 * 48 + 24, 10 * 48 + 30, 40 * 48 + 20):
+            r = oracle.philox4x32_10([p, img, 0, gpu_noise.TAG], [key & 0xFFFFFFFF, key >> 32])
+            u1 = ((int(r[0]) >> 8) + 1) * 2.0 ** -24
+            u2 = (int(r[1]) >> 8) * 2.0 ** -24
+            rad = sd * math.sqrt(-2 * math.log(u1))
+            want = complex(rad * math.cos(2 * math.pi * u2), rad * math.sin(2 * math.pi * u2))
+            got = complex(nz[i_row].reshape(-1)[p])
+            assert abs(got - want) <= 1e-4 * sd + 1e-5 * abs(want), (img, p, got, want)
+
+
 def test_streamed_run_matches_resident_run(E):
     res = E.make_dataset(32, 1000, 20, 12, float("inf"))
     st = E.make_dataset(32, 1000, 20, 12, float("inf"), stream=True)
