@@ -56,6 +56,7 @@
 //                  Hessian (real accumulator; no image is read)
 #include <type_traits>
 
+#include "carry.h"
 #include "csg_device.h"
 #include "csg_internal.h"
 
@@ -424,6 +425,14 @@ __device__ __forceinline__ double rint_scaled(float e) {
 // case, the result is about 1e-5 relative (measured), well below the noise of
 // a two-probe Hutchinson estimate; the gradient and the general HVP, whose
 // sums need float accuracy, keep one 64-bit integer per component.
+// x rounded to an integer, halves upwards (floor(x + 0.5) in one
+// instruction; |x| < 2^31)
+__device__ __forceinline__ int round_half_up(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 struct PackedScale {
     float S = 1.f, invS = 1.f;
     static __device__ __forceinline__ PackedScale make(float V) {
@@ -444,7 +453,7 @@ struct PackedScale {
     // the value once per pixel instead of every corner term gives the same
     // products)
     __device__ __forceinline__ unsigned long long pack_scaled(float re, float im) const {
-        const int qr = (int)rintf(re), qi = (int)rintf(im);
+        const int qr = round_half_up(re), qi = round_half_up(im);
         return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
     }
     __device__ __forceinline__ void unpack(unsigned long long v, float &re, float &im) const {
@@ -530,32 +539,12 @@ struct CarryScale {
 #endif
 constexpr int CARRY_GROUP = CSG_CARRY_GROUP;
 
-__device__ __forceinline__ unsigned long long carry_pack(int qr, int qi) {
-    return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
-}
-
-// sign bit set when a half of the old word lies outside [-2^30, 2^30)
-__device__ __forceinline__ uint32_t carry_may_wrap(unsigned long long old) {
-    return ((uint32_t)old + 0x40000000u) | ((uint32_t)(old >> 32) + 0x40000000u);
-}
-
-// the wraps made by adding (qr, qi) to the word whose old value was `old`
+// the lane's wraps go to the voxel's counters
 __device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi, int *c_lo, int *c_hi) {
-    const int lo_old = (int)(uint32_t)old;
-    const int lo_new = (int)((uint32_t)lo_old + (uint32_t)qr);
-    const int dl = ((lo_old ^ lo_new) & (qr ^ lo_new)) < 0 ? (qr > 0 ? 1 : -1) : 0;
-    const int h_old = (int)((uint32_t)(old >> 32) + (lo_old < 0 ? 1u : 0u));
-    const long long h_new = (long long)h_old + qi + dl;
-    const int dh = h_new > 0x7fffffffll ? 1 : (h_new < -0x80000000ll ? -1 : 0);
+    int dl, dh;
+    carry_wraps(old, qr, qi, dl, dh);
     if (dl) atomicAdd(c_lo, dl);
     if (dh) atomicAdd(c_hi, dh);
-}
-
-__device__ __forceinline__ void carry_decode(unsigned long long W, int c_lo, int c_hi, long long &R, long long &I) {
-    const int lo = (int)(uint32_t)W;
-    const int H = (int)((uint32_t)(W >> 32) + (lo < 0 ? 1u : 0u));
-    R = (long long)lo + (long long)c_lo * 4294967296ll;
-    I = (long long)H - c_lo + (long long)c_hi * 4294967296ll;
 }
 
 #ifndef CSG_BRICK_WAVES
@@ -1160,6 +1149,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                             // the packed atomics of CARRY_GROUP corners, then one
                                             // look at their old words (see CarryScale)
                                             const float2 vs = make_float2(val.x * qs.S, val.y * qs.S);
+                                            // corner (ax, ayz): (wx vs) times (wy wz)
+                                            const float ur[2] = {wx[0] * vs.x, wx[1] * vs.x};
+                                            const float ui[2] = {wx[0] * vs.y, wx[1] * vs.y};
+                                            const float wyz[4] = {wy[0] * wz[0], wy[1] * wz[0], wy[0] * wz[1],
+                                                                  wy[1] * wz[1]};
 #pragma unroll
                                             for (int c0 = 0; c0 < 8; c0 += CARRY_GROUP) {
                                                 unsigned long long old[CARRY_GROUP];
@@ -1167,10 +1161,10 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                 for (int k = 0; k < CARRY_GROUP; ++k) {
                                                     const int c = c0 + k;
                                                     const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                                    const float w = wx[ax] * wy[ay] * wz[az];
                                                     const int li = lb + az * XP + ay * XR + ax;
-                                                    old[k] = atomicAdd(&acc_w[li], carry_pack((int)rintf(w * vs.x),
-                                                                                              (int)rintf(w * vs.y)));
+                                                    old[k] = atomicAdd(&acc_w[li],
+                                                                       carry_pack(round_half_up(ur[ax] * wyz[c >> 1]),
+                                                                                  round_half_up(ui[ax] * wyz[c >> 1])));
                                                 }
                                                 uint32_t f = 0u;
 #pragma unroll
@@ -1180,10 +1174,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                     for (int k = 0; k < CARRY_GROUP; ++k) {
                                                         const int c = c0 + k;
                                                         const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                                        const float w = wx[ax] * wy[ay] * wz[az];
                                                         const int li = lb + az * XP + ay * XR + ax;
-                                                        carry_fix(old[k], (int)rintf(w * vs.x), (int)rintf(w * vs.y),
-                                                                  c_lo + li, c_hi + li);
+                                                        carry_fix(old[k], round_half_up(ur[ax] * wyz[c >> 1]),
+                                                                  round_half_up(ui[ax] * wyz[c >> 1]), c_lo + li, c_hi + li);
                                                     }
                                                 }
                                             }

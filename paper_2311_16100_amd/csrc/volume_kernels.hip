@@ -237,11 +237,13 @@ __global__ __launch_bounds__(kBlock) void precond_step_kernel(int64_t nvox, cons
         if (Dhat_out) Dhat_out[k] = dh;
         if (!v_out) continue;  // the diagonal update alone
         const float2 gk = g[k], vk = v[k];
-        const float inv = 1.0f / dh;
+        // the hardware reciprocal (1 ulp); each voxel's terms of the two
+        // sums are formed in float (a few ulp) and summed in double
+        const float inv = __builtin_amdgcn_rcpf(dh);
         const float2 o = make_float2(vk.x - eta * gk.x * inv, vk.y - eta * gk.y * inv);
         v_out[k] = o;
-        s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh;
-        s1 += (double)o.x * o.x + (double)o.y * o.y;
+        s0 += (double)(fmaf(gk.x, gk.x, gk.y * gk.y) * inv);
+        s1 += (double)fmaf(o.x, o.x, o.y * o.y);
     }
     if (!v_out) return;
     const double t0 = block_sum(s0, red);
@@ -278,13 +280,12 @@ __global__ __launch_bounds__(kBlock) void precond_step2_kernel(int64_t npair, co
         if (Dhat_out) Dhat_out[k] = dh;
         if (!v_out) continue;  // the diagonal update alone
         const float4 gk = g[k], vk = v[k];
-        const float i0 = 1.0f / dh.x, i1 = 1.0f / dh.y;
+        const float i0 = __builtin_amdgcn_rcpf(dh.x), i1 = __builtin_amdgcn_rcpf(dh.y);
         const float4 o = make_float4(vk.x - eta * gk.x * i0, vk.y - eta * gk.y * i0, vk.z - eta * gk.z * i1,
                                      vk.w - eta * gk.w * i1);
         v_out[k] = o;
-        s0 += ((double)gk.x * gk.x + (double)gk.y * gk.y) / (double)dh.x +
-              ((double)gk.z * gk.z + (double)gk.w * gk.w) / (double)dh.y;
-        s1 += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
+        s0 += (double)(fmaf(gk.x, gk.x, gk.y * gk.y) * i0) + (double)(fmaf(gk.z, gk.z, gk.w * gk.w) * i1);
+        s1 += (double)fmaf(o.x, o.x, o.y * o.y) + (double)fmaf(o.z, o.z, o.w * o.w);
     }
     if (!v_out) return;
     const double t0 = block_sum(s0, red);
