@@ -187,7 +187,9 @@ int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, voi
  * from a worst-case bound (the probe entries are +-1): the estimate matches
  * the one formed with csg_hvp to about 1e-5 relative, far below its own
  * sampling noise.  The probes are regenerated from their hash wherever they
- * are read and never stored (on nearest-neighbour grids the pair is stored in
+ * are read and never stored, and on trilinear grids each voxel's z (.) H z is
+ * formed where the product is accumulated, so no volume of H z is stored
+ * either (on nearest-neighbour grids the pair and its product are stored in
  * the workspace).
  *   diag_out device float [M^3], overwritten.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_HUTCHINSON). */
@@ -297,8 +299,9 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
  *   CSG_WS_BACKPROJECT_DETERMINISTIC  csg_backproject, deterministic = 1
  *                                  (trilinear grids: adds the 64-bit
  *                                  fixed-point volume, 16 M^3 bytes)
- *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: one complex volume
- *                                  (nearest-neighbour grids: two)
+ *   CSG_WS_HUTCHINSON              csg_hutchinson_diag: the brick tables
+ *                                  (nearest-neighbour grids: two complex
+ *                                  volumes)
  *   CSG_WS_GRADIENT                csg_gradient / csg_hvp, deterministic = 0
  *   CSG_WS_GRADIENT_DETERMINISTIC  csg_gradient / csg_hvp, deterministic = 1
  *                                  (trilinear grids: the fixed-point volume;

@@ -131,10 +131,11 @@ size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
         case CSG_WS_BACKPROJECT_DETERMINISTIC: return trilinear ? fixed : 0;
         case CSG_WS_GRADIENT: return kScalarBytes + bricks;
         case CSG_WS_GRADIENT_DETERMINISTIC: return trilinear ? fixed : kScalarBytes + image_bytes(M, n);
-        // the product of a probe pair (the pair itself is regenerated from
-        // its hash where it is needed; the nearest-neighbour kernels read it
-        // from a second volume)
-        case CSG_WS_HUTCHINSON: return kScalarBytes + (trilinear ? vol + bricks : 2 * vol);
+        // trilinear: the brick tables (the probe pair is regenerated from its
+        // hash in the staged bricks and z (.) H z goes straight into the
+        // output); nearest neighbour: the product of a probe pair and the
+        // stored pair
+        case CSG_WS_HUTCHINSON: return kScalarBytes + (trilinear ? bricks : 2 * vol);
         default: return 0;
     }
 }
@@ -388,23 +389,35 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
     if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_hutchinson_diag"))) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t nv = nvox_of(g);
-    // hz, then the brick tables (trilinear) or the stored probe pair (nearest
-    // neighbour)
-    float2 *hz = (float2 *)((char *)workspace + kScalarBytes);
-    void *bws = hz + nv;
-    float2 *z = g.interp == 0 ? hz + nv : nullptr;
     const float w = 1.0f / (float)n_probe;
+    if (g.interp != 0) {
+        // Trilinear grids: z (.) H z summed over the probes in place.  The
+        // lambda term of every probe is lambda z (.) z = lambda, so the mean
+        // over the probes starts from lambda; each pair's brick kernel then
+        // adds w z (.) (scale P^T C^2 P z) with the pair regenerated from its
+        // hash in the staged bricks (the workspace holds the brick tables).
+        void *bws = (char *)workspace + kScalarBytes;
+        CSG_TRY(csg::launch_fill_f32(diag_out, nv, lambda, st), "csg_hutchinson_diag");
+        for (int32_t p = 0; p < n_probe && poses->n > 0; p += 2) {
+            const int has_b = (p + 1 < n_probe) ? 1 : 0;
+            CSG_TRY(csg::launch_brick_hvp_probe(g, poses->rot, poses->defocus_A, poses->n, seed,
+                                                (uint64_t)(probe0 + p), (uint64_t)(probe0 + p + 1), has_b, scale * w,
+                                                diag_out, bws, st),
+                    "csg_hutchinson_diag");
+        }
+        return CSG_OK;
+    }
+    // nearest neighbour: hz = H z of each pair in the workspace (beside the
+    // stored pair z), then z (.) hz
+    float2 *hz = (float2 *)((char *)workspace + kScalarBytes);
+    float2 *z = hz + nv;
     for (int32_t p = 0; p < n_probe; p += 2) {
         const int has_b = (p + 1 < n_probe) ? 1 : 0;
         const uint64_t pa = (uint64_t)(probe0 + p), pb = (uint64_t)(probe0 + p + 1);
         // hz = lambda z (and z itself for the nearest-neighbour kernels)
         CSG_TRY(csg::launch_probe_init(z, hz, nv, seed, pa, pb, has_b, lambda, st), "csg_hutchinson_diag");
-        if (poses->n > 0 && g.interp == 0)
+        if (poses->n > 0)
             CSG_TRY(csg::launch_brick_hvp(g, poses->rot, poses->defocus_A, poses->n, z, scale, hz, nullptr, st),
-                    "csg_hutchinson_diag");
-        else if (poses->n > 0)
-            CSG_TRY(csg::launch_brick_hvp_probe(g, poses->rot, poses->defocus_A, poses->n, seed, pa, pb, has_b, scale,
-                                                hz, bws, st),
                     "csg_hutchinson_diag");
         CSG_TRY(csg::launch_zhz_hash(diag_out, hz, nv, seed, pa, pb, has_b, w, /*first=*/p == 0, st),
                 "csg_hutchinson_diag");

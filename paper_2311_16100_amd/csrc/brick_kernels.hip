@@ -46,10 +46,12 @@
 //   kBBackproject  accum += scale C^p img
 //   kBGradient     r = C P v - x; loss (owner); accum += scale C r
 //   kBHvp          accum += scale C^2 P z
-//   kBHvpProbe     the same for a Rademacher probe pair z (Hutchinson),
-//                  generated from its hash while the brick is staged: both
-//                  components of a contribution go into one 64-bit integer LDS
-//                  atomic as fixed-point numbers (see PackedScale)
+//   kBHvpProbe     diag += z (.) scale C^2 P z for a Rademacher probe pair z
+//                  (Hutchinson), generated from its hash while the brick is
+//                  staged: both components of a contribution go into one
+//                  64-bit integer LDS atomic as fixed-point numbers (see
+//                  PackedScale), and the flush multiplies each voxel's sums by
+//                  the probe signs and adds one real number to the diagonal
 //   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
 //                  sum of every voxel (no image is read)
 //   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
@@ -869,11 +871,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                     continue;
                 }
                 if (PK_ALWAYS) {
+                    // the sums are (H z_a, H z_b) at this voxel; z (.) H z of
+                    // the pair, z_a (H z_a) + z_b (H z_b), goes straight into
+                    // the diagonal (signs from the staged masks)
                     float re, im;
                     pk.unpack(acc_pk[li], re, im);
                     acc_pk[li] = 0ull;  // cleared for the next chunk
-                    if (re != 0.f) atomicAdd(&a.accum[gi].x, re);
-                    if (im != 0.f) atomicAdd(&a.accum[gi].y, im);
+                    const int row = tz * BX + ty;
+                    float d = ((s_zmask[row][0] >> tx) & 1u) ? -re : re;
+                    if (a.probe_has_b) d += ((s_zmask[row][1] >> tx) & 1u) ? -im : im;
+                    if (d != 0.f) atomicAdd(a.accum_real + gi, d);
                     continue;
                 }
                 const float re = (float)acc_re[li];
@@ -1478,13 +1485,13 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
 }
 
 hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,
-                                  uint64_t pa, uint64_t pb, int has_b, float scale, float2 *accum, void *ws,
+                                  uint64_t pa, uint64_t pb, int has_b, float scale, float *diag, void *ws,
                                   hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return hipErrorInvalidValue;  // the pixel kernels read a stored probe
     const ProbePair pp{seed, pa, pb, has_b};
-    return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, nullptr, nullptr, nullptr, accum, nullptr, scale, 2,
-                                      ws, st, nullptr, nullptr, &pp);
+    return run_brick_mode<kBHvpProbe>(g, rot, defocus, nullptr, n, nullptr, nullptr, nullptr, nullptr, nullptr, scale, 2,
+                                      ws, st, diag, nullptr, &pp);
 }
 
 // Deterministic adjoint: input bounds and a zeroed fixed-point volume, the

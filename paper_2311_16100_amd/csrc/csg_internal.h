@@ -45,9 +45,11 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
                             float scale, float2 *accum, void *ws, hipStream_t st);
 // the same for the Rademacher probe pair (seed, pa, pb, has_b) of
 // launch_probe_init, generated while the bricks are staged; its entries are
-// 0 or +-1 per component, which allows the packed fixed-point accumulator
+// 0 or +-1 per component, which allows the packed fixed-point accumulator.
+// It adds z_a (.) (H z_a) + z_b (.) (H z_b) (H = scale P^T C^2 P, no lambda
+// term) to the real diag, with float atomics
 hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,
-                                  uint64_t pa, uint64_t pb, int has_b, float scale, float2 *accum, void *ws,
+                                  uint64_t pa, uint64_t pb, int has_b, float scale, float *diag, void *ws,
                                   hipStream_t st);
 // the deterministic adjoint (fixed point; trilinear grids): scratch of
 // 16 M^3 bytes (the 64-bit fixed-point volume, 16-byte aligned) and two words
