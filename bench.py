@@ -320,20 +320,32 @@ def cpu_baseline(vol, rot_all, df_all, M, n_img, scale_full, lam, alpha):
     """One Algorithm 1 iteration of the FP64 oracle (Hutchinson arm, 2
     probes) on n_img images of the same workload, single-threaded."""
     import oracle
+    from threadpoolctl import threadpool_limits
     grid, opt = oracle.Grid(M), oracle.Optics()
     P = oracle.Poses(rot_all[:n_img], df_all[:n_img])
     v_true = vol.astype(np.complex128)
-    t0 = time.perf_counter()
-    x = oracle.project(grid, opt, P, v_true)
-    st = oracle.Alg1State(v=np.zeros(M ** 3, np.complex128), D=np.ones(M ** 3), D_avg=np.zeros(M ** 3), eta=1.0)
-    t1 = time.perf_counter()
-    zHz = oracle.hutchinson_diag(grid, opt, P, 2, 4, scale_full, lam).reshape(-1)
-    oracle.alg1_iteration(grid, opt, P, x, st, scale_full, lam, alpha, 0.9, 0.1, zHz=zHz)
-    t2 = time.perf_counter()
-    del t0
+    with threadpool_limits(limits=1):  # numpy's BLAS and OpenMP pools held to one thread
+        x = oracle.project(grid, opt, P, v_true)
+        st = oracle.Alg1State(v=np.zeros(M ** 3, np.complex128), D=np.ones(M ** 3), D_avg=np.zeros(M ** 3), eta=1.0)
+        t1 = time.perf_counter()
+        zHz = oracle.hutchinson_diag(grid, opt, P, 2, 4, scale_full, lam).reshape(-1)
+        oracle.alg1_iteration(grid, opt, P, x, st, scale_full, lam, alpha, 0.9, 0.1, zHz=zHz)
+        t2 = time.perf_counter()
     return {"value": round(n_img / (t2 - t1), 3), "unit": "images/s", "cores": 1, "kind": "oracle",
             "sample": "one Algorithm 1 iteration (2 probes) on %d images of the %d^3 workload, FP64 C + numpy, "
-                      "single thread; %.1f s" % (n_img, M, t2 - t1)}
+                      "single thread of %s (%d logical CPUs visible); %.1f s"
+                      % (n_img, M, cpu_model(), os.cpu_count() or 0, t2 - t1)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 if __name__ == "__main__":
