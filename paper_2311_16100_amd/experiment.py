@@ -82,7 +82,7 @@ class Dataset:
                       self.v_true)
         if self.sigma2 > 0:
             from synth import gpu_noise
-            ii = torch.arange(self.N, device=self.device)[idx] if isinstance(idx, slice) else idx
+            ii = torch.arange(*idx.indices(self.N), device=self.device) if isinstance(idx, slice) else idx
             gpu_noise.add_disk_noise(y, ii.to(torch.int64), int(math.floor(self.grid.rmax ** 2)), self.sigma2,
                                      gpu_noise.noise_seed(self.seed, synth.STREAM_NOISE))
         return y
