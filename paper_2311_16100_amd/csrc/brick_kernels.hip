@@ -86,6 +86,9 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #ifndef CSG_RUN_ADJ
 #define CSG_RUN_ADJ 2
 #endif
+#ifndef CSG_RUN_GRAD
+#define CSG_RUN_GRAD 1
+#endif
 #ifndef CSG_WI_ADJ
 #define CSG_WI_ADJ 32
 #endif
@@ -394,9 +397,11 @@ constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument a
 // and runs per pass of the run -> row table.
 template <int MODE>
 struct Win {
-    // consecutive pixels of a row per lane: one for the forward mode, two
-    // for the adjoint modes (measured fastest)
-    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : CSG_RUN_ADJ;
+    // consecutive pixels of a row per lane: one for the forward mode and the
+    // gradient (whose packed accumulator waits on its atomics' old words,
+    // which leaves no registers for a second pixel's state), two for the
+    // other adjoint modes (measured fastest)
+    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : MODE == kBGradient ? CSG_RUN_GRAD : CSG_RUN_ADJ;
     static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
