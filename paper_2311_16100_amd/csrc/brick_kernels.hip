@@ -101,8 +101,17 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #ifndef CSG_WI_FWD
 #define CSG_WI_FWD 64
 #endif
+// run-table entries of the gradient and HVP modes: as many as fit beside
+// their other LDS at two blocks per CU (80 KB); the gradient with in-plane
+// shifts keeps two image constants more per image and takes 384 fewer
 #ifndef CSG_RUNCAP_GH
-#define CSG_RUNCAP_GH 2048
+#define CSG_RUNCAP_GH 3584
+#endif
+#ifndef CSG_RUNCAP_ADJ
+#define CSG_RUNCAP_ADJ 2048
+#endif
+#ifndef CSG_RUNCAP_SHIFT_CUT
+#define CSG_RUNCAP_SHIFT_CUT 384
 #endif
 #ifndef CSG_BRICK_WAVES_GH
 #define CSG_BRICK_WAVES_GH 4
@@ -405,7 +414,7 @@ struct Win {
     static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
-    static constexpr int RUNCAP = MODE == kBProject ? 7168 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : 2048;
+    static constexpr int RUNCAP = MODE == kBProject ? 7168 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : CSG_RUNCAP_ADJ;
 };
 
 __device__ __forceinline__ double rint_scaled(float e) {
@@ -617,7 +626,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // probe HVP: signs of the staged rows ([row][probe]; see the staging)
     __shared__ uint32_t s_zmask[MODE == kBHvpProbe ? BX * BX : 1][2];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
-    constexpr int RUNCAP = Win<MODE>::RUNCAP, RUN = Win<MODE>::RUN;
+    constexpr int RUNCAP = Win<MODE>::RUNCAP - (SHIFTED && MODE == kBGradient ? CSG_RUNCAP_SHIFT_CUT : 0);
+    constexpr int RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
     // the item's images: index (as int bits), rows 0 and 1 of R, defocus,
     // in-plane shift
