@@ -102,13 +102,18 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #define CSG_WI_FWD 64
 #endif
 // run-table entries of the gradient and HVP modes: as many as fit beside
-// their other LDS at two blocks per CU (80 KB); the gradient with in-plane
+// their other LDS at two blocks per CU (80 KB).  The fast modes' carry
+// accumulator needs half the counter space of the two-word accumulator of
+// the deterministic modes and takes 4352 more; the gradient with in-plane
 // shifts keeps two image constants more per image and takes 384 fewer
 #ifndef CSG_RUNCAP_GH
 #define CSG_RUNCAP_GH 3584
 #endif
 #ifndef CSG_RUNCAP_ADJ
 #define CSG_RUNCAP_ADJ 2048
+#endif
+#ifndef CSG_RUNCAP_CARRY_EXTRA
+#define CSG_RUNCAP_CARRY_EXTRA 4352
 #endif
 #ifndef CSG_RUNCAP_SHIFT_CUT
 #define CSG_RUNCAP_SHIFT_CUT 384
@@ -556,11 +561,10 @@ struct CarryScale {
 constexpr int CARRY_GROUP = CSG_CARRY_GROUP;
 
 // the lane's wraps go to the voxel's counters
-__device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi, int *c_lo, int *c_hi) {
+__device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi, int *counters) {
     int dl, dh;
     carry_wraps(old, qr, qi, dl, dh);
-    if (dl) atomicAdd(c_lo, dl);
-    if (dh) atomicAdd(c_hi, dh);
+    if (dl | dh) atomicAdd(counters, carry_counter_step(dl, dh));
 }
 
 #ifndef CSG_BRICK_WAVES
@@ -610,7 +614,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     constexpr bool XRETRY = QITEM && READS_IMG;
     __shared__ float2 vh[GATHER ? XN : 1];
     __shared__ double acc_re[SCATTER ? XN : 1];
-    __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN : 1];
+    // (the carry accumulator keeps one 32-bit counter word per voxel here)
+    constexpr int XN_IM = QCARRY ? (XN + 1) / 2 : XN;
+    __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN_IM : 1];
     // the packed accumulator shares the storage of acc_re
     unsigned long long *const acc_pk = reinterpret_cast<unsigned long long *>(acc_re);
     // so do the fixed-point accumulators of the deterministic mode (zero bits
@@ -619,14 +625,14 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
     // and the carry accumulator: its words in acc_re, its counters in acc_im
     unsigned long long *const acc_w = reinterpret_cast<unsigned long long *>(acc_re);
-    int *const c_lo = reinterpret_cast<int *>(acc_im);
-    int *const c_hi = c_lo + XN;
+    int *const c_word = reinterpret_cast<int *>(acc_im);
     __shared__ unsigned s_wmax[kBT / 64];
     __shared__ unsigned s_xmax[kBT / 64];
     // probe HVP: signs of the staged rows ([row][probe]; see the staging)
     __shared__ uint32_t s_zmask[MODE == kBHvpProbe ? BX * BX : 1][2];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
-    constexpr int RUNCAP = Win<MODE>::RUNCAP - (SHIFTED && MODE == kBGradient ? CSG_RUNCAP_SHIFT_CUT : 0);
+    constexpr int RUNCAP = Win<MODE>::RUNCAP + (QCARRY ? CSG_RUNCAP_CARRY_EXTRA : 0) -
+                           (SHIFTED && MODE == kBGradient ? CSG_RUNCAP_SHIFT_CUT : 0);
     constexpr int RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
     // the item's images: index (as int bits), rows 0 and 1 of R, defocus,
@@ -809,7 +815,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
         } else if (SCATTER) {
             for (int t = threadIdx.x; t < XN; t += kBT) {
                 acc_re[t] = 0.0;
-                acc_im[t] = 0.0;
+                if (t < XN_IM) acc_im[t] = 0.0;
             }
         }
         PackedScale pk;  // set in the first window (after a barrier)
@@ -858,7 +864,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 }
                 if (QCARRY) {
                     long long R, I;
-                    carry_decode(acc_w[li], c_lo[li], c_hi[li], R, I);
+                    int c_lo, c_hi;
+                    carry_counters(c_word[li], c_lo, c_hi);
+                    carry_decode(acc_w[li], c_lo, c_hi, R, I);
                     if (!qs.ok) {
                         atomicAdd(&a.accum[gi].x, __builtin_nanf(""));
                         atomicAdd(&a.accum[gi].y, __builtin_nanf(""));
@@ -1198,7 +1206,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                         const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                                                         const int li = lb + az * XP + ay * XR + ax;
                                                         carry_fix(old[k], round_half_up(ur[ax] * wyz[c >> 1]),
-                                                                  round_half_up(ui[ax] * wyz[c >> 1]), c_lo + li, c_hi + li);
+                                                                  round_half_up(ui[ax] * wyz[c >> 1]), c_word + li);
                                                     }
                                                 }
                                             }
@@ -1267,7 +1275,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 lsum = 0.0;
                 for (int t = threadIdx.x; t < XN; t += kBT) {
                     acc_re[t] = 0.0;
-                    acc_im[t] = 0.0;
+                    if (t < XN_IM) acc_im[t] = 0.0;
                 }
             }
         }  // attempts

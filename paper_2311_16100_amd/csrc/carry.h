@@ -43,6 +43,18 @@ CSG_HD void carry_wraps(unsigned long long old, int qr, int qi, int &dl, int &dh
     dh = h_new > 0x7fffffffll ? 1 : (h_new < -0x80000000ll ? -1 : 0);
 }
 
+// The two counters of a voxel share one 32-bit word, c_lo + 2^16 c_hi: both
+// stay below 2^15 in magnitude (a wrap needs 2^32 of sum, an addend is below
+// 2^30, and a voxel receives at most 16 pixels of each of at most 1024
+// images per work item, so at most 2^12 + 1 wraps), and the word's low half
+// read as a signed 16-bit number is c_lo.
+CSG_HD int carry_counter_step(int dl, int dh) { return dl + dh * 65536; }
+
+CSG_HD void carry_counters(int w, int &c_lo, int &c_hi) {
+    c_lo = (int)(short)(w & 0xFFFF);
+    c_hi = (w - c_lo) >> 16;
+}
+
 // the exact sums of a word and its counters
 CSG_HD void carry_decode(unsigned long long W, int c_lo, int c_hi, long long &R, long long &I) {
     const int lo = (int)(uint32_t)W;

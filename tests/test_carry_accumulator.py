@@ -35,6 +35,21 @@ void accumulate(const int *qr, const int *qi, long long n, long long *R, long lo
     carry_decode(W, c_lo, c_hi, *R, *I);
     *wraps = nw;
 }
+// the same with the two counters in one word, as the kernel keeps them
+void accumulate_packed(const int *qr, const int *qi, long long n, long long *R, long long *I) {
+    unsigned long long W = 0;
+    int cw = 0;
+    for (long long k = 0; k < n; ++k) {
+        const unsigned long long old = W;
+        W += carry_pack(qr[k], qi[k]);
+        int dl, dh;
+        carry_wraps(old, qr[k], qi[k], dl, dh);
+        if (dl | dh) cw += carry_counter_step(dl, dh);
+    }
+    int c_lo, c_hi;
+    carry_counters(cw, c_lo, c_hi);
+    carry_decode(W, c_lo, c_hi, *R, *I);
+}
 unsigned may_wrap(unsigned long long old) { return carry_may_wrap(old); }
 void wraps(unsigned long long old, int qr, int qi, int *dl, int *dh) { carry_wraps(old, qr, qi, *dl, *dh); }
 }
@@ -52,6 +67,8 @@ def lib(tmp_path_factory):
     P = ctypes.POINTER
     L.accumulate.argtypes = [P(ctypes.c_int), P(ctypes.c_int), ctypes.c_longlong, P(ctypes.c_longlong),
                              P(ctypes.c_longlong), P(ctypes.c_int)]
+    L.accumulate_packed.argtypes = [P(ctypes.c_int), P(ctypes.c_int), ctypes.c_longlong, P(ctypes.c_longlong),
+                                    P(ctypes.c_longlong)]
     L.may_wrap.argtypes = [ctypes.c_ulonglong]
     L.may_wrap.restype = ctypes.c_uint
     L.wraps.argtypes = [ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
@@ -95,6 +112,25 @@ def test_many_wraps_in_both_directions(lib):
     alt = np.tile([LIM, -LIM + 3], 50_000)
     R, I, _ = run(lib, alt, alt[::-1].copy())
     assert (R, I) == (int(alt.sum()), int(alt[::-1].sum()))
+
+
+def test_counters_in_one_word(lib):
+    """The kernel keeps both wrap counters in one 32-bit word; within the
+    bound of one work item (16 pixels of each of 1024 images reach a voxel:
+    16384 addends below 2^30, so at most 2^12 + 1 wraps of each half) the
+    sums stay exact, in particular at that bound with addends of one sign."""
+    rng = np.random.default_rng(7)
+    cases = [(np.full(16384, LIM), np.full(16384, -LIM)), (np.full(16384, -LIM), np.full(16384, LIM))]
+    for _ in range(60):
+        n = int(rng.integers(1, 16385))
+        cases.append((rng.integers(-LIM, LIM + 1, n) * rng.choice([-1, 1]), np.abs(rng.integers(-LIM, LIM + 1, n))))
+    R, I = ctypes.c_longlong(), ctypes.c_longlong()
+    for qr, qi in cases:
+        qr = np.ascontiguousarray(qr, dtype=np.int32)
+        qi = np.ascontiguousarray(qi, dtype=np.int32)
+        lib.accumulate_packed(qr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              qi.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(qr), ctypes.byref(R), ctypes.byref(I))
+        assert (R.value, I.value) == (int(qr.astype(np.int64).sum()), int(qi.astype(np.int64).sum()))
 
 
 def _steps_to(total, last):
