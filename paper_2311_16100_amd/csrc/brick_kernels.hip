@@ -527,11 +527,12 @@ struct ItemScale {
 // lo and of H.  The atomic returns the word it added to; from that old value
 // the lane that made a half wrap sees it happen (the exact test runs only
 // when an old half lies outside [-2^30, 2^30), where a 30-bit addend can
-// wrap it) and adds +-1 to the counter.  Every addition is exact, so the
-// sums are exact 64-bit integers (as with one 64-bit word per component)
-// while each contribution costs one LDS atomic instead of two; each
-// contribution is rounded by at most 2^-30 |val|max, and the flush converts
-// each sum to float once.
+// wrap it) and adds +-1 to the counter (both counters of a voxel share one
+// 32-bit word, see carry.h).  Every addition is exact, so the sums are exact
+// 64-bit integers (as with one 64-bit word per component) while each
+// contribution costs one LDS atomic instead of two; each contribution is
+// rounded by at most half a step 2^-e <= 2^-28 V, V the item's bound, and
+// the flush converts each sum to float once.
 struct CarryScale {
     float S = 1.f;
     double invS = 1.0;
