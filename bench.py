@@ -108,6 +108,7 @@ def main():
     v0 = torch.zeros_like(v_true)
     cfg = Alg1Config(deterministic=args.deterministic)
     run = Alg1Runner(grid, optics, "hutchinson", scale, lam, alpha, cfg, v0, batch=Bsz)
+    run_fused = run.fused  # gradient and probe product in one kernel (fast mode)
 
     # per-call event timing inside the step
     calls = {}
@@ -139,7 +140,8 @@ def main():
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
     B.timing_enable(False)
-    kern = {k: B.timing_read(k) for k in ("gradient", "hvp", "project")}
+    kern = {k: B.timing_read(k) for k in ("gradient_probe", "gradient", "hvp", "project")}
+    kern = {k: v for k, v in kern.items() if v[1] > 0}
     ms_per_step = 1e3 * t_steps / args.steps
     print("[bench] %d Alg.1 steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
 
@@ -148,12 +150,19 @@ def main():
         st = run.state
         g_, o_ = grid, optics
         st.k += 1
-        timed("hutchinson_probe", lambda: B.hutchinson_diag(g_, o_, rot_b, df_b, cfg.n_probe, cfg.probe_seed, scale,
-                                                            lam, probe0=(st.k - 1) * cfg.n_probe,
-                                                            diag_out=run.zHz, workspace=run.ws_hutch))
-        timed("gradient", lambda: B.gradient(g_, o_, rot_b, df_b, st.v, x_b, scale, lam, grad_out=run.g,
-                                             loss_out=run.sc[0:1], deterministic=cfg.deterministic,
-                                             workspace=run.ws_grad))
+        if run.fused:
+            timed("gradient_probe", lambda: B.gradient_hutchinson(g_, o_, rot_b, df_b, st.v, x_b, scale, lam,
+                                                                  cfg.n_probe, cfg.probe_seed,
+                                                                  probe0=(st.k - 1) * cfg.n_probe, grad_out=run.g,
+                                                                  loss_out=run.sc[0:1], diag_out=run.zHz,
+                                                                  workspace=run.ws_grad))
+        else:
+            timed("hutchinson_probe", lambda: B.hutchinson_diag(g_, o_, rot_b, df_b, cfg.n_probe, cfg.probe_seed,
+                                                                scale, lam, probe0=(st.k - 1) * cfg.n_probe,
+                                                                diag_out=run.zHz, workspace=run.ws_hutch))
+            timed("gradient", lambda: B.gradient(g_, o_, rot_b, df_b, st.v, x_b, scale, lam, grad_out=run.g,
+                                                 loss_out=run.sc[0:1], deterministic=cfg.deterministic,
+                                                 workspace=run.ws_grad))
         timed("precond_step", lambda: B.precond_sgd_step(st.v, run.g, st.D, st.D_avg, run.zHz, st.k, cfg.beta,
                                                          alpha, st.eta, v_out=run.v_new, stats_out=run.sc[1:3]))
         timed("armijo_project", lambda: B.project(g_, o_, rot_b, df_b, run.v_new, subtract=x_b, out=None,
@@ -181,6 +190,7 @@ def main():
     model = {
         "gradient": 8 * P + 24 * U,
         "hutchinson_probe": 24 * U * math.ceil(cfg.n_probe / 2),
+        "gradient_probe": 8 * P + 24 * U + 24 * U,
         "armijo_project": 8 * P + 8 * U,
         "project": 8 * M * M + 8 * U,
         "backproject": 8 * P + 16 * U,
@@ -191,6 +201,9 @@ def main():
     per_image = {
         "gradient": 8 * P + 24 * U,  # image read, gather, read-modify-write
         "hvp": 24 * U,  # gather of the packed probe pair, read-modify-write
+        # both: the gradient's bytes and the probe product's (its gather and
+        # read-modify-write; the two operators act on different volumes)
+        "gradient_probe": 8 * P + 24 * U + 24 * U,
         "project": 8 * P + 8 * U,  # Armijo forward: image read, gather (loss only)
     }
     dominant = max(kern, key=lambda k: kern[k][0])
@@ -209,7 +222,10 @@ def main():
     # read-modify-write of the packed accumulator for the probe product; one
     # volume read for the loss-only forward)
     nvox = M ** 3
-    compulsory = {"gradient": 8 * P * Bsz + 24 * nvox, "hvp": 16 * nvox, "project": 8 * P * Bsz + 8 * nvox}
+    compulsory = {"gradient": 8 * P * Bsz + 24 * nvox, "hvp": 16 * nvox, "project": 8 * P * Bsz + 8 * nvox,
+                  # the gradient's, plus one read-modify-write of the real
+                  # diagonal (the probe pair is generated, not read)
+                  "gradient_probe": 8 * P * Bsz + 24 * nvox + 8 * nvox}
     cb = compulsory[dominant]
     roofline["compulsory"] = {"bytes_per_launch": cb,
                               "frac": round(cb / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -228,6 +244,8 @@ def main():
     # the same bytes over the whole entry point's event-timed duration (for
     # the gradient: the volume copy lam v, cull, plan and the kernel)
     if dominant in ms:
+        # (the fused kernel's call is csg_gradient_hutchinson: the lambda v
+        # copy, the lambda fill of the diagonal, cull, plan and the kernel)
         roofline["call_ms"] = round(ms[dominant], 4)
         roofline["call_frac"] = round(per_image[dominant] * Bsz / (ms[dominant] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     tr = traffic_record(dominant, Bsz, M, args.deterministic)
@@ -265,10 +283,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hires_256: Algorithm 1 iteration (Hutchinson arm, 2 probes) per batch of "
+        "config": {"workload": "hires_256: Algorithm 1 iteration (Hutchinson arm, 2 probes%s) per batch of "
                                "%d images of %dx%d (%d distinct resident batches in turn), %d^3 complex64 volume of %d "
                                "Gaussian blobs, N=%d, trilinear, CTF 300kV/Cs2.7/A0.1, defocus 1-3um"
-                               % (Bsz, M, M, nb, M, W.n_blobs, N),
+                               % (", gradient and probe product in one kernel" if run_fused else "", Bsz, M, M, nb,
+                                  M, W.n_blobs, N),
                    "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic)},
         "fwd_adj_images_per_s": round(fwd_adj, 1),
         "fwd_adj_roofline": fwd_adj_roofline,

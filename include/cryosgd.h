@@ -197,6 +197,25 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
                         int32_t n_probe, uint64_t seed, int64_t probe0, float scale, float lambda,
                         float *diag_out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* The two minibatch quantities of one iteration of Algorithm 1 (Sec. 3.4) on
+ * the same batch: the gradient and loss of csg_gradient (deterministic = 0)
+ * and the Hutchinson diagonal of csg_hutchinson_diag.  The Hessian does not
+ * depend on v (eq. (hessian)), so the probe product and the gradient visit
+ * the same pixels with the same sample points, CTF values and weights; on
+ * trilinear grids without in-plane shifts one brick kernel computes the
+ * gradient and the first probe pair's product in one pass over the pixels
+ * (further pairs, nearest-neighbour grids and shifted poses take the two
+ * separate paths).  Results equal those of the two calls up to the order of
+ * float additions.
+ *   Arguments as in csg_gradient and csg_hutchinson_diag; grad_out and
+ *   diag_out must not alias vol or each other.
+ *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_GRADIENT_HUTCHINSON). */
+int csg_gradient_hutchinson(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,
+                            const float *vol, const float *x, float scale, float lambda,
+                            float *grad_out, double *loss_out, int32_t n_probe, uint64_t seed,
+                            int64_t probe0, float *diag_out, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
 /* Exact diagonal of the minibatch Hessian: diag_out = scale * sum_ij C_ij^2
  * w_ijk^2 + lambda (squared interpolation weights; eq. (hessian) with eq.
  * (def tri interp)).  diag_out device float [M^3], overwritten; workspace as for
@@ -307,6 +326,8 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
  *                                  (trilinear grids: the fixed-point volume;
  *                                  nearest neighbour: one complex image per
  *                                  batch image)
+ *   CSG_WS_GRADIENT_HUTCHINSON     csg_gradient_hutchinson: the larger of
+ *                                  CSG_WS_GRADIENT and CSG_WS_HUTCHINSON
  * Workspaces must be 256-byte aligned.  Returns 0 for an invalid grid. */
 #define CSG_WS_BACKPROJECT 0
 #define CSG_WS_HUTCHINSON 1
@@ -314,6 +335,7 @@ int csg_learned_diag(const csg_grid *grid, int64_t n_images, float lambda, const
 #define CSG_WS_GRADIENT_DETERMINISTIC 3
 #define CSG_WS_PROJECT 4
 #define CSG_WS_BACKPROJECT_DETERMINISTIC 5
+#define CSG_WS_GRADIENT_HUTCHINSON 6
 size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which);
 
 /* Per-shell sums of two volumes over the Fourier shells round(|k|) = s,
@@ -346,6 +368,8 @@ int csg_shell_sums(const csg_grid *grid, const float *u, const float *v, double 
  *                                  csg_hutchinson_diag)
  *           CSG_KERNEL_FEATURES    csg_feature_sums
  *           CSG_KERNEL_SQ_DIAG     csg_exact_diag
+ *           CSG_KERNEL_GRADIENT_PROBE  gradient with the first probe pair
+ *                                  (csg_gradient_hutchinson)
  * ------------------------------------------------------------------------ */
 #define CSG_KERNEL_PROJECT 0
 #define CSG_KERNEL_BACKPROJECT 1
@@ -353,6 +377,7 @@ int csg_shell_sums(const csg_grid *grid, const float *u, const float *v, double 
 #define CSG_KERNEL_HVP 3
 #define CSG_KERNEL_FEATURES 4
 #define CSG_KERNEL_SQ_DIAG 5
+#define CSG_KERNEL_GRADIENT_PROBE 6
 int csg_timing_enable(int32_t on);
 int csg_timing_read(int32_t kernel, double *total_ms, int64_t *launches);
 

@@ -26,6 +26,7 @@ CSG_WS_GRADIENT = 2
 CSG_WS_GRADIENT_DETERMINISTIC = 3
 CSG_WS_PROJECT = 4
 CSG_WS_BACKPROJECT_DETERMINISTIC = 5
+CSG_WS_GRADIENT_HUTCHINSON = 6
 
 
 class CsgError(RuntimeError):
@@ -60,6 +61,10 @@ EXPORTS = {
     "csg_hutchinson_diag": [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_float,
                                                     ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_size_t, ctypes.c_void_p],
+    "csg_gradient_hutchinson": [ctypes.c_void_p] * 5 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                        ctypes.c_size_t, ctypes.c_void_p],
     "csg_exact_diag": [ctypes.c_void_p] * 3 + [ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_size_t, ctypes.c_void_p],
     "csg_features": [ctypes.c_void_p] * 5 + [ctypes.c_void_p],
@@ -311,6 +316,32 @@ def hutchinson_diag(grid: Grid, optics: Optics, rot, defocus, n_probe: int, seed
     return diag_out
 
 
+def gradient_hutchinson(grid: Grid, optics: Optics, rot, defocus, vol, x, scale: float, lam: float, n_probe: int,
+                        seed: int, probe0: int = 0, grad_out=None, loss_out=None, diag_out=None, workspace=None,
+                        stream=None, shift=None):
+    """gradient(...) and hutchinson_diag(...) of one batch in one call
+    (csg_gradient_hutchinson); returns (grad_out, diag_out)."""
+    M = grid.M
+    p = _poses(rot, defocus, shift)
+    if grad_out is None:
+        grad_out = torch.empty((M, M, M), dtype=torch.complex64, device=vol.device)
+    if diag_out is None:
+        diag_out = torch.empty((M, M, M), dtype=torch.float32, device=vol.device)
+    if diag_out.dtype != torch.float32 or diag_out.numel() != M ** 3:
+        raise CsgError("diag_out must be float32 with M^3 = %d elements" % M ** 3)
+    if workspace is None:
+        workspace = alloc_workspace(grid, p.n, CSG_WS_GRADIENT_HUTCHINSON, vol.device)
+    g, o = grid.c(), optics.c()
+    wp, wn = _ws(workspace)
+    _check(lib().csg_gradient_hutchinson(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
+                                         _cplx(vol, (M, M, M), "vol"), _cplx(x, (p.n, M, M), "x"), float(scale),
+                                         float(lam), _cplx(grad_out, (M, M, M), "grad_out"),
+                                         None if loss_out is None else _ptr(loss_out), int(n_probe), int(seed),
+                                         int(probe0), _ptr(diag_out), wp, wn, _stream(stream)),
+           "csg_gradient_hutchinson")
+    return grad_out, diag_out
+
+
 def exact_diag(grid: Grid, optics: Optics, rot, defocus, scale: float, lam: float, diag_out=None, workspace=None,
                stream=None):
     M = grid.M
@@ -473,7 +504,8 @@ def fsc(grid: Grid, u, v):
     return torch.where(den > 0, s[0] / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
 
 
-KERNELS = {"project": 0, "backproject": 1, "gradient": 2, "hvp": 3, "features": 4, "sq_diag": 5}
+KERNELS = {"project": 0, "backproject": 1, "gradient": 2, "hvp": 3, "features": 4, "sq_diag": 5,
+           "gradient_probe": 6}
 
 
 def timing_enable(on: bool = True):

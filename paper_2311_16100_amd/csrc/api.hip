@@ -136,6 +136,7 @@ size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
         // output); nearest neighbour: the product of a probe pair and the
         // stored pair
         case CSG_WS_HUTCHINSON: return kScalarBytes + (trilinear ? bricks : 2 * vol);
+        case CSG_WS_GRADIENT_HUTCHINSON: return kScalarBytes + (trilinear ? bricks : 2 * vol);
         default: return 0;
     }
 }
@@ -422,6 +423,55 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
         CSG_TRY(csg::launch_zhz_hash(diag_out, hz, nv, seed, pa, pb, has_b, w, /*first=*/p == 0, st),
                 "csg_hutchinson_diag");
     }
+    return CSG_OK;
+}
+
+int csg_gradient_hutchinson(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses, const float *vol,
+                            const float *x, float scale, float lambda, float *grad_out, double *loss_out,
+                            int32_t n_probe, uint64_t seed, int64_t probe0, float *diag_out, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+    csg::Geom g;
+    int rc = make_geom(grid, optics, &g);
+    if (rc) return rc;
+    if ((rc = check_poses(poses))) return rc;
+    if (n_probe < 1) return fail(CSG_EINVAL, "csg_gradient_hutchinson: n_probe=%d must be >= 1", n_probe);
+    if (!vol || !grad_out || !diag_out || (poses->n > 0 && !x))
+        return fail(CSG_EINVAL, "csg_gradient_hutchinson: vol, x, grad_out and diag_out must be non-NULL");
+    if (vol == grad_out || (const void *)vol == (const void *)diag_out || (void *)grad_out == (void *)diag_out)
+        return fail(CSG_EINVAL, "csg_gradient_hutchinson: vol, grad_out and diag_out must not alias");
+    const size_t need = csg_workspace_bytes(grid, poses->n, CSG_WS_GRADIENT_HUTCHINSON);
+    if ((rc = need_workspace(workspace, workspace_bytes, need, "csg_gradient_hutchinson"))) return rc;
+    if (g.interp == 0 || poses->shift_px || poses->n == 0) {
+        // the two separate paths (their workspaces are no larger than this one)
+        rc = csg_gradient(grid, optics, poses, vol, x, scale, lambda, grad_out, loss_out, 0, workspace,
+                          workspace_bytes, stream);
+        if (rc) return rc;
+        return csg_hutchinson_diag(grid, optics, poses, n_probe, seed, probe0, scale, lambda, diag_out, workspace,
+                                   workspace_bytes, stream);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    double *sc = (double *)workspace;  // sc[0] = 1/2 sum |r|^2, sc[1] = ||v||^2
+    void *bws = (char *)workspace + kScalarBytes;
+    const int64_t nv = nvox_of(g);
+    const float w = 1.0f / (float)n_probe;
+    CSG_TRY(csg::launch_fill_f64(sc, 2, 0.0, st), "csg_gradient_hutchinson");
+    CSG_TRY(csg::launch_scaled_copy((float2 *)grad_out, (const float2 *)vol, lambda, nv, sc + 1, st),
+            "csg_gradient_hutchinson");
+    // the lambda term of every probe is lambda z (.) z = lambda (as in csg_hutchinson_diag)
+    CSG_TRY(csg::launch_fill_f32(diag_out, nv, lambda, st), "csg_gradient_hutchinson");
+    CSG_TRY(csg::launch_brick_gradient_probe(g, poses->rot, poses->defocus_A, poses->n, (const float2 *)vol,
+                                             (const float2 *)x, scale, (float2 *)grad_out, sc, seed,
+                                             (uint64_t)probe0, (uint64_t)(probe0 + 1), n_probe > 1 ? 1 : 0,
+                                             scale * w, diag_out, bws, st),
+            "csg_gradient_hutchinson");
+    for (int32_t p = 2; p < n_probe; p += 2) {
+        const int has_b = (p + 1 < n_probe) ? 1 : 0;
+        CSG_TRY(csg::launch_brick_hvp_probe(g, poses->rot, poses->defocus_A, poses->n, seed, (uint64_t)(probe0 + p),
+                                            (uint64_t)(probe0 + p + 1), has_b, scale * w, diag_out, bws, st),
+                "csg_gradient_hutchinson");
+    }
+    if (loss_out)
+        CSG_TRY(csg::launch_finish_loss(loss_out, sc, sc + 1, scale, lambda, st), "csg_gradient_hutchinson");
     return CSG_OK;
 }
 

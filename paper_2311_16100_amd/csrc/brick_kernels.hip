@@ -56,6 +56,13 @@
 //                  sum of every voxel (no image is read)
 //   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
 //                  Hessian (real accumulator; no image is read)
+//   kBGradProbe    kBGradient and kBHvpProbe of the same images in one pass
+//                  (the Hessian does not depend on v, so both visit the same
+//                  pixels with the same cells, weights and CTF values): the
+//                  probe pair is staged as halves beside the volume, and each
+//                  contribution to z (.) H z is multiplied by the receiving
+//                  voxel's probe signs at once, so its accumulator holds one
+//                  32-bit fixed-point number per voxel (no in-plane shifts)
 #include <type_traits>
 
 #include "carry.h"
@@ -121,18 +128,27 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #ifndef CSG_BRICK_WAVES_GH
 #define CSG_BRICK_WAVES_GH 4
 #endif
+// the fused gradient and probe mode: images per window and run-table
+// entries (as many as fit beside its two accumulators at two blocks per CU)
+#ifndef CSG_WI_GP
+#define CSG_WI_GP 32
+#endif
+#ifndef CSG_RUNCAP_GP
+#define CSG_RUNCAP_GP 3584
+#endif
 constexpr int CHUNK_ADJ = CSG_CHUNK_ADJ;  // images per work item of the adjoint modes
 constexpr int CHUNK_FWD = CSG_CHUNK_FWD;  // images per work item of the forward mode (no flush)
 constexpr float kClipEps = 1e-2f;
 
 enum BrickMode { kBProject = 0, kBBackproject = 1, kBGradient = 2, kBHvp = 3, kBFeatures = 4, kBSqDiag = 5,
-                 kBHvpProbe = 6 };
+                 kBHvpProbe = 6, kBGradProbe = 7 };
 constexpr bool is_hvp(int mode) { return mode == kBHvp || mode == kBHvpProbe; }
+constexpr bool is_grad(int mode) { return mode == kBGradient || mode == kBGradProbe; }
 // the most chunks of a brick's images per work item (staged and flushed once
 // for all of them): eight for the gradient and HVP modes (two blocks per CU),
 // two for the modes with three blocks per CU (measured: a whole brick per
 // item leaves those with a long tail); the plan lowers it for small batches
-constexpr int max_chunks_per_item(int mode) { return (mode == kBGradient || is_hvp(mode)) ? 8 : 2; }
+constexpr int max_chunks_per_item(int mode) { return (is_grad(mode) || is_hvp(mode)) ? 8 : 2; }
 
 struct BrickArgs {
     Geom g;
@@ -147,6 +163,7 @@ struct BrickArgs {
     float *accum_real;  // real target (squared-weight diagonal)
     double *loss;
     float scale;
+    float scale2;       // fused gradient and probe: the probe product's factor
     int ctf_power;
     const int *counts;  // [nb]
     const int *lists;   // [nb][stride]
@@ -415,11 +432,13 @@ struct Win {
     // gradient (whose packed accumulator waits on its atomics' old words,
     // which leaves no registers for a second pixel's state), two for the
     // other adjoint modes (measured fastest)
-    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : MODE == kBGradient ? CSG_RUN_GRAD : CSG_RUN_ADJ;
-    static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
+    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : is_grad(MODE) ? CSG_RUN_GRAD : CSG_RUN_ADJ;
+    static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : MODE == kBGradProbe ? CSG_WI_GP
+                            : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
     static constexpr int RPT = (ROWCAP + kBT - 1) / kBT; // rows per thread
-    static constexpr int RUNCAP = MODE == kBProject ? 7168 : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : CSG_RUNCAP_ADJ;
+    static constexpr int RUNCAP = MODE == kBProject ? 7168 : MODE == kBGradProbe ? CSG_RUNCAP_GP
+                                : (MODE == kBGradient || is_hvp(MODE)) ? CSG_RUNCAP_GH : CSG_RUNCAP_ADJ;
 };
 
 __device__ __forceinline__ double rint_scaled(float e) {
@@ -568,6 +587,55 @@ __device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi
     if (dl | dh) atomicAdd(counters, carry_counter_step(dl, dh));
 }
 
+// IEEE half-precision bits of 0, 1 or -1, and the two halves of a word as floats
+__device__ __forceinline__ uint32_t half_bits(float x) {
+    return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)x);
+}
+__device__ __forceinline__ float half_lo(uint32_t u) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xFFFFu));
+}
+__device__ __forceinline__ float half_hi(uint32_t u) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+}
+
+// Probe signs of row `row` (row = y + BX z of the extended brick) and probe p
+// (0: z_a, 1: z_b): bit x is set where the probe is -1 at voxel x of the row
+// (at most 13 consecutive voxels, which fall in one or two Philox blocks),
+// bit 16 + x where that voxel lies in the grid.
+__device__ __forceinline__ uint32_t probe_row_mask(const BrickArgs &a, const int o[3], int M, int row, int p) {
+    const int qy = o[1] + row % BX, qz = o[2] + row / BX;
+    const int nx = min(BX, M - o[0]);
+    uint32_t m = 0u;
+    if (qy < M && qz < M && (p == 0 || a.probe_has_b)) {
+        const int64_t g0 = ((int64_t)qz * M + qy) * M + o[0];
+        const uint64_t probe = p ? a.probe_b : a.probe_a;
+        const uint32_t b0 = (uint32_t)(g0 >> 7);
+        const U4 r0 = rademacher_block(a.probe_seed, probe, b0);
+        const bool next_block = (uint32_t)((g0 + nx - 1) >> 7) != b0;
+        const U4 r1 = next_block ? rademacher_block(a.probe_seed, probe, b0 + 1) : r0;
+        // the 13 bits from bit (g0 mod 128) on, in the words r0.x .. r0.w
+        // r1.x r1.y (a run of 13 spans at most two consecutive words)
+        const int start = (int)(g0 & 127), wi = start >> 5, sh = start & 31;
+        const uint32_t lo = wi == 0 ? r0.x : wi == 1 ? r0.y : wi == 2 ? r0.z : r0.w;
+        const uint32_t hi = wi == 0 ? r0.y : wi == 1 ? r0.z : wi == 2 ? r0.w : r1.x;
+        const uint64_t two = ((uint64_t)hi << 32) | lo;
+        m = (uint32_t)(two >> sh) & ((1u << nx) - 1u);
+        m |= ((1u << nx) - 1u) << 16;
+    }
+    return m;
+}
+
+// z_a + i z_b at voxel x of a row from the row's masks (0 outside the grid;
+// z_b = 0 without the second probe)
+__device__ __forceinline__ float2 probe_value(const uint32_t m[2], int x, int has_b) {
+    float2 z = make_float2(0.f, 0.f);
+    if ((m[0] >> (16 + x)) & 1u) {
+        z.x = ((m[0] >> x) & 1u) ? -1.f : 1.f;
+        if (has_b) z.y = ((m[1] >> x) & 1u) ? -1.f : 1.f;
+    }
+    return z;
+}
+
 #ifndef CSG_BRICK_WAVES
 #define CSG_BRICK_WAVES 6
 #endif
@@ -579,12 +647,18 @@ __device__ __forceinline__ void carry_fix(unsigned long long old, int qr, int qi
 // the fixed-point volume a.fx, so the result does not depend on the order in
 // which blocks and lanes add them.
 template <int MODE, bool SHIFT, bool FX>
-__global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
+__global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WAVES_GH : CSG_BRICK_WAVES) void brick_kernel(BrickArgs a) {
     static_assert(!FX || MODE == kBBackproject || MODE == kBGradient || MODE == kBHvp,
                   "fixed-point accumulation is built for backproject, gradient and HVP");
-    constexpr bool GATHER = MODE == kBProject || MODE == kBGradient || is_hvp(MODE);
+    static_assert(!(MODE == kBGradProbe && SHIFT), "the fused gradient and probe mode takes no in-plane shifts");
+    // the fused mode: the gradient of kBGradient and, in the same pass over the
+    // pixels, the probe product of kBHvpProbe (the probe pair staged beside the
+    // gathered volume; z (.) H z in an accumulator of its own, flushed after
+    // every chunk)
+    constexpr bool PROBE2 = MODE == kBGradProbe;
+    constexpr bool GATHER = MODE == kBProject || is_grad(MODE) || is_hvp(MODE);
     constexpr bool SCATTER = MODE != kBProject;
-    constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || MODE == kBGradient;
+    constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || is_grad(MODE);
     // the in-plane shift is compiled in only where a launch carries shifts
     constexpr bool SHIFTED = SHIFT && READS_IMG;
     constexpr int IMGDAT = SHIFTED ? 10 : 8;
@@ -605,7 +679,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // the packed accumulator with wrap counters (see CarryScale)
     // (gradient and HVP; in backproject, with its 80-register budget, the
     // held old words cost spills that ate the gain)
-    constexpr bool QCARRY = QITEM && (MODE == kBGradient || MODE == kBHvp);
+    constexpr bool QCARRY = QITEM && (is_grad(MODE) || MODE == kBHvp);
     using QScale = typename std::conditional<QCARRY, CarryScale, ItemScale>::type;
     // the item bound needs the largest staged volume value (gradient, HVP)
     // and, where images are read (backproject, gradient), a bound on their
@@ -630,9 +704,16 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     __shared__ unsigned s_wmax[kBT / 64];
     __shared__ unsigned s_xmax[kBT / 64];
     // probe HVP: signs of the staged rows ([row][probe]; see the staging)
-    __shared__ uint32_t s_zmask[MODE == kBHvpProbe ? BX * BX : 1][2];
+    // (the fused mode keeps them in the run table's storage, see below)
+    __shared__ uint32_t s_zmask_own[MODE == kBHvpProbe ? BX * BX : 1][2];
+    // fused mode: the staged probe pair (z_a, z_b as two halves, exact for
+    // 0 and +-1) and the sums of z (.) H z, one fixed-point integer per voxel
+    // (the probe signs of the receiving voxel are applied to each
+    // contribution, so the flush needs no signs)
+    __shared__ uint32_t zq[PROBE2 ? XN : 1];
+    __shared__ int acc_d[PROBE2 ? XN : 1];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
-    constexpr int RUNCAP = Win<MODE>::RUNCAP + (QCARRY ? CSG_RUNCAP_CARRY_EXTRA : 0) -
+    constexpr int RUNCAP = Win<MODE>::RUNCAP + (QCARRY && !PROBE2 ? CSG_RUNCAP_CARRY_EXTRA : 0) -
                            (SHIFTED && MODE == kBGradient ? CSG_RUNCAP_SHIFT_CUT : 0);
     constexpr int RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -642,7 +723,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     // row record: x = first run | len << 16 | image slot << 24,
     //             y = (kx0 + 32768) | (ky + 32768) << 16
     __shared__ int2 seg[ROWCAP];
-    __shared__ unsigned short run2row[RUNCAP];
+    __shared__ __align__(8) unsigned short run2row[RUNCAP];
+    // the fused mode's row masks live only while a brick is staged, when the
+    // run table is unused (barriers separate the two uses)
+    static_assert(!PROBE2 || RUNCAP * sizeof(unsigned short) >= BX * BX * 2 * sizeof(uint32_t), "run table too small");
+    uint32_t(*const s_zmask)[2] = PROBE2 ? reinterpret_cast<uint32_t(*)[2]>(run2row) : s_zmask_own;
     __shared__ int wave_sums[kBT / 64];
     __shared__ int s_item;
     __shared__ double red[16];
@@ -720,48 +805,15 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             constexpr int HPT = (HALO + kBT - 1) / kBT;
             float2 hv[HPT];
             if (MODE == kBHvpProbe) {
-                // the probe pair is generated, not loaded: one thread per row
-                // and probe of the extended brick forms the signs of the row's
-                // (at most 13, consecutive) voxels from the one or two Philox
-                // blocks they fall in, with the in-grid voxels marked in bits
-                // 16 and up; then every thread expands its voxels
-                if ((int)threadIdx.x < 2 * BX * BX) {
-                    const int row = threadIdx.x >> 1, p = threadIdx.x & 1;
-                    const int qy = o[1] + row % BX, qz = o[2] + row / BX;
-                    const int nx = min(BX, M - o[0]);
-                    uint32_t m = 0u;
-                    if (qy < M && qz < M && (p == 0 || a.probe_has_b)) {
-                        const int64_t g0 = ((int64_t)qz * M + qy) * M + o[0];
-                        const uint64_t probe = p ? a.probe_b : a.probe_a;
-                        const uint32_t b0 = (uint32_t)(g0 >> 7);
-                        const U4 r0 = rademacher_block(a.probe_seed, probe, b0);
-                        const bool next_block = (uint32_t)((g0 + nx - 1) >> 7) != b0;
-                        const U4 r1 = next_block ? rademacher_block(a.probe_seed, probe, b0 + 1) : r0;
-                        // the 13 bits from bit (g0 mod 128) on, in the words
-                        // r0.x .. r0.w r1.x r1.y (a run of 13 spans at most
-                        // two consecutive words)
-                        const int start = (int)(g0 & 127), wi = start >> 5, sh = start & 31;
-                        const uint32_t lo = wi == 0 ? r0.x : wi == 1 ? r0.y : wi == 2 ? r0.z : r0.w;
-                        const uint32_t hi = wi == 0 ? r0.y : wi == 1 ? r0.z : wi == 2 ? r0.w : r1.x;
-                        const uint64_t two = ((uint64_t)hi << 32) | lo;
-                        m = (uint32_t)(two >> sh) & ((1u << nx) - 1u);
-                        m |= ((1u << nx) - 1u) << 16;
-                    }
-                    s_zmask[row][p] = m;
-                }
+                // the probe pair is generated, not loaded (see probe_row_mask);
+                // then every thread expands its voxels
+                if ((int)threadIdx.x < 2 * BX * BX)
+                    s_zmask[threadIdx.x >> 1][threadIdx.x & 1] = probe_row_mask(a, o, M, threadIdx.x >> 1, threadIdx.x & 1);
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < HPT; ++k) {
                     const int t = threadIdx.x + k * kBT;
-                    const int hx = t % BX, row = t / BX;
-                    hv[k] = make_float2(0.f, 0.f);
-                    if (t < HALO) {
-                        const uint32_t ma = s_zmask[row][0], mb = s_zmask[row][1];
-                        if ((ma >> (16 + hx)) & 1u) {
-                            hv[k].x = ((ma >> hx) & 1u) ? -1.f : 1.f;
-                            if (a.probe_has_b) hv[k].y = ((mb >> hx) & 1u) ? -1.f : 1.f;
-                        }
-                    }
+                    hv[k] = t < HALO ? probe_value(s_zmask[t / BX], t % BX, a.probe_has_b) : make_float2(0.f, 0.f);
                 }
             } else {
 #pragma unroll
@@ -775,6 +827,22 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 hv[k] = make_float2(0.f, 0.f);
                 if (t < HALO && qx < M && qy < M && qz < M) hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
             }
+            }
+            if (PROBE2) {
+                // the probe pair beside the volume: masks while the volume's
+                // loads are in flight, then the expanded values
+                if ((int)threadIdx.x < 2 * BX * BX)
+                    s_zmask[threadIdx.x >> 1][threadIdx.x & 1] = probe_row_mask(a, o, M, threadIdx.x >> 1, threadIdx.x & 1);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < HPT; ++k) {
+                    const int t = threadIdx.x + k * kBT;
+                    if (t < HALO) {
+                        const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
+                        const float2 z = probe_value(s_zmask[t / BX], hx, a.probe_has_b);
+                        zq[(hz * XR + hy) * XR + hx] = half_bits(z.x) | (half_bits(z.y) << 16);
+                    }
+                }
             }
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
@@ -817,6 +885,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
             for (int t = threadIdx.x; t < XN; t += kBT) {
                 acc_re[t] = 0.0;
                 if (t < XN_IM) acc_im[t] = 0.0;
+                if (PROBE2) acc_d[t] = 0;
             }
         }
         PackedScale pk;  // set in the first window (after a barrier)
@@ -917,6 +986,20 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 }
             }
         };
+        // fused mode: the probe pair's sums of one chunk, z (.) H z into the
+        // diagonal as in the probe HVP's flush, cleared for the next chunk
+        auto flush_probe = [&]() {
+            constexpr int NV = BX * BX * BX;
+            for (int t = threadIdx.x; t < NV; t += kBT) {
+                const int tx = t % BX, ty = (t / BX) % BX, tz = t / (BX * BX);
+                const int li = (tz * XR + ty) * XR + tx;
+                const int q = acc_d[li];
+                acc_d[li] = 0;
+                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
+                const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
+                if (q) atomicAdd(a.accum_real + gi, (float)q * pk.invS);
+            }
+        };
 
         for (int attempt = 0;; ++attempt) {
             unsigned xmax_item = 0u;  // this thread's largest image value of the item
@@ -943,6 +1026,8 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                         for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
                         const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
                         if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
+                        // the fused probe pair: |z_a| + |z_b| <= 2 (1 without z_b)
+                        if (PROBE2) pk = PackedScale::make(fabsf(a.scale2) * (a.probe_has_b ? 2.f : 1.f));
                         if (QITEM) {
                             const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
                             const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
@@ -1120,6 +1205,9 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                         // index of the base corner in the extended brick; the
                                         // eight corners lie in it
                                         const int lb = (l[2] * XR + l[1]) * XR + l[0];
+                                        // fused mode: the probe pair at the corners and P z
+                                        uint32_t zc[PROBE2 ? 8 : 1];
+                                        float2 pz = make_float2(0.f, 0.f);
                                         if (GATHER) {
                                             // staged voxels outside the grid hold zeros, which
                                             // drops those corners
@@ -1130,6 +1218,11 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                 const float2 v = vh[lb + az * XP + ay * XR + ax];
                                                 acc.x = fmaf(w, v.x, acc.x);
                                                 acc.y = fmaf(w, v.y, acc.y);
+                                                if (PROBE2) {
+                                                    zc[c] = zq[lb + az * XP + ay * XR + ax];
+                                                    pz.x = fmaf(w, half_lo(zc[c]), pz.x);
+                                                    pz.y = fmaf(w, half_hi(zc[c]), pz.y);
+                                                }
                                             }
                                         }
                                         // in-plane shift: T on the forward value, conj(T)
@@ -1160,7 +1253,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                             const float2 x = cmul_conj(xin[jj], T);
                                             const float fct = a.scale * ctf_pow(C, a.ctf_power);
                                             val = make_float2(fct * x.x, fct * x.y);
-                                        } else if (MODE == kBGradient) {
+                                        } else if (is_grad(MODE)) {
                                             const float2 x = xin[jj];
                                             const float2 rr = make_float2(fmaf(C, acc.x, -x.x), fmaf(C, acc.y, -x.y));
                                             lsum += 0.5 * ((double)rr.x * rr.x + (double)rr.y * rr.y);
@@ -1211,6 +1304,23 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                                                     }
                                                 }
                                             }
+                                            if (PROBE2 && attempt == 0) {
+                                                // fused mode, after the gradient's atomics: the
+                                                // probe pair's product scale2 C^2 P z at this
+                                                // pixel; corner c receives w_c (z_a(c) re +
+                                                // z_b(c) im) of z (.) H z, one fixed-point integer
+                                                // (the bound of PackedScale); a retried item
+                                                // (attempt > 0) has its probe sums flushed already
+                                                const float fz = a.scale2 * C * C;
+                                                const float px = fz * pz.x * pk.S, py = fz * pz.y * pk.S;
+#pragma unroll
+                                                for (int c = 0; c < 8; ++c) {
+                                                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                    const float w = wx[ax] * wy[ay] * wz[az];
+                                                    const float d = fmaf(half_lo(zc[c]), px, half_hi(zc[c]) * py);
+                                                    atomicAdd(&acc_d[lb + az * XP + ay * XR + ax], round_half_up(w * d));
+                                                }
+                                            }
                                         } else if (SCATTER) {
                                             // all eight corners; a corner beyond the grid edge
                                             // lands in a slot that is never written back
@@ -1246,6 +1356,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 }
                 // the probe mode's packed sums hold one chunk (see PackedScale)
                 if (PK_ALWAYS) flush_voxels();
+                if (PROBE2 && attempt == 0) flush_probe();
             }  // chunks
             if (!XRETRY) break;
             // the item's largest image value; above the guess, a fixed-point sum
@@ -1265,7 +1376,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
                 if (threadIdx.x == 0) s_xseen = max(s_xseen, im);
                 if (im <= guess || attempt > 0) {
                     // the item's loss terms, added once the item is accepted
-                    if (MODE == kBGradient && a.loss) {
+                    if (is_grad(MODE) && a.loss) {
                         const double t = block_sum(lsum, red);
                         if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
                     }
@@ -1288,7 +1399,7 @@ __global__ __launch_bounds__(kBT, (MODE == kBGradient || is_hvp(MODE)) ? CSG_BRI
     }  // work items
 
     // (the gradient with the retry adds its loss per item)
-    if ((MODE == kBProject || (MODE == kBGradient && !XRETRY)) && a.loss) {
+    if ((MODE == kBProject || (is_grad(MODE) && !XRETRY)) && a.loss) {
         const double t = block_sum(lsum, red);
         if (threadIdx.x == 0 && t != 0.0) atomicAdd(a.loss, t);
     }
@@ -1361,10 +1472,12 @@ static int resident_blocks() {
     return cus * per;
 }
 
-// The Rademacher probe pair of the probe HVP mode (seed, pa, pb, has_b).
+// The Rademacher probe pair of the probe HVP mode (seed, pa, pb, has_b) and,
+// in the fused gradient and probe mode, the factor of its product.
 struct ProbePair {
     uint64_t seed, pa, pb;
     int has_b;
+    float scale = 0.f;
 };
 
 template <int MODE, bool FX = false>
@@ -1435,14 +1548,19 @@ static hipError_t run_brick_mode(const Geom &g, const float *rot, const float *d
             a.probe_a = probe->pa;
             a.probe_b = probe->pb;
             a.probe_has_b = probe->has_b;
+            a.scale2 = probe->scale;
         }
-        // the probe HVP is timed with the HVP
-        constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE;
+        // the probe HVP is timed with the HVP, the fused mode under index 6
+        constexpr int TMODE = MODE == kBHvpProbe ? kBHvp : MODE == kBGradProbe ? kTimedGradProbe : MODE;
         hipEvent_t t0 = timed ? timing_begin(TMODE, st) : nullptr;
-        if (shift)
-            hipLaunchKernelGGL((brick_kernel<MODE, true, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
-        else
+        if constexpr (MODE == kBGradProbe) {
             hipLaunchKernelGGL((brick_kernel<MODE, false, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+        } else {
+            if (shift)
+                hipLaunchKernelGGL((brick_kernel<MODE, true, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+            else
+                hipLaunchKernelGGL((brick_kernel<MODE, false, FX>), dim3((unsigned)grid), dim3(kBT), 0, st, a);
+        }
         e = hipGetLastError();
         timing_end(TMODE, t0, st);
         if (e != hipSuccess) return e;
@@ -1506,6 +1624,19 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
     if (n == 0) return hipSuccess;
     if (g.interp == 0) return launch_hvp_atomic(g, rot, defocus, n, z, scale, accum, st);
     return run_brick_mode<kBHvp>(g, rot, defocus, nullptr, n, z, nullptr, nullptr, accum, nullptr, scale, 2, ws, st);
+}
+
+// Gradient (as launch_brick_gradient, no in-plane shifts) and the probe
+// pair's z (.) scale2 P^T C^2 P z added to diag, in one pass over the pixels.
+hipError_t launch_brick_gradient_probe(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                       const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
+                                       uint64_t seed, uint64_t pa, uint64_t pb, int has_b, float scale2, float *diag,
+                                       void *ws, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (g.interp == 0) return hipErrorInvalidValue;  // trilinear stencils only
+    const ProbePair pp{seed, pa, pb, has_b, scale2};
+    return run_brick_mode<kBGradProbe>(g, rot, defocus, nullptr, n, vol, x, nullptr, accum, loss, scale, 1, ws, st,
+                                       diag, nullptr, &pp);
 }
 
 hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,

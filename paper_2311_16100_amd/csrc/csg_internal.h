@@ -14,7 +14,8 @@ namespace csg {
 constexpr int64_t kBrickSubBatch = 2048;
 
 // optional kernel timing (timing.hip): brick kernel modes 0..kTimedKernels-1
-constexpr int kTimedKernels = 6;
+constexpr int kTimedKernels = 7;
+constexpr int kTimedGradProbe = 6;  // the fused gradient and probe kernel
 void timing_set(int on);
 hipEvent_t timing_begin(int kernel, hipStream_t st);  // nullptr when not timing
 void timing_end(int kernel, hipEvent_t start, hipStream_t st);
@@ -51,6 +52,12 @@ hipError_t launch_brick_hvp(const Geom &g, const float *rot, const float *defocu
 hipError_t launch_brick_hvp_probe(const Geom &g, const float *rot, const float *defocus, int64_t n, uint64_t seed,
                                   uint64_t pa, uint64_t pb, int has_b, float scale, float *diag, void *ws,
                                   hipStream_t st);
+// launch_brick_gradient (no in-plane shifts) and launch_brick_hvp_probe with
+// factor scale2 in one pass over the pixels (trilinear grids)
+hipError_t launch_brick_gradient_probe(const Geom &g, const float *rot, const float *defocus, int64_t n,
+                                       const float2 *vol, const float2 *x, float scale, float2 *accum, double *loss,
+                                       uint64_t seed, uint64_t pa, uint64_t pb, int has_b, float scale2, float *diag,
+                                       void *ws, hipStream_t st);
 // the deterministic adjoint (fixed point; trilinear grids): scratch of
 // 16 M^3 bytes (the 64-bit fixed-point volume, 16-byte aligned) and two words
 // (input bounds), both in device memory

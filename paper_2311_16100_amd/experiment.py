@@ -298,7 +298,7 @@ def load_checkpoint(path: str):
 def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: float = 1e-2, max_epochs: int = 20,
             eval_every: int = 1, eta0: float = 1.0, decay_epochs: int = 0, D_fixed=None, setup_seconds: float = 0.0,
             seed: int = 0, time_limit: float = 120.0, n_probe: int = 2, stop_on: str = "ball",
-            deterministic: bool = False, progress=None, queue_probes: bool = True,
+            deterministic: bool = False, progress=None, queue_probes: bool = True, fused: bool = True,
             average_from_epoch: int | None = None, fsc_every: int = 0, checkpoint: str | None = None,
             checkpoint_every: int = 0, resume: str | None = None, stop_at: int | None = None) -> RunResult:
     """Algorithm 1 from v = 0 until the relative error of `stop_on` ("ball":
@@ -312,9 +312,11 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     (and the averaging); the error evaluations are timed apart (`eval_seconds`)
     and not counted, and for a streamed data set neither is the regeneration
     of each batch's images (`gen_seconds`).
-    `deterministic` selects the bitwise-reproducible adjoint.  With
-    `queue_probes` the runner is told the next batch's poses (the Hutchinson
-    arm then computes its next probe product during the line search).
+    `deterministic` selects the bitwise-reproducible adjoint.  `fused` (fast
+    adjoint only) has the Hutchinson arm form each iteration's gradient and
+    probe product in one call; otherwise, with `queue_probes`, the runner is
+    told the next batch's poses and computes that batch's probe product
+    during the line search.
     The shell correlation with v* is recorded after every epoch, at the stop,
     and every `fsc_every` iterations if that is > 0 (outside the timing).
     Checkpoints: with `checkpoint` a path, the run's state (iterate, diagonal
@@ -328,7 +330,7 @@ def run_arm(ds: Dataset, v_star: torch.Tensor, arm: str, batch: int, target: flo
     dev = ds.device
     scale = ds.N / batch
     alpha = B.threshold_alpha(ds.grid, ds.optics, ds.rot, ds.defocus, ds.lam).item()
-    cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17, deterministic=deterministic)
+    cfg = Alg1Config(eta0=eta0, n_probe=n_probe, probe_seed=seed + 17, deterministic=deterministic, fused=fused)
     kind = {"plain": "plain", "hutchinson": "hutchinson", "learned": "fixed", "exact": "fixed",
             "precomputed": "fixed"}[arm]
     v0 = torch.zeros_like(v_star)

@@ -41,6 +41,10 @@ class Alg1Config:
     max_halvings: int = 30
     probe_seed: int = 4
     deterministic: bool = False
+    # Hutchinson arm, fast gradient: the gradient and the iteration's probe
+    # product in one call (csg_gradient_hutchinson); otherwise two calls, the
+    # probe product of the next batch queued behind the line search
+    fused: bool = True
 
 
 @dataclass
@@ -72,18 +76,20 @@ class Alg1Runner:
         else:
             D, Da = None, None
         self.state = Alg1State(v=v0.clone(), D=D, D_avg=Da, eta=cfg.eta0)
+        self.fused = arm == "hutchinson" and cfg.fused and not cfg.deterministic
         self.g = torch.empty_like(v0)
         self.v_new = torch.empty_like(v0)
         self.zHz = torch.empty((M, M, M), dtype=torch.float32, device=dev) if arm == "hutchinson" else None
-        self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" else None
+        self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" and not self.fused else None
         self._queued = None  # (rot, defocus, k) of the probe product already in zHz_next
         # scalars: [0] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data term of f(v')
         self.sc = torch.zeros(4, dtype=torch.float64, device=dev)
         self.sc_host = torch.zeros(4, dtype=torch.float64, pin_memory=True)
         self.sc_ready = torch.cuda.Event()
         self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
-                                         else B.CSG_WS_GRADIENT, dev)
-        self.ws_hutch = B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev) if arm == "hutchinson" else None
+                                         else B.CSG_WS_GRADIENT_HUTCHINSON if self.fused else B.CSG_WS_GRADIENT, dev)
+        self.ws_hutch = (B.alloc_workspace(grid, batch, B.CSG_WS_HUTCHINSON, dev)
+                         if arm == "hutchinson" and not self.fused else None)
         self.ws_proj = B.alloc_workspace(grid, batch, B.CSG_WS_PROJECT, dev)
 
     def state_dict(self) -> dict:
@@ -113,21 +119,31 @@ class Alg1Runner:
     def iteration(self, rot_I, df_I, x_I, next_poses=None) -> int:
         """One iteration on the batch (rot_I, df_I, x_I).  `next_poses` =
         (rot, defocus) of the next call's batch, if known: the Hutchinson arm
-        then computes that batch's probe product during this line search, and
-        the next call uses it when it is given the same two tensors."""
+        without the fused call then computes that batch's probe product during
+        this line search, and the next call uses it when it is given the same
+        two tensors."""
         st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
         st.k += 1
+        have_grad = False
         if self.arm == "hutchinson":
             q = self._queued
             if q is not None and q[0] is rot_I and q[1] is df_I and q[2] == st.k:
                 self.zHz, self.zHz_next = self.zHz_next, self.zHz
+            elif self.fused:
+                # the gradient and z (.) H_I z for this iteration's probes
+                # (Algorithm 1: gradient and running-mean line) in one pass
+                B.gradient_hutchinson(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, cfg.n_probe,
+                                      cfg.probe_seed, probe0=(st.k - 1) * cfg.n_probe, grad_out=self.g,
+                                      loss_out=self.sc[0:1], diag_out=self.zHz, workspace=self.ws_grad)
+                have_grad = True
             else:
                 # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
                 B.hutchinson_diag(g, o, rot_I, df_I, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
                                   probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
             self._queued = None
-        B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g, loss_out=self.sc[0:1],
-                   deterministic=cfg.deterministic, workspace=self.ws_grad)
+        if not have_grad:
+            B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g, loss_out=self.sc[0:1],
+                       deterministic=cfg.deterministic, workspace=self.ws_grad)
         eta = st.eta
         halvings = 0
         first = True
@@ -140,7 +156,7 @@ class Alg1Runner:
                       workspace=self.ws_proj)
             self.sc_host.copy_(self.sc, non_blocking=True)
             self.sc_ready.record()
-            if first and next_poses is not None and self.arm == "hutchinson":
+            if first and next_poses is not None and self.arm == "hutchinson" and not self.fused:
                 rn, dn = next_poses
                 B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
                                   probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)

@@ -108,11 +108,12 @@ def test_bad_ctf_power_rejected(b):
 def test_timing_arguments_checked(b):
     L = b.lib()
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
-    assert L.csg_timing_read(6, ctypes.byref(ms), ctypes.byref(n)) == -1
+    assert L.csg_timing_read(7, ctypes.byref(ms), ctypes.byref(n)) == -1
     assert L.csg_timing_read(-1, ctypes.byref(ms), ctypes.byref(n)) == -1
     assert L.csg_timing_read(0, None, ctypes.byref(n)) == -1
     # nothing recorded: zero launches, and reading needs no device
     assert b.timing_read("gradient") == (0.0, 0)
+    assert b.timing_read("gradient_probe") == (0.0, 0)
     b.timing_enable(False)
 
 
@@ -128,3 +129,31 @@ def test_noalloc_gradient_checks_arguments_on_the_host(b):
     assert L.csg_gradient_noalloc(ctypes.byref(bad), ctypes.byref(o), ctypes.byref(p), None, None, 1.0, 0.0, None,
                                   None, None) == -1
     assert b"must be even" in L.csg_last_error()
+
+
+def test_gradient_hutchinson_checks_arguments_on_the_host(b):
+    """The one-call gradient and Hutchinson diagonal rejects bad arguments
+    and a missing workspace before anything is enqueued (the pointers below
+    are host buffers that no kernel ever sees)."""
+    L = b.lib()
+    g, o = b.Grid(32).c(), b.Optics().c()
+    bufs = [ctypes.create_string_buffer(64) for _ in range(5)]
+    rot, df, vol, x, out = (ctypes.cast(u, ctypes.c_void_p) for u in bufs)
+    p = b._Poses(4, rot, df, None)
+    diag = ctypes.c_void_p(ctypes.addressof(bufs[4]) + 32)
+
+    def call(n_probe=2, grad=out, dg=diag, ws=None, wn=0, v=vol):
+        return L.csg_gradient_hutchinson(ctypes.byref(g), ctypes.byref(o), ctypes.byref(p), v, x, 1.0, 0.1, grad,
+                                         None, n_probe, 7, 0, dg, ws, wn, None)
+
+    assert call(n_probe=0) == -1 and b"n_probe" in L.csg_last_error()
+    assert call(dg=None) == -1 and b"non-NULL" in L.csg_last_error()
+    assert call(grad=diag) == -1 and b"alias" in L.csg_last_error()
+    assert call(v=out) == -1 and b"alias" in L.csg_last_error()
+    assert call() == -3 and b"workspace" in L.csg_last_error()
+    need = b.workspace_bytes(b.Grid(32), 4, b.CSG_WS_GRADIENT_HUTCHINSON)
+    assert need == max(b.workspace_bytes(b.Grid(32), 4, b.CSG_WS_GRADIENT),
+                       b.workspace_bytes(b.Grid(32), 4, b.CSG_WS_HUTCHINSON))
+    nn = b.Grid(32, interp=0)
+    assert b.workspace_bytes(nn, 4, b.CSG_WS_GRADIENT_HUTCHINSON) >= b.workspace_bytes(nn, 4, b.CSG_WS_HUTCHINSON)
+    assert b.workspace_bytes(nn, 4, b.CSG_WS_GRADIENT_HUTCHINSON) >= b.workspace_bytes(nn, 4, b.CSG_WS_GRADIENT)

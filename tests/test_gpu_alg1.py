@@ -81,7 +81,8 @@ def run_oracle(case, grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
     return out
 
 
-def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False):
+def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False,
+            fused=None):
     from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
     M = case.M
     g = b.Grid(M)
@@ -90,7 +91,10 @@ def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, misma
     rot_d = torch.from_numpy(np.ascontiguousarray(P.rot)).to(dev)
     df_d = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)
     x_d = torch.from_numpy(x).to(dev)
-    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED, deterministic=deterministic)
+    # the queued probe products belong to the two-call form of the Hutchinson
+    # arm; without queueing it runs the one-kernel gradient and probe product
+    cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED, deterministic=deterministic,
+                     fused=(not queue) if fused is None else fused)
     kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
     Df = None if D_fixed is None else torch.from_numpy(D_fixed.astype(np.float32).reshape(M, M, M)).to(dev)
     v0 = torch.zeros((M, M, M), dtype=torch.complex64, device=dev)
@@ -145,7 +149,7 @@ def test_queued_probe_for_other_tensors_is_recomputed():
     the queued product unused: the trajectory equals the one computed in
     place."""
     b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
-    a = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson")
+    a = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", fused=False)
     m = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", queue=True, mismatch=True)
     for (ha, ea, va), (hm, em, vm) in zip(a, m):
         assert ha == hm and ea == em

@@ -6,8 +6,9 @@ configuration the benchmark times (one call over the 1024 images).
 Every entry point of the timed step is compared with the oracle on the same
 float32 inputs: the forward projection, the adjoint (fast and
 deterministic), the fused gradient and loss (fast and deterministic), the
-Hessian-vector product (fast and deterministic) and the Hutchinson probe
-product.  Two bounds per output, both written here:
+Hessian-vector product (fast and deterministic), the Hutchinson probe
+product, and the gradient with the probe product in one kernel (the launch
+of the benchmark's Algorithm 1 step).  Two bounds per output, both written here:
   relative L2        <= 1e-5 (project) / 1e-4 (adjoint modes)
   per element  max|got - want| <= 1e-5 / 1e-4 times max|want|
 The oracle's C loops run over chunks of the batch in threads (the ctypes
@@ -97,23 +98,54 @@ def test_full_batch_backproject(full, det):
     close(acc.cpu().numpy(), want, 1e-4, 1e-4, "backproject (%s)" % ("deterministic" if det else "fast"))
 
 
+# the oracle's results are computed once per module and shared by the tests
+# that compare with them
+_WANT = {}
+G_SCALE, G_LAM = 195.3, 0.05
+H_SEED, H_PROBE0 = 99, 6
+
+
+def gradient_case(full):
+    """Images x near the model's images (the regime of the iterations: the
+    oracle's projections of a second blob volume plus noise) and the oracle's
+    gradient and loss at vol."""
+    if "gradient" not in _WANT:
+        b, grid, P, vol, rot, df, v, disk = full
+        x = (o_project(grid, oracle.Optics(), P, synth.blob_volume(M, 1000, SEED + 1))
+             + 30.0 * synth.random_complex((N_IMG, M, M), 7, stream=14)) * disk[None]
+        x = x.astype(np.complex64)
+        r = o_project(grid, oracle.Optics(), P, vol) - x.astype(np.complex128)
+        want = o_backproject(grid, oracle.Optics(), P, r, 1, G_SCALE) + G_LAM * vol.astype(np.complex128)
+        vv = vol.astype(np.complex128)
+        want_f = G_SCALE * 0.5 * np.vdot(r, r).real + 0.5 * G_LAM * np.vdot(vv, vv).real
+        _WANT["gradient"] = (x, want, want_f)
+    return _WANT["gradient"]
+
+
+def hutchinson_want(full, scale, lam):
+    """The oracle's z (.) H z for the probes H_PROBE0 and H_PROBE0 + 1 (seed
+    H_SEED), averaged."""
+    key = ("hutchinson", scale, lam)
+    if key not in _WANT:
+        b, grid, P, vol, rot, df, v, disk = full
+        want = np.zeros(M ** 3)
+        for p in (H_PROBE0, H_PROBE0 + 1):
+            z = oracle.rademacher(H_SEED, p, M ** 3)
+            hz = o_backproject(grid, oracle.Optics(), P, o_project(grid, oracle.Optics(), P, z.reshape(M, M, M)), 1,
+                               scale).reshape(-1) + lam * z
+            want += z * hz.real / 2
+        _WANT[key] = want
+    return _WANT[key]
+
+
 @pytest.mark.parametrize("det", [False, True], ids=["fast", "deterministic"])
 def test_full_batch_gradient_and_loss(full, det):
     b, grid, P, vol, rot, df, v, disk = full
-    # data near the model's images (the regime of the iterations): the
-    # oracle's projections of a second blob volume plus noise
-    x = (o_project(grid, oracle.Optics(), P, synth.blob_volume(M, 1000, SEED + 1))
-         + 30.0 * synth.random_complex((N_IMG, M, M), 7, stream=14)) * disk[None]
-    x = x.astype(np.complex64)
-    scale, lam = 195.3, 0.05
+    x, want, want_f = gradient_case(full)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    gr = b.gradient(b.Grid(M), b.Optics(), rot, df, v, torch.from_numpy(x).cuda(), scale, lam, loss_out=loss,
+    gr = b.gradient(b.Grid(M), b.Optics(), rot, df, v, torch.from_numpy(x).cuda(), G_SCALE, G_LAM, loss_out=loss,
                     deterministic=det)
-    r = o_project(grid, oracle.Optics(), P, vol) - x.astype(np.complex128)
-    want = o_backproject(grid, oracle.Optics(), P, r, 1, scale) + lam * vol.astype(np.complex128)
     close(gr.cpu().numpy(), want, 1e-4, 1e-4, "gradient (%s)" % ("deterministic" if det else "fast"))
-    vv = vol.astype(np.complex128)
-    want_f = scale * 0.5 * np.vdot(r, r).real + 0.5 * lam * np.vdot(vv, vv).real
     assert loss.item() == pytest.approx(want_f, rel=1e-5)
 
 
@@ -133,12 +165,20 @@ def test_full_batch_hutchinson(full):
     whole batch against the oracle's z (.) H z for the same two Rademacher
     probes, averaged."""
     b, grid, P, vol, rot, df, v, disk = full
-    scale, lam, seed, p0 = 195.3, 0.05, 99, 6
-    got = b.hutchinson_diag(b.Grid(M), b.Optics(), rot, df, 2, seed=seed, scale=scale, lam=lam, probe0=p0)
-    want = np.zeros(M ** 3)
-    for p in (p0, p0 + 1):
-        z = oracle.rademacher(seed, p, M ** 3)
-        hz = o_backproject(grid, oracle.Optics(), P, o_project(grid, oracle.Optics(), P, z.reshape(M, M, M)), 1,
-                           scale).reshape(-1) + lam * z
-        want += z * hz.real / 2
-    close(got.cpu().numpy(), want, 1e-4, 1e-4, "hutchinson probe pair")
+    got = b.hutchinson_diag(b.Grid(M), b.Optics(), rot, df, 2, seed=H_SEED, scale=G_SCALE, lam=G_LAM,
+                            probe0=H_PROBE0)
+    close(got.cpu().numpy(), hutchinson_want(full, G_SCALE, G_LAM), 1e-4, 1e-4, "hutchinson probe pair")
+
+
+def test_full_batch_gradient_hutchinson(full):
+    """The benchmark's timed launch: gradient, loss and the probe pair's
+    z (.) H z of the whole batch in one kernel (csg_gradient_hutchinson),
+    against the oracle's gradient, loss and Hutchinson diagonal."""
+    b, grid, P, vol, rot, df, v, disk = full
+    x, want_g, want_f = gradient_case(full)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr, dg = b.gradient_hutchinson(b.Grid(M), b.Optics(), rot, df, v, torch.from_numpy(x).cuda(), G_SCALE, G_LAM, 2,
+                                   H_SEED, probe0=H_PROBE0, loss_out=loss)
+    close(gr.cpu().numpy(), want_g, 1e-4, 1e-4, "fused: gradient")
+    assert loss.item() == pytest.approx(want_f, rel=1e-5)
+    close(dg.cpu().numpy(), hutchinson_want(full, G_SCALE, G_LAM), 1e-4, 1e-4, "fused: hutchinson probe pair")

@@ -7,8 +7,8 @@ same central bricks, so the fast adjoint's packed LDS sums wrap their 32-bit
 halves often there.
 
 Compared with the oracle: the fast and the deterministic gradient and loss
-(the runs on this set use the deterministic one) and the Hutchinson probe
-pair.  Bounds, written here: relative L2 <= 1e-4 and, per element,
+(the runs on this set use the deterministic one), the Hutchinson probe pair,
+and both from the kernel that forms them in one pass.  Bounds, written here: relative L2 <= 1e-4 and, per element,
 max|got - want| <= 1e-4 max|want|.  The oracle's C loops run over chunks of
 the batch in threads; the chunks' volumes are summed in chunk order (a split
 of the sum over images of the definitions).
@@ -89,6 +89,11 @@ def test_stress_batch_gradient_and_loss(stress):
         gr = b.gradient(b.Grid(M), b.Optics(), rot, df, v, xd, scale, lam, loss_out=loss, deterministic=det)
         close(gr.cpu().numpy(), want, 1e-4, "gradient (%s)" % ("deterministic" if det else "fast"))
         assert loss.item() == pytest.approx(want_f, rel=1e-5)
+    # the gradient with the probe product in one kernel
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr, _ = b.gradient_hutchinson(b.Grid(M), b.Optics(), rot, df, v, xd, scale, lam, 2, 23, probe0=40, loss_out=loss)
+    close(gr.cpu().numpy(), want, 1e-4, "gradient (fused with the probe product)")
+    assert loss.item() == pytest.approx(want_f, rel=1e-5)
 
 
 def test_stress_batch_hutchinson(stress):
@@ -102,3 +107,8 @@ def test_stress_batch_hutchinson(stress):
                            scale).reshape(-1) + lam * z
         want += z * hz.real / 2
     close(got.cpu().numpy(), want, 1e-4, "hutchinson probe pair")
+    # the same pair's product from the kernel that also forms the gradient
+    # (the diagonal depends on neither the volume nor the images)
+    x0 = torch.zeros((N_IMG, M, M), dtype=torch.complex64, device="cuda")
+    _, dg = b.gradient_hutchinson(b.Grid(M), b.Optics(), rot, df, v, x0, scale, lam, 2, seed, probe0=p0)
+    close(dg.cpu().numpy(), want, 1e-4, "hutchinson probe pair (fused with the gradient)")

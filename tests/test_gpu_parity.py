@@ -243,6 +243,68 @@ def test_hutchinson_parity_many_images(b):
     close(got, want, 1e-4)
 
 
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "M%d-n%d-i%d" % (c["M"], c["n"], c["interp"]))
+@pytest.mark.parametrize("n_probe", [1, 2, 3])
+def test_gradient_hutchinson_parity(b, case, n_probe):
+    """csg_gradient_hutchinson against the oracle's gradient, loss and
+    Hutchinson diagonal of the same batch (trilinear grids: one kernel forms
+    the gradient and the first probe pair's product, a third probe takes the
+    probe kernel; nearest-neighbour grids: the two separate paths)."""
+    grid_o, opt_o, P, vol, img = make_case(**case)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    scale, lam = 3.5, 0.2
+    img_d = img * _disk(grid_o)[None]
+    want_g = oracle.gradient(grid_o, opt_o, P, vol, img_d, scale, lam)
+    want_f = oracle.loss(grid_o, opt_o, P, vol, img_d, scale, lam)
+    want_d = oracle.hutchinson_diag(grid_o, opt_o, P, n_probe, 77, scale, lam, probe0=3)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr, dg = b.gradient_hutchinson(g, o, rot, df, v, x, scale, lam, n_probe, 77, probe0=3, loss_out=loss)
+    close(gr.cpu().numpy(), want_g, 1e-4, "gradient")
+    assert loss.item() == pytest.approx(want_f, rel=1e-5)
+    close(dg.cpu().numpy(), want_d, 1e-4, "hutchinson")
+
+
+@pytest.mark.parametrize("M,n,blob", [(36, 300, False), (72, 200, True)])
+def test_gradient_hutchinson_many_images(b, M, n, blob):
+    """More than 128 images per brick (several chunks per work item, whose
+    probe sums are flushed one chunk at a time, several 32-image windows per
+    chunk, several work items per brick): the one-kernel gradient and probe
+    product against the oracle."""
+    grid_o, opt_o, P, vol, img = make_case(M=M, n=n, seed=23, blob=blob)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    scale, lam = 0.7, 0.02
+    want_g = oracle.gradient(grid_o, opt_o, P, vol, img * _disk(grid_o)[None], scale, lam)
+    want_d = oracle.hutchinson_diag(grid_o, opt_o, P, 2, 5, scale, lam, probe0=11)
+    gr, dg = b.gradient_hutchinson(g, o, rot, df, v, x, scale, lam, 2, 5, probe0=11)
+    close(gr.cpu().numpy(), want_g, 1e-4, "gradient")
+    close(dg.cpu().numpy(), want_d, 1e-4, "hutchinson")
+
+
+def test_gradient_hutchinson_with_shifts_and_empty_batch(b):
+    """In-plane shifts take the separate gradient and probe kernels (the
+    Hessian ignores the shifts); an empty batch leaves the gradient lambda v,
+    the loss lambda/2 |v|^2 and the diagonal lambda."""
+    grid_o, opt_o, P, vol, img = make_case(M=32, n=24, seed=24)
+    shifts = np.random.default_rng(24).uniform(-8.0, 8.0, (P.n, 2)).astype(np.float32)
+    Ps = oracle.Poses(P.rot, P.defocus, shifts)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x, sh = to_dev(P.rot, P.defocus, vol, img, shifts)
+    img_d = img * _disk(grid_o)[None]
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr, dg = b.gradient_hutchinson(g, o, rot, df, v, x, 2.0, 0.1, 2, 8, probe0=2, loss_out=loss, shift=sh)
+    close(gr.cpu().numpy(), oracle.gradient(grid_o, opt_o, Ps, vol, img_d, 2.0, 0.1), 1e-4, "gradient")
+    assert loss.item() == pytest.approx(oracle.loss(grid_o, opt_o, Ps, vol, img_d, 2.0, 0.1), rel=1e-5)
+    close(dg.cpu().numpy(), oracle.hutchinson_diag(grid_o, opt_o, P, 2, 8, 2.0, 0.1, probe0=2), 1e-4, "hutchinson")
+    loss.zero_()
+    gr, dg = b.gradient_hutchinson(g, o, rot[:0], df[:0], v, x[:0], 2.0, 0.1, 2, 8, loss_out=loss)
+    vv = vol.astype(np.complex128)
+    close(gr.cpu().numpy(), 0.1 * vv, 1e-6, "empty batch: gradient")
+    assert loss.item() == pytest.approx(0.05 * np.vdot(vv, vv).real, rel=1e-6)
+    assert np.all(dg.cpu().numpy() == np.float32(0.1))
+
+
 @pytest.mark.parametrize("interp", [0, 1])
 def test_exact_diag_and_features_parity(b, interp):
     grid_o, opt_o, P, vol, img = make_case(M=36, n=37, seed=31, interp=interp)

@@ -97,13 +97,17 @@ def test_queued_probes_leave_the_run_unchanged(E):
     of 32 per epoch) feeds the same poses and images as the plain loop."""
     ds = E.make_dataset(32, 1000, 20, 14, float("inf"))
     v_star, _, _ = E.ground_truth(ds)
-    a = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9)
-    b = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9, queue_probes=False)
+    a = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9, fused=False)
+    b = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9, queue_probes=False,
+                  fused=False)
+    # and the one-kernel gradient and probe product (no queue) on the same run
+    c = E.run_arm(ds, v_star, "hutchinson", 32, max_epochs=2, eval_every=5, target=1e-9)
     assert a.iterations == b.iterations == 62
     # float atomics differ between the runs; a batch whose images and poses
     # did not belong together would move the errors far beyond this
-    ea, eb = [e[2] for e in a.errors], [e[2] for e in b.errors]
+    ea, eb, ec = [e[2] for e in a.errors], [e[2] for e in b.errors], [e[2] for e in c.errors]
     assert len(ea) == len(eb) and max(abs(x - y) / y for x, y in zip(ea, eb)) < 1e-3
+    assert c.iterations == 62 and len(ec) == len(ea) and max(abs(x - y) / y for x, y in zip(ea, ec)) < 1e-3
 
 
 def test_checkpoint_resume_is_bit_exact(E, tmp_path):
