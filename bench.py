@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=192, help="images in the oracle's timed sample")
     ap.add_argument("--deterministic", action="store_true")
+    ap.add_argument("--separate", action="store_true",
+                    help="Hutchinson arm in two calls (gradient, probe product queued behind the line search) "
+                         "instead of the one-kernel gradient and probe product")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-2 comparison of the SGD arms")
     return ap.parse_args()
 
@@ -106,7 +109,7 @@ def main():
     lam = 1e-2
     alpha = B.threshold_alpha(grid, optics, rot_d, df_d, lam).item()
     v0 = torch.zeros_like(v_true)
-    cfg = Alg1Config(deterministic=args.deterministic)
+    cfg = Alg1Config(deterministic=args.deterministic, fused=not args.separate)
     run = Alg1Runner(grid, optics, "hutchinson", scale, lam, alpha, cfg, v0, batch=Bsz)
     run_fused = run.fused  # gradient and probe product in one kernel (fast mode)
 
@@ -288,7 +291,8 @@ def main():
                                "Gaussian blobs, N=%d, trilinear, CTF 300kV/Cs2.7/A0.1, defocus 1-3um"
                                % (", gradient and probe product in one kernel" if run_fused else "", Bsz, M, M, nb,
                                   M, W.n_blobs, N),
-                   "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic)},
+                   "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic),
+                   "fused_gradient_probe": bool(run_fused)},
         "fwd_adj_images_per_s": round(fwd_adj, 1),
         "fwd_adj_roofline": fwd_adj_roofline,
         "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},

@@ -205,8 +205,10 @@ int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const cs
  * trilinear grids without in-plane shifts one brick kernel computes the
  * gradient and the first probe pair's product in one pass over the pixels
  * (further pairs, nearest-neighbour grids and shifted poses take the two
- * separate paths).  Results equal those of the two calls up to the order of
- * float additions.
+ * separate paths).  Results equal those of the two calls up to rounding:
+ * the gradient and loss up to the order of float additions, the diagonal to
+ * about 1e-5 relative (its 32-bit fixed-point sums take each contribution
+ * after the receiving voxel's probe signs are applied, as one number).
  *   Arguments as in csg_gradient and csg_hutchinson_diag; grad_out and
  *   diag_out must not alias vol or each other.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_GRADIENT_HUTCHINSON). */
