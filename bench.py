@@ -27,7 +27,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -188,25 +187,16 @@ def main():
     ms = {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in calls.items()}
     fwd_adj = Bsz / ((ms["project"] + ms["backproject"]) * 1e-3)
 
-    # footprint model (bytes per image): gather 8U, scatter read-modify-write
-    # 16U, image read 8P, image write 8 M^2
-    model = {
-        "gradient": 8 * P + 24 * U,
-        "hutchinson_probe": 24 * U * math.ceil(cfg.n_probe / 2),
-        "gradient_probe": 8 * P + 24 * U + 24 * U,
-        "armijo_project": 8 * P + 8 * U,
-        "project": 8 * M * M + 8 * U,
-        "backproject": 8 * P + 16 * U,
-    }
     # dominant kernel of the timed steps: algorithmic bytes per launch (the
     # per-image footprint times the images of one launch) over its average
     # event-timed launch duration
+    # (footprint model: image read 8P, gather 8U, scatter read-modify-write
+    # 16U; a probe pair generated from its hash costs no gather bytes)
     per_image = {
         "gradient": 8 * P + 24 * U,  # image read, gather, read-modify-write
-        "hvp": 24 * U,  # gather of the packed probe pair, read-modify-write
-        # both: the gradient's bytes and the probe product's (its gather and
-        # read-modify-write; the two operators act on different volumes)
-        "gradient_probe": 8 * P + 24 * U + 24 * U,
+        "hvp": 16 * U,  # the packed probe pair's read-modify-write
+        # both: the gradient's bytes and the probe pair's read-modify-write
+        "gradient_probe": 8 * P + 24 * U + 16 * U,
         "project": 8 * P + 8 * U,  # Armijo forward: image read, gather (loss only)
     }
     dominant = max(kern, key=lambda k: kern[k][0])
