@@ -819,9 +819,11 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
                 int t = threadIdx.x + k * kBT;
-                // in the forward mode (80-register budget) recomputed per item
-                // instead of being kept live across the item loop
-                if (MODE == kBProject) asm volatile("" : "+v"(t));
+                // recomputed per item instead of being kept live across the
+                // item loop: in the forward mode (80-register budget) and the
+                // fused mode (whose 128 registers the pixel loop fills; kept
+                // live, these coordinates were spilled and reloaded per item)
+                if (MODE == kBProject || PROBE2) asm volatile("" : "+v"(t));
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
                 hv[k] = make_float2(0.f, 0.f);
@@ -836,7 +838,8 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < HPT; ++k) {
-                    const int t = threadIdx.x + k * kBT;
+                    int t = threadIdx.x + k * kBT;
+                    asm volatile("" : "+v"(t));
                     if (t < HALO) {
                         const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                         const float2 z = probe_value(s_zmask[t / BX], hx, a.probe_has_b);
@@ -846,7 +849,8 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
             }
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
-                const int t = threadIdx.x + k * kBT;
+                int t = threadIdx.x + k * kBT;
+                if (PROBE2) asm volatile("" : "+v"(t));
                 const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
                 if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
             }
