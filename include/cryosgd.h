@@ -182,15 +182,15 @@ int csg_rademacher(int64_t nvox, uint64_t seed, int64_t probe, float *z_out, voi
 
 /* Hutchinson's diagonal estimate D = mean_p z_p (.) H z_p (eq. (hutch)) over
  * the probes probe0 .. probe0 + n_probe - 1 (as csg_rademacher), with H the
- * minibatch Hessian of csg_hvp.  Two probes share one complex product, whose
- * adjoint sums are kept in 32-bit fixed point per component with a scale
- * from a worst-case bound (the probe entries are +-1): the estimate matches
- * the one formed with csg_hvp to about 1e-5 relative, far below its own
- * sampling noise.  The probes are regenerated from their hash wherever they
- * are read and never stored, and on trilinear grids each voxel's z (.) H z is
- * formed where the product is accumulated, so no volume of H z is stored
- * either (on nearest-neighbour grids the pair and its product are stored in
- * the workspace).
+ * minibatch Hessian of csg_hvp.  Two probes share one complex product.  The
+ * probes are regenerated from their hash wherever they are read and never
+ * stored; on trilinear grids each contribution to z (.) H z is formed where
+ * the product is scattered (multiplied by the receiving voxel's probe
+ * signs) and summed in 32-bit fixed point per voxel with a scale from a
+ * worst-case bound (the probe entries are +-1), so no volume of H z is
+ * stored either: the estimate matches the one formed with csg_hvp to about
+ * 1e-5 relative, far below its own sampling noise (on nearest-neighbour
+ * grids the pair and its product are stored in the workspace).
  *   diag_out device float [M^3], overwritten.
  *   workspace >= csg_workspace_bytes(grid, n, CSG_WS_HUTCHINSON). */
 int csg_hutchinson_diag(const csg_grid *grid, const csg_optics *optics, const csg_poses *poses,

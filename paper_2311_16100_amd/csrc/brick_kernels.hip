@@ -14,8 +14,9 @@
 //     fixed-point integers: in the gradient and the HVP both components
 //     of a contribution in one 64-bit word with wrap counters (CarryScale),
 //     elsewhere one 64-bit integer per component (ItemScale; the
-//     deterministic mode: FxScale; the probe HVP packs both components into
-//     one, see PackedScale: flushed after every chunk), and adds it to HBM
+//     deterministic mode: FxScale; the probe modes keep one 32-bit sum of
+//     z (.) H z per voxel, see PackedScale: flushed after every chunk), and
+//     adds it to HBM
 //     once per voxel at the end with global
 //     atomics (the upper faces of the extent belong to the neighbouring
 //     bricks, which other blocks may be flushing at the same time).  On gfx950
@@ -48,21 +49,19 @@
 //   kBHvp          accum += scale C^2 P z
 //   kBHvpProbe     diag += z (.) scale C^2 P z for a Rademacher probe pair z
 //                  (Hutchinson), generated from its hash while the brick is
-//                  staged: both components of a contribution go into one
-//                  64-bit integer LDS atomic as fixed-point numbers (see
-//                  PackedScale), and the flush multiplies each voxel's sums by
-//                  the probe signs and adds one real number to the diagonal
+//                  staged and kept as two halves per voxel; each contribution
+//                  is multiplied by the receiving voxel's probe signs at once,
+//                  so the accumulator holds z (.) H z itself, one 32-bit
+//                  fixed-point number per voxel (see PackedScale), added to
+//                  the diagonal after every chunk of images
 //   kBFeatures     accum += (C^2, 1) w: the CTF^2 weight and the plain weight
 //                  sum of every voxel (no image is read)
 //   kBSqDiag       diag += scale C^2 w^2: the exact diagonal of the data
 //                  Hessian (real accumulator; no image is read)
 //   kBGradProbe    kBGradient and kBHvpProbe of the same images in one pass
 //                  (the Hessian does not depend on v, so both visit the same
-//                  pixels with the same cells, weights and CTF values): the
-//                  probe pair is staged as halves beside the volume, and each
-//                  contribution to z (.) H z is multiplied by the receiving
-//                  voxel's probe signs at once, so its accumulator holds one
-//                  32-bit fixed-point number per voxel (no in-plane shifts)
+//                  pixels with the same cells, weights and CTF values; no
+//                  in-plane shifts)
 #include <type_traits>
 
 #include "carry.h"
@@ -124,6 +123,11 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #endif
 #ifndef CSG_RUNCAP_SHIFT_CUT
 #define CSG_RUNCAP_SHIFT_CUT 384
+#endif
+// the probe HVP, which stages only the probe pair and keeps one 32-bit sum
+// per voxel, takes this many more run-table entries
+#ifndef CSG_RUNCAP_PROBE_EXTRA
+#define CSG_RUNCAP_PROBE_EXTRA 4608
 #endif
 #ifndef CSG_BRICK_WAVES_GH
 #define CSG_BRICK_WAVES_GH 4
@@ -445,26 +449,26 @@ __device__ __forceinline__ double rint_scaled(float e) {
     return rint((double)fminf(fmaxf(e, -2.0f), 2.0f) * 0x1p32);
 }
 
-// Fixed-point packing of a complex contribution for the 64-bit integer LDS
-// accumulator.  Each component is rounded to an integer multiple of 1/S and the
-// pair is added as re + im 2^32; the 64-bit sum is exact, and since both
-// component sums stay below 2^31 in magnitude they are recovered exactly: re
-// is the low word read as a signed integer, im the rest shifted down.
+// Fixed-point scale of the probe modes' LDS accumulator of z (.) H z for a
+// Rademacher pair z = z_a + i z_b.  The pixel's value is val = scale C^2
+// (P z)_pixel, and corner c of its stencil receives w_c (z_a(c) val.x +
+// z_b(c) val.y), the contribution to z (.) H z of the voxel it lands in,
+// rounded to an integer multiple of 1/S and added to that voxel's signed
+// 32-bit integer.
 //
-// The bound: a contribution is w val with val = scale C^2 (P z)_pixel, so
-// |val| <= V = |scale| max|z| over the staged brick (|C| <= 1 and the
-// trilinear weights sum to 1).  A voxel receives from one image at most
-// the pixels of the plane lattice inside its 2x2x2 neighbourhood, whose section
-// has area at most 4 sqrt(2): at most 13 pixels (Pick's theorem; 16 is used),
-// each with weight <= 1.
-// Over a chunk of at most 128 images (the probe mode flushes after each) a
-// component sum is therefore below
-// 2048 V = B, and S = 2^e with B S <= 2^30 keeps every sum (and every rounded
-// contribution) below 2^30.  The rounding error is at most 1/(2S) per
-// contribution, i.e. 2^-31 B (relative 5e-10 of B).  Because B is a worst
-// case, the result is about 1e-5 relative (measured), well below the noise of
-// a two-probe Hutchinson estimate; the gradient and the general HVP, whose
-// sums need float accuracy, keep one 64-bit integer per component.
+// The bound: |z_a(c) val.x + z_b(c) val.y| <= |val.x| + |val.y| <= V =
+// |scale| (|z_a| + |z_b|) = 2 |scale| (|C| <= 1 and the trilinear weights
+// sum to 1), and w_c <= 1.  A voxel receives from one image at most the
+// pixels of the plane lattice inside its 2x2x2 neighbourhood, whose section
+// has area at most 4 sqrt(2): at most 13 pixels (Pick's theorem; 16 is
+// used).  Over a chunk of at most 128 images (the probe modes flush after
+// each) a voxel's sum is therefore below 2048 V = B, and S = 2^e with
+// B S <= 2^30 keeps every sum (and every rounded contribution) below 2^30.
+// The rounding error is at most 1/(2S) per contribution, i.e. 2^-31 B
+// (relative 5e-10 of B).  Because B is a worst case, the result is about
+// 1e-5 relative (measured), well below the noise of a two-probe Hutchinson
+// estimate; the gradient and the general HVP, whose sums need float
+// accuracy, keep exact 64-bit sums.
 // x rounded to an integer, halves upwards (floor(x + 0.5) in one
 // instruction; |x| < 2^31)
 __device__ __forceinline__ int round_half_up(float x) {
@@ -488,19 +492,6 @@ struct PackedScale {
         p.S = ldexpf(1.f, e);
         p.invS = ldexpf(1.f, -e);
         return p;
-    }
-    // re and im already carry the factor S (S is a power of two, so scaling
-    // the value once per pixel instead of every corner term gives the same
-    // products)
-    __device__ __forceinline__ unsigned long long pack_scaled(float re, float im) const {
-        const int qr = round_half_up(re), qi = round_half_up(im);
-        return (unsigned long long)(long long)qr + ((unsigned long long)(unsigned)qi << 32);
-    }
-    __device__ __forceinline__ void unpack(unsigned long long v, float &re, float &im) const {
-        const int lo = (int)(unsigned)v;
-        const long long hi = ((long long)v - (long long)lo) >> 32;
-        re = (float)lo * invS;
-        im = (float)(int)hi * invS;
     }
 };
 
@@ -656,25 +647,28 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
     // gathered volume; z (.) H z in an accumulator of its own, flushed after
     // every chunk)
     constexpr bool PROBE2 = MODE == kBGradProbe;
-    constexpr bool GATHER = MODE == kBProject || is_grad(MODE) || is_hvp(MODE);
+    // the probe modes (probe HVP, fused): the Rademacher pair staged as two
+    // halves per voxel, z (.) H z accumulated as one signed 32-bit
+    // fixed-point number per voxel (each contribution multiplied by the
+    // receiving voxel's probe signs), flushed into the diagonal after every
+    // chunk of images
+    constexpr bool PSIGNED = MODE == kBHvpProbe || PROBE2;
+    // the modes that gather a staged volume (the probe HVP gathers only the pair)
+    constexpr bool GATHER = MODE == kBProject || is_grad(MODE) || MODE == kBHvp;
     constexpr bool SCATTER = MODE != kBProject;
     constexpr bool READS_IMG = MODE == kBProject || MODE == kBBackproject || is_grad(MODE);
     // the in-plane shift is compiled in only where a launch carries shifts
     constexpr bool SHIFTED = SHIFT && READS_IMG;
     constexpr int IMGDAT = SHIFTED ? 10 : 8;
     constexpr int CHUNK = MODE == kBProject ? CHUNK_FWD : CHUNK_ADJ;
-    // Packed accumulation (see PackedScale): both components of a contribution
-    // go into one 64-bit integer LDS atomic, as 32-bit fixed-point numbers with
-    // a per-item power-of-two scale.  Only the probe HVP packs.
-    constexpr bool PK_ALWAYS = MODE == kBHvpProbe;
     // fixed-point LDS accumulators: the deterministic modes (one 64-bit
     // integer per component, one launch-wide scale, FxScale) and the fast
-    // modes other than the packed probe (a scale per work item: the carry
+    // modes other than the probe HVP (a scale per work item: the carry
     // accumulator of CarryScale in gradient and HVP, one 64-bit integer per
     // component with ItemScale in the backproject, features and
     // squared-weight modes; the flush adds floats).  On gfx950 the LDS 64-bit integer atomic
     // add is cheaper than the double one.
-    constexpr bool QLDS = FX || (CSG_LDS_FIXED && SCATTER && !PK_ALWAYS);
+    constexpr bool QLDS = FX || (CSG_LDS_FIXED && SCATTER && MODE != kBHvpProbe);
     constexpr bool QITEM = QLDS && !FX;
     // the packed accumulator with wrap counters (see CarryScale)
     // (gradient and HVP; in backproject, with its 80-register budget, the
@@ -685,17 +679,17 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
     // and, where images are read (backproject, gradient), a bound on their
     // values: a guess, checked against every value read; an item that meets
     // a larger one is redone with its exact maximum (see the retry below)
-    constexpr bool STAGE_MAX = PK_ALWAYS || (QITEM && GATHER);
+    constexpr bool STAGE_MAX = QITEM && GATHER;
     constexpr bool XRETRY = QITEM && READS_IMG;
+    // the complex volume accumulator (all adjoint modes but the probe HVP)
+    constexpr bool ACC = SCATTER && MODE != kBHvpProbe;
     __shared__ float2 vh[GATHER ? XN : 1];
-    __shared__ double acc_re[SCATTER ? XN : 1];
+    __shared__ double acc_re[ACC ? XN : 1];
     // (the carry accumulator keeps one 32-bit counter word per voxel here)
     constexpr int XN_IM = QCARRY ? (XN + 1) / 2 : XN;
-    __shared__ double acc_im[SCATTER && !PK_ALWAYS ? XN_IM : 1];
-    // the packed accumulator shares the storage of acc_re
-    unsigned long long *const acc_pk = reinterpret_cast<unsigned long long *>(acc_re);
-    // so do the fixed-point accumulators of the deterministic mode (zero bits
-    // are zero in both)
+    __shared__ double acc_im[ACC ? XN_IM : 1];
+    // the fixed-point accumulators of the deterministic mode share the
+    // storage (zero bits are zero in both)
     unsigned long long *const acc_qre = reinterpret_cast<unsigned long long *>(acc_re);
     unsigned long long *const acc_qim = reinterpret_cast<unsigned long long *>(acc_im);
     // and the carry accumulator: its words in acc_re, its counters in acc_im
@@ -703,17 +697,15 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
     int *const c_word = reinterpret_cast<int *>(acc_im);
     __shared__ unsigned s_wmax[kBT / 64];
     __shared__ unsigned s_xmax[kBT / 64];
-    // probe HVP: signs of the staged rows ([row][probe]; see the staging)
-    // (the fused mode keeps them in the run table's storage, see below)
-    __shared__ uint32_t s_zmask_own[MODE == kBHvpProbe ? BX * BX : 1][2];
-    // fused mode: the staged probe pair (z_a, z_b as two halves, exact for
+    // probe modes: the staged probe pair (z_a, z_b as two halves, exact for
     // 0 and +-1) and the sums of z (.) H z, one fixed-point integer per voxel
     // (the probe signs of the receiving voxel are applied to each
     // contribution, so the flush needs no signs)
-    __shared__ uint32_t zq[PROBE2 ? XN : 1];
-    __shared__ int acc_d[PROBE2 ? XN : 1];
+    __shared__ uint32_t zq[PSIGNED ? XN : 1];
+    __shared__ int acc_d[PSIGNED ? XN : 1];
     constexpr int WI = Win<MODE>::WI, ROWCAP = Win<MODE>::ROWCAP, RPT = Win<MODE>::RPT;
-    constexpr int RUNCAP = Win<MODE>::RUNCAP + (QCARRY && !PROBE2 ? CSG_RUNCAP_CARRY_EXTRA : 0) -
+    constexpr int RUNCAP = Win<MODE>::RUNCAP + (QCARRY && !PROBE2 ? CSG_RUNCAP_CARRY_EXTRA : 0) +
+                           (MODE == kBHvpProbe ? CSG_RUNCAP_PROBE_EXTRA : 0) -
                            (SHIFTED && MODE == kBGradient ? CSG_RUNCAP_SHIFT_CUT : 0);
     constexpr int RUN = Win<MODE>::RUN;
     __shared__ ImgSlot slot[WI];
@@ -724,10 +716,11 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
     //             y = (kx0 + 32768) | (ky + 32768) << 16
     __shared__ int2 seg[ROWCAP];
     __shared__ __align__(8) unsigned short run2row[RUNCAP];
-    // the fused mode's row masks live only while a brick is staged, when the
-    // run table is unused (barriers separate the two uses)
-    static_assert(!PROBE2 || RUNCAP * sizeof(unsigned short) >= BX * BX * 2 * sizeof(uint32_t), "run table too small");
-    uint32_t(*const s_zmask)[2] = PROBE2 ? reinterpret_cast<uint32_t(*)[2]>(run2row) : s_zmask_own;
+    // probe modes: the signs of the staged rows ([row][probe]; see
+    // probe_row_mask) live only while a brick is staged, when the run table
+    // is unused (barriers separate the two uses)
+    static_assert(!PSIGNED || RUNCAP * sizeof(unsigned short) >= BX * BX * 2 * sizeof(uint32_t), "run table too small");
+    uint32_t(*const s_zmask)[2] = reinterpret_cast<uint32_t(*)[2]>(run2row);
     __shared__ int wave_sums[kBT / 64];
     __shared__ int s_item;
     __shared__ double red[16];
@@ -798,41 +791,30 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
         const bool holds_img = (int)threadIdx.x < min(CHUNK, last - first0);
         int my_ii = 0;
         if (holds_img) my_ii = list[first0 + threadIdx.x];
-        if (GATHER) {
+        if (GATHER || PSIGNED) {
             // the extended brick of the gathered volume; every load is issued
             // before the first LDS store
             constexpr int HALO = BX * BX * BX;
             constexpr int HPT = (HALO + kBT - 1) / kBT;
-            float2 hv[HPT];
-            if (MODE == kBHvpProbe) {
-                // the probe pair is generated, not loaded (see probe_row_mask);
-                // then every thread expands its voxels
-                if ((int)threadIdx.x < 2 * BX * BX)
-                    s_zmask[threadIdx.x >> 1][threadIdx.x & 1] = probe_row_mask(a, o, M, threadIdx.x >> 1, threadIdx.x & 1);
-                __syncthreads();
+            float2 hv[GATHER ? HPT : 1];
+            if constexpr (GATHER) {
 #pragma unroll
                 for (int k = 0; k < HPT; ++k) {
-                    const int t = threadIdx.x + k * kBT;
-                    hv[k] = t < HALO ? probe_value(s_zmask[t / BX], t % BX, a.probe_has_b) : make_float2(0.f, 0.f);
+                    int t = threadIdx.x + k * kBT;
+                    // recomputed per item instead of being kept live across
+                    // the item loop, where the pixel loop's registers are
+                    // short (kept live, these coordinates were spilled and
+                    // reloaded from scratch memory per item)
+                    asm volatile("" : "+v"(t));
+                    const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
+                    const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
+                    hv[k] = make_float2(0.f, 0.f);
+                    if (t < HALO && qx < M && qy < M && qz < M) hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
                 }
-            } else {
-#pragma unroll
-            for (int k = 0; k < HPT; ++k) {
-                int t = threadIdx.x + k * kBT;
-                // recomputed per item instead of being kept live across the
-                // item loop: in the forward mode (80-register budget) and the
-                // fused mode (whose 128 registers the pixel loop fills; kept
-                // live, these coordinates were spilled and reloaded per item)
-                if (MODE == kBProject || PROBE2) asm volatile("" : "+v"(t));
-                const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
-                const int qx = o[0] + hx, qy = o[1] + hy, qz = o[2] + hz;
-                hv[k] = make_float2(0.f, 0.f);
-                if (t < HALO && qx < M && qy < M && qz < M) hv[k] = a.src[((int64_t)qz * M + qy) * M + qx];
             }
-            }
-            if (PROBE2) {
-                // the probe pair beside the volume: masks while the volume's
-                // loads are in flight, then the expanded values
+            if (PSIGNED) {
+                // the probe pair is generated, not loaded: row masks (while
+                // the volume's loads are in flight), then the values
                 if ((int)threadIdx.x < 2 * BX * BX)
                     s_zmask[threadIdx.x >> 1][threadIdx.x & 1] = probe_row_mask(a, o, M, threadIdx.x >> 1, threadIdx.x & 1);
                 __syncthreads();
@@ -847,14 +829,16 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                     }
                 }
             }
+            if constexpr (GATHER) {
 #pragma unroll
-            for (int k = 0; k < HPT; ++k) {
-                int t = threadIdx.x + k * kBT;
-                if (PROBE2) asm volatile("" : "+v"(t));
-                const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
-                if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
+                for (int k = 0; k < HPT; ++k) {
+                    int t = threadIdx.x + k * kBT;
+                    asm volatile("" : "+v"(t));
+                    const int hx = t % BX, hy = (t / BX) % BX, hz = t / (BX * BX);
+                    if (t < HALO) vh[(hz * XR + hy) * XR + hx] = hv[k];
+                }
             }
-            if (STAGE_MAX) {
+            if constexpr (STAGE_MAX) {
                 // bound on |z| over the staged brick (|re| + |im| >= modulus),
                 // per wave; combined after the next barrier.  The maximum is
                 // taken over the float bits with the sign cleared, which
@@ -883,16 +867,19 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
             for (int d = 0; d < IMGDAT - 1; ++d) imgdat[threadIdx.x][1 + d] = e[d];
         };
         if (holds_img) stage_image(my_ii);
-        if (SCATTER && PK_ALWAYS) {
-            for (int t = threadIdx.x; t < XN; t += kBT) acc_pk[t] = 0ull;
-        } else if (SCATTER) {
+        if (SCATTER) {
             for (int t = threadIdx.x; t < XN; t += kBT) {
-                acc_re[t] = 0.0;
-                if (t < XN_IM) acc_im[t] = 0.0;
-                if (PROBE2) acc_d[t] = 0;
+                if (ACC) {
+                    acc_re[t] = 0.0;
+                    if (t < XN_IM) acc_im[t] = 0.0;
+                }
+                if (PSIGNED) acc_d[t] = 0;
             }
         }
-        PackedScale pk;  // set in the first window (after a barrier)
+        // the probe modes' fixed-point scale: |z_a| + |z_b| <= 2 (1 without z_b)
+        const PackedScale pk = PSIGNED ? PackedScale::make(fabsf(PROBE2 ? a.scale2 : a.scale) *
+                                                           (a.probe_has_b ? 2.f : 1.f))
+                                       : PackedScale{};
         QScale qs;       // likewise
         // the image-value guess of the item: twice the block's maximum so far
         // (the exponent raised by one, at most the largest float; a NaN or an
@@ -918,17 +905,13 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
 
         // flush: every voxel of the extended brick that lies in the grid is
         // added to HBM with global atomics (voxels that received nothing are
-        // skipped); the probe mode flushes after every chunk and clears its
-        // packed sums as it goes
+        // skipped)
         auto flush_voxels = [&]() {
             constexpr int NV = BX * BX * BX;
             for (int t = threadIdx.x; t < NV; t += kBT) {
                 const int tx = t % BX, ty = (t / BX) % BX, tz = t / (BX * BX);
                 const int li = (tz * XR + ty) * XR + tx;
-                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) {
-                    if (PK_ALWAYS) acc_pk[li] = 0ull;  // cleared for the next chunk
-                    continue;
-                }
+                if (o[0] + tx >= M || o[1] + ty >= M || o[2] + tz >= M) continue;
                 const int64_t gi = ((int64_t)(o[2] + tz) * M + (o[1] + ty)) * M + (o[0] + tx);
                 if (FX) {
                     const unsigned long long qr = acc_qre[li], qi = acc_qim[li];
@@ -967,19 +950,6 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                     }
                     continue;
                 }
-                if (PK_ALWAYS) {
-                    // the sums are (H z_a, H z_b) at this voxel; z (.) H z of
-                    // the pair, z_a (H z_a) + z_b (H z_b), goes straight into
-                    // the diagonal (signs from the staged masks)
-                    float re, im;
-                    pk.unpack(acc_pk[li], re, im);
-                    acc_pk[li] = 0ull;  // cleared for the next chunk
-                    const int row = tz * BX + ty;
-                    float d = ((s_zmask[row][0] >> tx) & 1u) ? -re : re;
-                    if (a.probe_has_b) d += ((s_zmask[row][1] >> tx) & 1u) ? -im : im;
-                    if (d != 0.f) atomicAdd(a.accum_real + gi, d);
-                    continue;
-                }
                 const float re = (float)acc_re[li];
                 if (MODE == kBSqDiag) {
                     if (re != 0.f) atomicAdd(a.accum_real + gi, re);
@@ -990,8 +960,8 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                 }
             }
         };
-        // fused mode: the probe pair's sums of one chunk, z (.) H z into the
-        // diagonal as in the probe HVP's flush, cleared for the next chunk
+        // probe modes: the sums of z (.) H z of one chunk into the diagonal,
+        // cleared for the next chunk
         auto flush_probe = [&]() {
             constexpr int NV = BX * BX * BX;
             for (int t = threadIdx.x; t < NV; t += kBT) {
@@ -1029,9 +999,6 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
 #pragma unroll
                         for (int w = 0; w < kBT / 64; ++w) zbits = max(zbits, s_wmax[w]);
                         const float zb = __uint_as_float(__builtin_amdgcn_readfirstlane(zbits));
-                        if (PK_ALWAYS) pk = PackedScale::make(fabsf(a.scale) * zb);
-                        // the fused probe pair: |z_a| + |z_b| <= 2 (1 without z_b)
-                        if (PROBE2) pk = PackedScale::make(fabsf(a.scale2) * (a.probe_has_b ? 2.f : 1.f));
                         if (QITEM) {
                             const unsigned gb = __builtin_amdgcn_readfirstlane(s_guess);
                             const double xg = READS_IMG ? (double)__uint_as_float(gb) : 0.0;
@@ -1209,20 +1176,22 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                         // index of the base corner in the extended brick; the
                                         // eight corners lie in it
                                         const int lb = (l[2] * XR + l[1]) * XR + l[0];
-                                        // fused mode: the probe pair at the corners and P z
-                                        uint32_t zc[PROBE2 ? 8 : 1];
+                                        // probe modes: the probe pair at the corners and P z
+                                        uint32_t zc[PSIGNED ? 8 : 1];
                                         float2 pz = make_float2(0.f, 0.f);
-                                        if (GATHER) {
+                                        if (GATHER || PSIGNED) {
                                             // staged voxels outside the grid hold zeros, which
                                             // drops those corners
 #pragma unroll
                                             for (int c = 0; c < 8; ++c) {
                                                 const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
                                                 const float w = wx[ax] * wy[ay] * wz[az];
-                                                const float2 v = vh[lb + az * XP + ay * XR + ax];
-                                                acc.x = fmaf(w, v.x, acc.x);
-                                                acc.y = fmaf(w, v.y, acc.y);
-                                                if (PROBE2) {
+                                                if (GATHER) {
+                                                    const float2 v = vh[lb + az * XP + ay * XR + ax];
+                                                    acc.x = fmaf(w, v.x, acc.x);
+                                                    acc.y = fmaf(w, v.y, acc.y);
+                                                }
+                                                if (PSIGNED) {
                                                     zc[c] = zq[lb + az * XP + ay * XR + ax];
                                                     pz.x = fmaf(w, half_lo(zc[c]), pz.x);
                                                     pz.y = fmaf(w, half_hi(zc[c]), pz.y);
@@ -1264,7 +1233,7 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                             const float fct = a.scale * C;
                                             const float2 rt = cmul_conj(rr, T);
                                             val = make_float2(fct * rt.x, fct * rt.y);
-                                        } else if (is_hvp(MODE)) {
+                                        } else if (MODE == kBHvp) {
                                             const float fct = a.scale * C * C;
                                             val = make_float2(fct * acc.x, fct * acc.y);
                                         } else if (MODE == kBFeatures) {
@@ -1272,7 +1241,6 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                         } else if (MODE == kBSqDiag) {
                                             val = make_float2(a.scale * C * C, 0.0f);
                                         }
-                                        if (PK_ALWAYS) val = make_float2(val.x * pk.S, val.y * pk.S);
                                         if (QCARRY) {
                                             // the packed atomics of CARRY_GROUP corners, then one
                                             // look at their old words (see CarryScale)
@@ -1308,24 +1276,7 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                                     }
                                                 }
                                             }
-                                            if (PROBE2 && attempt == 0) {
-                                                // fused mode, after the gradient's atomics: the
-                                                // probe pair's product scale2 C^2 P z at this
-                                                // pixel; corner c receives w_c (z_a(c) re +
-                                                // z_b(c) im) of z (.) H z, one fixed-point integer
-                                                // (the bound of PackedScale); a retried item
-                                                // (attempt > 0) has its probe sums flushed already
-                                                const float fz = a.scale2 * C * C;
-                                                const float px = fz * pz.x * pk.S, py = fz * pz.y * pk.S;
-#pragma unroll
-                                                for (int c = 0; c < 8; ++c) {
-                                                    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-                                                    const float w = wx[ax] * wy[ay] * wz[az];
-                                                    const float d = fmaf(half_lo(zc[c]), px, half_hi(zc[c]) * py);
-                                                    atomicAdd(&acc_d[lb + az * XP + ay * XR + ax], round_half_up(w * d));
-                                                }
-                                            }
-                                        } else if (SCATTER) {
+                                        } else if (ACC) {
                                             // all eight corners; a corner beyond the grid edge
                                             // lands in a slot that is never written back
 #pragma unroll
@@ -1337,8 +1288,6 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                                     atomicAdd(&acc_qre[li], fx_quant(w * w * val.x, qs.S));
                                                 } else if (MODE == kBSqDiag) {
                                                     atomicAdd(&acc_re[li], (double)(w * w * val.x));
-                                                } else if (PK_ALWAYS) {
-                                                    atomicAdd(&acc_pk[li], pk.pack_scaled(w * val.x, w * val.y));
                                                 } else if (QLDS) {
                                                     const double S = FX ? fxS : qs.S;
                                                     atomicAdd(&acc_qre[li], fx_quant(w * val.x, S));
@@ -1347,6 +1296,24 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                                                     atomicAdd(&acc_re[li], (double)(w * val.x));
                                                     atomicAdd(&acc_im[li], (double)(w * val.y));
                                                 }
+                                            }
+                                        }
+                                        if (PSIGNED && attempt == 0) {
+                                            // probe modes (in the fused mode after the
+                                            // gradient's atomics): the probe pair's product
+                                            // scale C^2 P z at this pixel; corner c receives
+                                            // w_c (z_a(c) re + z_b(c) im) of z (.) H z, one
+                                            // fixed-point integer (the bound of PackedScale); a
+                                            // retried item (attempt > 0) has its probe sums
+                                            // flushed already
+                                            const float fz = (PROBE2 ? a.scale2 : a.scale) * C * C;
+                                            const float px = fz * pz.x * pk.S, py = fz * pz.y * pk.S;
+#pragma unroll
+                                            for (int c = 0; c < 8; ++c) {
+                                                const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+                                                const float w = wx[ax] * wy[ay] * wz[az];
+                                                const float d = fmaf(half_lo(zc[c]), px, half_hi(zc[c]) * py);
+                                                atomicAdd(&acc_d[lb + az * XP + ay * XR + ax], round_half_up(w * d));
                                             }
                                         }
                                     }
@@ -1358,9 +1325,8 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
                         __syncthreads();  // the table is rebuilt (and, after the last pass, the window)
                     }
                 }
-                // the probe mode's packed sums hold one chunk (see PackedScale)
-                if (PK_ALWAYS) flush_voxels();
-                if (PROBE2 && attempt == 0) flush_probe();
+                // the probe modes' 32-bit sums hold one chunk (see PackedScale)
+                if (PSIGNED && attempt == 0) flush_probe();
             }  // chunks
             if (!XRETRY) break;
             // the item's largest image value; above the guess, a fixed-point sum
@@ -1396,7 +1362,7 @@ __global__ __launch_bounds__(kBT, (is_grad(MODE) || is_hvp(MODE)) ? CSG_BRICK_WA
             }
         }  // attempts
 
-        if (SCATTER && !PK_ALWAYS) {
+        if (ACC) {
             __syncthreads();
             flush_voxels();
         }
