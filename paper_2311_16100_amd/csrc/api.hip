@@ -136,7 +136,8 @@ size_t csg_workspace_bytes(const csg_grid *grid, int64_t n, int32_t which) {
         // output); nearest neighbour: the product of a probe pair and the
         // stored pair
         case CSG_WS_HUTCHINSON: return kScalarBytes + (trilinear ? bricks : 2 * vol);
-        case CSG_WS_GRADIENT_HUTCHINSON: return kScalarBytes + (trilinear ? bricks : 2 * vol);
+        // the larger of the two (nearest-neighbour grids run the two calls)
+        case CSG_WS_GRADIENT_HUTCHINSON: return kScalarBytes + (trilinear || bricks > 2 * vol ? bricks : 2 * vol);
         default: return 0;
     }
 }

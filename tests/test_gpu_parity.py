@@ -282,6 +282,20 @@ def test_gradient_hutchinson_many_images(b, M, n, blob):
     close(dg.cpu().numpy(), want_d, 1e-4, "hutchinson")
 
 
+def test_gradient_hutchinson_nearest_neighbour_many_images(b):
+    """Nearest-neighbour grids take the two separate calls in the one
+    workspace; at 16^3 with 2048 images the gradient's brick tables are the
+    larger part of it."""
+    grid_o, opt_o, P, vol, img = make_case(M=16, n=2048, seed=25, interp=0)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    ws = b.alloc_workspace(g, 2048, b.CSG_WS_GRADIENT_HUTCHINSON, v.device)
+    gr, dg = b.gradient_hutchinson(g, o, rot, df, v, x, 0.5, 0.1, 2, 6, probe0=1, workspace=ws)
+    close(gr.cpu().numpy(), oracle.gradient(grid_o, opt_o, P, vol, img * _disk(grid_o)[None], 0.5, 0.1), 1e-4,
+          "gradient")
+    close(dg.cpu().numpy(), oracle.hutchinson_diag(grid_o, opt_o, P, 2, 6, 0.5, 0.1, probe0=1), 1e-4, "hutchinson")
+
+
 def test_gradient_hutchinson_with_shifts_and_empty_batch(b):
     """In-plane shifts take the separate gradient and probe kernels (the
     Hessian ignores the shifts); an empty batch leaves the gradient lambda v,
