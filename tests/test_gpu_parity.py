@@ -282,6 +282,20 @@ def test_gradient_hutchinson_many_images(b, M, n, blob):
     close(dg.cpu().numpy(), want_d, 1e-4, "hutchinson")
 
 
+def test_gradient_hutchinson_two_sub_batches(b):
+    """2100 images: two launches of the one-pass kernel (2048 + 52 images per
+    launch), each adding its gradient and probe sums."""
+    grid_o, opt_o, P, vol, img = make_case(M=24, n=2100, seed=26)
+    g, o = gpu_desc(b, grid_o, opt_o)
+    rot, df, v, x = to_dev(P.rot, P.defocus, vol, img)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gr, dg = b.gradient_hutchinson(g, o, rot, df, v, x, 0.3, 0.05, 2, 9, probe0=4, loss_out=loss)
+    img_d = img * _disk(grid_o)[None]
+    close(gr.cpu().numpy(), oracle.gradient(grid_o, opt_o, P, vol, img_d, 0.3, 0.05), 1e-4, "gradient")
+    assert loss.item() == pytest.approx(oracle.loss(grid_o, opt_o, P, vol, img_d, 0.3, 0.05), rel=1e-5)
+    close(dg.cpu().numpy(), oracle.hutchinson_diag(grid_o, opt_o, P, 2, 9, 0.3, 0.05, probe0=4), 1e-4, "hutchinson")
+
+
 def test_gradient_hutchinson_nearest_neighbour_many_images(b):
     """Nearest-neighbour grids take the two separate calls in the one
     workspace; at 16^3 with 2048 images the gradient's brick tables are the
