@@ -93,7 +93,10 @@ constexpr int kBT = 512;         // threads per brick block (8 waves)
 #define CSG_RUN_ADJ 2
 #endif
 #ifndef CSG_RUN_GRAD
-#define CSG_RUN_GRAD 1
+#define CSG_RUN_GRAD 2
+#endif
+#ifndef CSG_RUN_GP
+#define CSG_RUN_GP 1
 #endif
 #ifndef CSG_WI_ADJ
 #define CSG_WI_ADJ 32
@@ -432,11 +435,12 @@ constexpr int MAXLEN = MAXROWS + 8;  // bound on a row interval (same argument a
 // and runs per pass of the run -> row table.
 template <int MODE>
 struct Win {
-    // consecutive pixels of a row per lane: one for the forward mode and the
-    // gradient (whose packed accumulator waits on its atomics' old words,
-    // which leaves no registers for a second pixel's state), two for the
-    // other adjoint modes (measured fastest)
-    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : is_grad(MODE) ? CSG_RUN_GRAD : CSG_RUN_ADJ;
+    // consecutive pixels of a row per lane (measured fastest): one for the
+    // forward mode and the fused gradient and probe mode (whose two
+    // accumulators leave no registers for a second pixel's state), two for
+    // the adjoint modes, the gradient among them
+    static constexpr int RUN = MODE == kBProject ? CSG_RUN_FWD : MODE == kBGradProbe ? CSG_RUN_GP
+                             : MODE == kBGradient ? CSG_RUN_GRAD : CSG_RUN_ADJ;
     static constexpr int WI = MODE == kBProject ? CSG_WI_FWD : MODE == kBGradProbe ? CSG_WI_GP
                             : (MODE == kBGradient || is_hvp(MODE)) ? CSG_WI_GH : CSG_WI_ADJ;
     static constexpr int ROWCAP = WI * MAXROWS;          // row records per window
