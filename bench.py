@@ -122,13 +122,16 @@ def main():
         e.record()
         calls.setdefault(name, []).append((s, e))
 
-    def step(i):
+    def step(i, last=False):
+        # the next batch's work is queued during this step's line search,
+        # except on the last warmup and the last timed step: the timed region
+        # holds exactly the work of its own steps
         r, d, x = batches[i % nb]
-        rn, dn, _ = batches[(i + 1) % nb]
-        run.iteration(r, d, x, next_poses=(rn, dn))
+        rn, dn, xn = batches[(i + 1) % nb]
+        run.iteration(r, d, x, next_poses=None if last else (rn, dn), next_images=None if last else xn)
 
     for i in range(args.warmup):
-        step(i)
+        step(i, last=i == args.warmup - 1)
     torch.cuda.synchronize()
     calls.clear()
     # HIP events around every brick-kernel launch of the timed steps, on the
@@ -138,13 +141,16 @@ def main():
         B.timing_read(k)
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(args.warmup + i)
+        step(args.warmup + i, last=i == args.steps - 1)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
     B.timing_enable(False)
     kern = {k: B.timing_read(k) for k in ("gradient_probe", "gradient", "hvp", "project")}
     kern = {k: v for k, v in kern.items() if v[1] > 0}
     ms_per_step = 1e3 * t_steps / args.steps
+    # halvings of the timed steps' line searches (a rejected first trial also
+    # discards the next batch's queued results: that work is redone)
+    halvings_timed = int(sum(run.state.halvings[-args.steps:]))
     print("[bench] %d Alg.1 steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
 
     # per-call breakdown of the same step (separate, identical iterations)
@@ -282,7 +288,7 @@ def main():
                                % (", gradient and probe product in one kernel" if run_fused else "", Bsz, M, M, nb,
                                   M, W.n_blobs, N),
                    "global_batch": Bsz, "M": M, "deterministic": bool(args.deterministic),
-                   "fused_gradient_probe": bool(run_fused)},
+                   "fused_gradient_probe": bool(run_fused), "line_search_halvings": halvings_timed},
         "fwd_adj_images_per_s": round(fwd_adj, 1),
         "fwd_adj_roofline": fwd_adj_roofline,
         "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},

@@ -7,10 +7,16 @@ arithmetic step (gradient, Hessian-vector probes, the running mean and
 exponential average of the diagonal, thresholding, the step, the line-search
 losses) runs in the library's kernels.  The only host work is the line
 search's decision, which needs one read-back of four device scalars per trial.
-The Hutchinson probe product of the next batch does not depend on v (the
-Hessian of the least-squares loss is constant), so when the caller names the
-next batch's poses it is queued behind that read-back and the device keeps
-working while the host decides.
+The device keeps working while the host decides:
+  - two-call form: the Hutchinson probe product of the next batch does not
+    depend on v (the Hessian of the least-squares loss is constant), so when
+    the caller names the next batch's poses it is queued behind that
+    read-back;
+  - one-call form: when the caller names the next batch's poses and images,
+    its gradient and probe product are queued at the first trial point v'.
+    The first trial is usually accepted, and then v' is the next iterate and
+    the queued results are the next iteration's; after a rejected first
+    trial they are discarded and the next iteration forms its own.
 
 Arms (same loop, same step-size rule):
   "hutchinson"  D estimated on the fly from Rademacher probes (Algorithm 1)
@@ -80,11 +86,17 @@ class Alg1Runner:
         self.g = torch.empty_like(v0)
         self.v_new = torch.empty_like(v0)
         self.zHz = torch.empty((M, M, M), dtype=torch.float32, device=dev) if arm == "hutchinson" else None
-        self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" and not self.fused else None
-        self._queued = None  # (rot, defocus, k) of the probe product already in zHz_next
-        # scalars: [0] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data term of f(v')
-        self.sc = torch.zeros(4, dtype=torch.float64, device=dev)
-        self.sc_host = torch.zeros(4, dtype=torch.float64, pin_memory=True)
+        self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" else None
+        # one-call form: the next batch's gradient, formed at the first trial point
+        self.g_next = torch.empty_like(v0) if self.fused else None
+        # (rot, defocus, images or None, k) of the results already in zHz_next
+        # (and g_next, sc[4 - f_at] when images are named)
+        self._queued = None
+        # scalars: [f_at] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data
+        # term of f(v'), [4 - f_at] f of the queued next batch (f_at is 0 or 4)
+        self.f_at = 0
+        self.sc = torch.zeros(5, dtype=torch.float64, device=dev)
+        self.sc_host = torch.zeros(5, dtype=torch.float64, pin_memory=True)
         self.sc_ready = torch.cuda.Event()
         self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
                                          else B.CSG_WS_GRADIENT_HUTCHINSON if self.fused else B.CSG_WS_GRADIENT, dev)
@@ -116,25 +128,35 @@ class Alg1Runner:
         st.halvings = list(sd["halvings"])
         self._queued = None
 
-    def iteration(self, rot_I, df_I, x_I, next_poses=None) -> int:
+    def iteration(self, rot_I, df_I, x_I, next_poses=None, next_images=None) -> int:
         """One iteration on the batch (rot_I, df_I, x_I).  `next_poses` =
         (rot, defocus) of the next call's batch, if known: the Hutchinson arm
-        without the fused call then computes that batch's probe product during
-        this line search, and the next call uses it when it is given the same
-        two tensors."""
+        in its two-call form then computes that batch's probe product during
+        this line search; in its one-call form, given also `next_images`, it
+        computes that batch's gradient and probe product at the first trial
+        point.  The next call uses them when it is given the same tensors
+        (and, for the gradient, when the first trial was accepted)."""
         st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
         st.k += 1
         have_grad = False
         if self.arm == "hutchinson":
             q = self._queued
-            if q is not None and q[0] is rot_I and q[1] is df_I and q[2] == st.k:
+            if q is not None and q[0] is rot_I and q[1] is df_I and q[3] == st.k and q[2] is None:
                 self.zHz, self.zHz_next = self.zHz_next, self.zHz
+            elif q is not None and q[0] is rot_I and q[1] is df_I and q[3] == st.k and q[2] is x_I:
+                # gradient, f(v) and probe product of this batch at v, queued
+                # by the previous call at its accepted first trial point
+                self.zHz, self.zHz_next = self.zHz_next, self.zHz
+                self.g, self.g_next = self.g_next, self.g
+                self.f_at = 4 - self.f_at
+                have_grad = True
             elif self.fused:
                 # the gradient and z (.) H_I z for this iteration's probes
                 # (Algorithm 1: gradient and running-mean line) in one pass
                 B.gradient_hutchinson(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, cfg.n_probe,
                                       cfg.probe_seed, probe0=(st.k - 1) * cfg.n_probe, grad_out=self.g,
-                                      loss_out=self.sc[0:1], diag_out=self.zHz, workspace=self.ws_grad)
+                                      loss_out=self.sc[self.f_at:self.f_at + 1], diag_out=self.zHz,
+                                      workspace=self.ws_grad)
                 have_grad = True
             else:
                 # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
@@ -142,8 +164,9 @@ class Alg1Runner:
                                   probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
             self._queued = None
         if not have_grad:
-            B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g, loss_out=self.sc[0:1],
-                       deterministic=cfg.deterministic, workspace=self.ws_grad)
+            B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g,
+                       loss_out=self.sc[self.f_at:self.f_at + 1], deterministic=cfg.deterministic,
+                       workspace=self.ws_grad)
         eta = st.eta
         halvings = 0
         first = True
@@ -156,17 +179,33 @@ class Alg1Runner:
                       workspace=self.ws_proj)
             self.sc_host.copy_(self.sc, non_blocking=True)
             self.sc_ready.record()
-            if first and next_poses is not None and self.arm == "hutchinson" and not self.fused:
+            if first and next_poses is not None and self.arm == "hutchinson":
                 rn, dn = next_poses
-                B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
-                                  probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)
-                self._queued = (rn, dn, st.k + 1)
+                if not self.fused:
+                    B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
+                                      probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)
+                    self._queued = (rn, dn, None, st.k + 1)
+                elif next_images is not None:
+                    # stream order: the read-back above is taken before this
+                    # writes sc[4 - f_at], and a later trial's step writes
+                    # v_new only after this has read it
+                    B.gradient_hutchinson(g, o, rn, dn, self.v_new, next_images, self.scale, self.lam, cfg.n_probe,
+                                          cfg.probe_seed, probe0=st.k * cfg.n_probe, grad_out=self.g_next,
+                                          loss_out=self.sc[4 - self.f_at:5 - self.f_at], diag_out=self.zHz_next,
+                                          workspace=self.ws_grad)
+                    self._queued = (rn, dn, next_images, st.k + 1)
+            elif not first and self._queued is not None and self._queued[2] is not None:
+                # the first trial was rejected: the queued gradient is not at
+                # the next iterate
+                self._queued = None
             first = False
             self.sc_ready.synchronize()
-            f0, gn, vn2, l1 = self.sc_host.tolist()
+            sc = self.sc_host.tolist()
+            f0, gn, vn2, l1 = sc[self.f_at], sc[1], sc[2], sc[3]
             f1 = self.scale * l1 + 0.5 * self.lam * vn2
             if not (math.isfinite(f0) and math.isfinite(f1) and math.isfinite(gn)):
                 # v is left as it was (the trial went to v_new)
+                self._queued = None
                 raise B.CsgError("Armijo line search at iteration %d: f(v) = %r, f(v') = %r, |g|^2_D^-1 = %r "
                                  "(non-finite input or preconditioner)" % (st.k, f0, f1, gn))
             if f1 <= f0 - cfg.c * eta * gn:

@@ -82,7 +82,7 @@ def run_oracle(case, grid_o, opt_o, P, x, alpha, batches, arm, D_fixed=None):
 
 
 def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, mismatch=False, deterministic=False,
-            fused=None):
+            fused=None, queue_grad=False):
     from paper_2311_16100_amd.sgd import Alg1Config, Alg1Runner
     M = case.M
     g = b.Grid(M)
@@ -92,7 +92,11 @@ def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, misma
     df_d = torch.from_numpy(np.ascontiguousarray(P.defocus)).to(dev)
     x_d = torch.from_numpy(x).to(dev)
     # the queued probe products belong to the two-call form of the Hutchinson
-    # arm; without queueing it runs the one-kernel gradient and probe product
+    # arm; without queueing it runs the one-kernel gradient and probe
+    # product, with `queue_grad` queueing the next batch's at the first trial
+    # point
+    if queue_grad:
+        queue, fused = True, True
     cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED, deterministic=deterministic,
                      fused=(not queue) if fused is None else fused)
     kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
@@ -104,14 +108,16 @@ def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, misma
     for I in batches:
         idx = torch.from_numpy(I).to(dev)
         poses.append((rot_d[idx].contiguous(), df_d[idx].contiguous()))
+    xs = [x_d[torch.from_numpy(I).to(dev)].contiguous() for I in batches]
     out = []
     for k, I in enumerate(batches):
-        nxt = None
+        nxt, nxt_x = None, None
         if queue and k + 1 < len(batches):
             # a copy of the next poses when checking that a mismatch is ignored
             nxt = tuple(t.clone() for t in poses[k + 1]) if mismatch else poses[k + 1]
-        idx = torch.from_numpy(I).to(dev)
-        h = run.iteration(poses[k][0], poses[k][1], x_d[idx].contiguous(), next_poses=nxt)
+            if queue_grad:
+                nxt_x = xs[k + 1].clone() if mismatch else xs[k + 1]
+        h = run.iteration(poses[k][0], poses[k][1], xs[k], next_poses=nxt, next_images=nxt_x)
         out.append((h, run.state.eta, run.state.v.reshape(-1).cpu().numpy()))
     return out
 
@@ -142,6 +148,52 @@ def test_trajectory_matches_oracle(case, arm, queue, det):
     assert max(errs) <= 1e-4
     # the iterate moved: the comparison is not between two zero volumes
     assert np.linalg.norm(want[-1][2]) > 0
+
+
+def test_queued_next_gradient_matches_oracle(monkeypatch):
+    """One-call form with each next batch's gradient, loss and probe product
+    queued at the first trial point of the line search: the trajectory is the
+    oracle's.  The first iteration rejects its first trial (2 halvings in the
+    oracle at 16^3, 3 at 40^3), so its queued work is discarded and redone;
+    the later iterations accept it and use the queued results."""
+    from paper_2311_16100_amd import binding
+    calls = []
+    real = binding.gradient_hutchinson
+
+    def counted(*args, **kw):
+        calls.append(1)
+        return real(*args, **kw)
+
+    monkeypatch.setattr(binding, "gradient_hutchinson", counted)
+    for case in (SMALL, BRICKS):
+        b, grid_o, opt_o, P, x, alpha, batches = make(case)
+        want = run_oracle(case, grid_o, opt_o, P, x, alpha, batches, "hutchinson")
+        calls.clear()
+        got = run_gpu(case, b, P, x, alpha, batches, "hutchinson", queue_grad=True)
+        hw = [w[0] for w in want]
+        errs = []
+        for k, ((hw_k, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
+            assert hg == hw_k and eg == ew, (case.M, k)
+            errs.append(rel(vg, vw))
+        print("[alg1] M=%d queued next gradient: halvings %s, %d one-call launches, rel err %s"
+              % (case.M, hw, len(calls), ["%.1e" % e for e in errs]))
+        assert hw[0] > 0 and hw[1:] == [0] * (len(hw) - 1)
+        # iteration 1: its own and a discarded queued launch; iteration 2:
+        # its own and a used queued launch; later iterations queue one each
+        # except the last
+        assert len(calls) == len(batches) + 1
+        assert max(errs) <= 1e-4
+
+
+def test_queued_next_gradient_for_other_tensors_is_recomputed():
+    """Queued next-batch results named for copies of the next call's tensors
+    are not used: the trajectory equals the one without queueing."""
+    b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
+    a = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson")
+    m = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", queue_grad=True, mismatch=True)
+    for (ha, ea, va), (hm, em, vm) in zip(a, m):
+        assert ha == hm and ea == em
+        assert rel(vm, va) <= 1e-5
 
 
 def test_queued_probe_for_other_tensors_is_recomputed():
