@@ -7,16 +7,16 @@ arithmetic step (gradient, Hessian-vector probes, the running mean and
 exponential average of the diagonal, thresholding, the step, the line-search
 losses) runs in the library's kernels.  The only host work is the line
 search's decision, which needs one read-back of four device scalars per trial.
-The device keeps working while the host decides:
-  - two-call form: the Hutchinson probe product of the next batch does not
-    depend on v (the Hessian of the least-squares loss is constant), so when
-    the caller names the next batch's poses it is queued behind that
-    read-back;
-  - one-call form: when the caller names the next batch's poses and images,
-    its gradient and probe product are queued at the first trial point v'.
-    The first trial is usually accepted, and then v' is the next iterate and
-    the queued results are the next iteration's; after a rejected first
-    trial they are discarded and the next iteration forms its own.
+The device keeps working while the host decides, on the next batch's work
+queued behind that read-back when the caller names that batch:
+  - the Hutchinson probe product does not depend on v (the Hessian of the
+    least-squares loss is constant), so it needs only the next poses (the
+    one-call form forms it with the gradient and needs the images too);
+  - the gradient and loss, given the next images, are formed at the first
+    trial point v'.  The first trial is usually accepted, and then v' is the
+    next iterate and the queued gradient is the next iteration's; after a
+    rejected first trial it is discarded and the next iteration forms its
+    own.
 
 Arms (same loop, same step-size rule):
   "hutchinson"  D estimated on the fly from Rademacher probes (Algorithm 1)
@@ -87,10 +87,11 @@ class Alg1Runner:
         self.v_new = torch.empty_like(v0)
         self.zHz = torch.empty((M, M, M), dtype=torch.float32, device=dev) if arm == "hutchinson" else None
         self.zHz_next = torch.empty_like(self.zHz) if arm == "hutchinson" else None
-        # one-call form: the next batch's gradient, formed at the first trial point
-        self.g_next = torch.empty_like(v0) if self.fused else None
-        # (rot, defocus, images or None, k) of the results already in zHz_next
-        # (and g_next, sc[4 - f_at] when images are named)
+        # the next batch's gradient, formed at the first trial point
+        self.g_next = torch.empty_like(v0)
+        # (rot, defocus, images or None, k, probe) of the next batch's queued
+        # results: the gradient and f(v) in g_next and sc[4 - f_at] when images
+        # are named, the probe product in zHz_next when probe is true
         self._queued = None
         # scalars: [f_at] f(v), [1] sum |g|^2 / D_hat, [2] ||v'||^2, [3] data
         # term of f(v'), [4 - f_at] f of the queued next batch (f_at is 0 or 4)
@@ -130,27 +131,30 @@ class Alg1Runner:
 
     def iteration(self, rot_I, df_I, x_I, next_poses=None, next_images=None) -> int:
         """One iteration on the batch (rot_I, df_I, x_I).  `next_poses` =
-        (rot, defocus) of the next call's batch, if known: the Hutchinson arm
-        in its two-call form then computes that batch's probe product during
-        this line search; in its one-call form, given also `next_images`, it
-        computes that batch's gradient and probe product at the first trial
-        point.  The next call uses them when it is given the same tensors
-        (and, for the gradient, when the first trial was accepted)."""
+        (rot, defocus) of the next call's batch and `next_images` its images,
+        if known: during this line search the Hutchinson arm computes that
+        batch's probe product (needs the poses; in the one-call form also the
+        images), and every arm given the images computes that batch's
+        gradient and loss at the first trial point.  The next call uses them
+        when it is given the same tensors (and, for the gradient, when the
+        first trial was accepted)."""
         st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
         st.k += 1
-        have_grad = False
-        if self.arm == "hutchinson":
-            q = self._queued
-            if q is not None and q[0] is rot_I and q[1] is df_I and q[3] == st.k and q[2] is None:
-                self.zHz, self.zHz_next = self.zHz_next, self.zHz
-            elif q is not None and q[0] is rot_I and q[1] is df_I and q[3] == st.k and q[2] is x_I:
-                # gradient, f(v) and probe product of this batch at v, queued
-                # by the previous call at its accepted first trial point
-                self.zHz, self.zHz_next = self.zHz_next, self.zHz
-                self.g, self.g_next = self.g_next, self.g
-                self.f_at = 4 - self.f_at
-                have_grad = True
-            elif self.fused:
+        q, self._queued = self._queued, None
+        match = q is not None and q[0] is rot_I and q[1] is df_I and q[3] == st.k
+        have_probe = match and q[4]
+        have_grad = match and q[2] is x_I
+        if have_probe:
+            self.zHz, self.zHz_next = self.zHz_next, self.zHz
+        if have_grad:
+            # gradient and f(v) of this batch at v, queued by the previous
+            # call at its accepted first trial point
+            self.g, self.g_next = self.g_next, self.g
+            self.f_at = 4 - self.f_at
+        if self.arm == "hutchinson" and not have_probe:
+            if self.fused:
+                # a queued gradient of the one-call form comes with its probe product
+                assert not have_grad
                 # the gradient and z (.) H_I z for this iteration's probes
                 # (Algorithm 1: gradient and running-mean line) in one pass
                 B.gradient_hutchinson(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, cfg.n_probe,
@@ -162,7 +166,6 @@ class Alg1Runner:
                 # z (.) H_I z for this iteration's probes (Algorithm 1, running-mean line)
                 B.hutchinson_diag(g, o, rot_I, df_I, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
                                   probe0=(st.k - 1) * cfg.n_probe, diag_out=self.zHz, workspace=self.ws_hutch)
-            self._queued = None
         if not have_grad:
             B.gradient(g, o, rot_I, df_I, st.v, x_I, self.scale, self.lam, grad_out=self.g,
                        loss_out=self.sc[self.f_at:self.f_at + 1], deterministic=cfg.deterministic,
@@ -179,25 +182,14 @@ class Alg1Runner:
                       workspace=self.ws_proj)
             self.sc_host.copy_(self.sc, non_blocking=True)
             self.sc_ready.record()
-            if first and next_poses is not None and self.arm == "hutchinson":
-                rn, dn = next_poses
-                if not self.fused:
-                    B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
-                                      probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)
-                    self._queued = (rn, dn, None, st.k + 1)
-                elif next_images is not None:
-                    # stream order: the read-back above is taken before this
-                    # writes sc[4 - f_at], and a later trial's step writes
-                    # v_new only after this has read it
-                    B.gradient_hutchinson(g, o, rn, dn, self.v_new, next_images, self.scale, self.lam, cfg.n_probe,
-                                          cfg.probe_seed, probe0=st.k * cfg.n_probe, grad_out=self.g_next,
-                                          loss_out=self.sc[4 - self.f_at:5 - self.f_at], diag_out=self.zHz_next,
-                                          workspace=self.ws_grad)
-                    self._queued = (rn, dn, next_images, st.k + 1)
+            if first and next_poses is not None:
+                self._queue_next(next_poses, next_images)
             elif not first and self._queued is not None and self._queued[2] is not None:
                 # the first trial was rejected: the queued gradient is not at
-                # the next iterate
-                self._queued = None
+                # the next iterate; a queued probe product does not depend on
+                # v and is kept
+                qn = self._queued
+                self._queued = (qn[0], qn[1], None, qn[3], True) if qn[4] else None
             first = False
             self.sc_ready.synchronize()
             sc = self.sc_host.tolist()
@@ -221,3 +213,31 @@ class Alg1Runner:
         st.eta = eta
         st.halvings.append(halvings)
         return halvings
+
+    def _queue_next(self, next_poses, next_images):
+        """Enqueue the next batch's work behind the first trial's read-back:
+        the probe product (Hutchinson arm) and, given the images, the
+        gradient and loss at the trial point v_new.  Stream order: the
+        read-back is taken before this writes sc[4 - f_at], and a later
+        trial's step writes v_new only after this has read it."""
+        st, cfg, g, o = self.state, self.cfg, self.grid, self.optics
+        rn, dn = next_poses
+        probe = self.arm == "hutchinson"
+        if self.fused:
+            if next_images is None:
+                return
+            B.gradient_hutchinson(g, o, rn, dn, self.v_new, next_images, self.scale, self.lam, cfg.n_probe,
+                                  cfg.probe_seed, probe0=st.k * cfg.n_probe, grad_out=self.g_next,
+                                  loss_out=self.sc[4 - self.f_at:5 - self.f_at], diag_out=self.zHz_next,
+                                  workspace=self.ws_grad)
+        else:
+            if probe:
+                B.hutchinson_diag(g, o, rn, dn, cfg.n_probe, cfg.probe_seed, self.scale, self.lam,
+                                  probe0=st.k * cfg.n_probe, diag_out=self.zHz_next, workspace=self.ws_hutch)
+            if next_images is not None:
+                B.gradient(g, o, rn, dn, self.v_new, next_images, self.scale, self.lam, grad_out=self.g_next,
+                           loss_out=self.sc[4 - self.f_at:5 - self.f_at], deterministic=cfg.deterministic,
+                           workspace=self.ws_grad)
+            elif not probe:
+                return
+        self._queued = (rn, dn, next_images, st.k + 1, probe)

@@ -93,10 +93,10 @@ def run_gpu(case, b, P, x, alpha, batches, arm, D_fixed=None, queue=False, misma
     x_d = torch.from_numpy(x).to(dev)
     # the queued probe products belong to the two-call form of the Hutchinson
     # arm; without queueing it runs the one-kernel gradient and probe
-    # product, with `queue_grad` queueing the next batch's at the first trial
-    # point
+    # product; `queue_grad` also names the next images, so that the next
+    # batch's gradient is queued at the first trial point
     if queue_grad:
-        queue, fused = True, True
+        queue = True
     cfg = Alg1Config(beta=BETA, c=C, eta0=1.0, n_probe=N_PROBE, probe_seed=PROBE_SEED, deterministic=deterministic,
                      fused=(not queue) if fused is None else fused)
     kind = {"plain": "plain", "fixed": "fixed", "hutchinson": "hutchinson"}[arm]
@@ -150,39 +150,49 @@ def test_trajectory_matches_oracle(case, arm, queue, det):
     assert np.linalg.norm(want[-1][2]) > 0
 
 
-def test_queued_next_gradient_matches_oracle(monkeypatch):
-    """One-call form with each next batch's gradient, loss and probe product
-    queued at the first trial point of the line search: the trajectory is the
-    oracle's.  The first iteration rejects its first trial (2 halvings in the
-    oracle at 16^3, 3 at 40^3), so its queued work is discarded and redone;
-    the later iterations accept it and use the queued results."""
+@pytest.mark.parametrize("case,arm,fused,det", [
+    (SMALL, "hutchinson", True, False), (BRICKS, "hutchinson", True, False), (SMALL, "hutchinson", False, False),
+    (SMALL, "hutchinson", False, True), (SMALL, "plain", False, False), (BRICKS, "fixed", False, False)],
+    ids=["one-call", "M40-one-call", "two-call", "two-call-deterministic", "plain", "M40-fixed"])
+def test_queued_next_gradient_matches_oracle(monkeypatch, case, arm, fused, det):
+    """Each next batch's gradient and loss (with the probe product for the
+    Hutchinson arm) queued at the first trial point of the line search: the
+    trajectory is the oracle's.  An iteration whose first trial is rejected
+    (the first one in these runs) discards the queued gradient and the next
+    iteration forms its own; the other iterations use the queued one, which
+    the count of gradient launches shows."""
     from paper_2311_16100_amd import binding
     calls = []
-    real = binding.gradient_hutchinson
+    for name in ("gradient", "gradient_hutchinson"):
+        real = getattr(binding, name)
 
-    def counted(*args, **kw):
-        calls.append(1)
-        return real(*args, **kw)
+        def counted(*args, _real=real, **kw):
+            calls.append(1)
+            return _real(*args, **kw)
 
-    monkeypatch.setattr(binding, "gradient_hutchinson", counted)
-    for case in (SMALL, BRICKS):
-        b, grid_o, opt_o, P, x, alpha, batches = make(case)
-        want = run_oracle(case, grid_o, opt_o, P, x, alpha, batches, "hutchinson")
-        calls.clear()
-        got = run_gpu(case, b, P, x, alpha, batches, "hutchinson", queue_grad=True)
-        hw = [w[0] for w in want]
-        errs = []
-        for k, ((hw_k, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
-            assert hg == hw_k and eg == ew, (case.M, k)
-            errs.append(rel(vg, vw))
-        print("[alg1] M=%d queued next gradient: halvings %s, %d one-call launches, rel err %s"
-              % (case.M, hw, len(calls), ["%.1e" % e for e in errs]))
-        assert hw[0] > 0 and hw[1:] == [0] * (len(hw) - 1)
-        # iteration 1: its own and a discarded queued launch; iteration 2:
-        # its own and a used queued launch; later iterations queue one each
-        # except the last
-        assert len(calls) == len(batches) + 1
-        assert max(errs) <= 1e-4
+        monkeypatch.setattr(binding, name, counted)
+    b, grid_o, opt_o, P, x, alpha, batches = make(case)
+    D_fixed = None
+    if arm == "fixed":
+        D_fixed = np.maximum(oracle.exact_diag(grid_o, opt_o, P, 1.0, LAM).reshape(-1), alpha)
+        D_fixed = D_fixed.astype(np.float32).astype(np.float64)
+    want = run_oracle(case, grid_o, opt_o, P, x, alpha, batches, arm, D_fixed)
+    got = run_gpu(case, b, P, x, alpha, batches, arm, D_fixed, queue_grad=True, fused=fused, deterministic=det)
+    hw = [w[0] for w in want]
+    errs = []
+    for k, ((hw_k, ew, vw), (hg, eg, vg)) in enumerate(zip(want, got)):
+        assert hg == hw_k and eg == ew, (case.M, arm, k)
+        errs.append(rel(vg, vw))
+    print("[alg1] M=%d %s%s queued next gradient: halvings %s, %d gradient launches, rel err %s"
+          % (case.M, arm, " one-call" if fused else (" deterministic" if det else ""), hw, len(calls),
+             ["%.1e" % e for e in errs]))
+    assert hw[0] > 0, "the first trial of the first iteration should be rejected"
+    assert 0 in hw[:-1], "some iteration should accept its first trial"
+    # one queued launch per iteration but the last, and an own launch for
+    # the first iteration and after every rejected first trial
+    own = 1 + sum(1 for h in hw[:-1] if h > 0)
+    assert len(calls) == (len(batches) - 1) + own
+    assert max(errs) <= 1e-4
 
 
 def test_queued_next_gradient_for_other_tensors_is_recomputed():
@@ -190,10 +200,11 @@ def test_queued_next_gradient_for_other_tensors_is_recomputed():
     are not used: the trajectory equals the one without queueing."""
     b, grid_o, opt_o, P, x, alpha, batches = make(SMALL)
     a = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson")
-    m = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", queue_grad=True, mismatch=True)
-    for (ha, ea, va), (hm, em, vm) in zip(a, m):
-        assert ha == hm and ea == em
-        assert rel(vm, va) <= 1e-5
+    for fused in (True, False):
+        m = run_gpu(SMALL, b, P, x, alpha, batches, "hutchinson", queue_grad=True, mismatch=True, fused=fused)
+        for (ha, ea, va), (hm, em, vm) in zip(a, m):
+            assert ha == hm and ea == em
+            assert rel(vm, va) <= 1e-5
 
 
 def test_queued_probe_for_other_tensors_is_recomputed():
