@@ -97,7 +97,7 @@ class Alg1Runner:
         # term of f(v'), [4 - f_at] f of the queued next batch (f_at is 0 or 4)
         self.f_at = 0
         self.sc = torch.zeros(5, dtype=torch.float64, device=dev)
-        self.sc_host = torch.zeros(5, dtype=torch.float64, pin_memory=True)
+        self.sc_host = torch.zeros(5, dtype=torch.float64, pin_memory=v0.is_cuda)
         self.sc_ready = torch.cuda.Event()
         self.ws_grad = B.alloc_workspace(grid, batch, B.CSG_WS_GRADIENT_DETERMINISTIC if cfg.deterministic
                                          else B.CSG_WS_GRADIENT_HUTCHINSON if self.fused else B.CSG_WS_GRADIENT, dev)
