@@ -5,6 +5,11 @@ whole hot path: Rademacher probes and their Hessian-vector
 product, the fused minibatch gradient (forward projection, residual, loss,
 adjoint), the running-mean / exponential-average / threshold update of the
 diagonal, the preconditioned step and the Armijo line-search forward pass.
+Each step queues the next batch's gradient and probe product at its line
+search's first trial point, as a training loop that knows its next batch
+does (used by the next step when that trial is accepted); the last warm-up
+step and the last timed step queue nothing, so the timed region holds
+exactly its own steps' work.
 
 Prints one JSON line.  `value` = images per second through full iterations;
 `fwd_adj_images_per_s` = images per second of one plain forward projection
@@ -49,8 +54,8 @@ def parse():
     ap.add_argument("--cpu-images", type=int, default=192, help="images in the oracle's timed sample")
     ap.add_argument("--deterministic", action="store_true")
     ap.add_argument("--separate", action="store_true",
-                    help="Hutchinson arm in two calls (gradient, probe product queued behind the line search) "
-                         "instead of the one-kernel gradient and probe product")
+                    help="Hutchinson arm in two calls (gradient and probe product, each queued for the next "
+                         "batch behind the line search) instead of the one-kernel gradient and probe product")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-2 comparison of the SGD arms")
     return ap.parse_args()
 
